@@ -1,0 +1,240 @@
+"""Hot macro-electron physics of the hybrid-PIC step (Sec. II and App. B of
+the paper).  Oracle-only implementation: FP64, SI (positions in m, momenta
+in kg m/s, energies in J), vectorised over particles with NumPy.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import constants as K
+from . import philox as P
+
+Q_E = -K.E            # electron charge
+
+
+# --------------------------------------------------------------------------
+# kinematics
+# --------------------------------------------------------------------------
+def gamma_of(p):
+    """Lorentz factor of momenta p (n, 3)."""
+    return np.sqrt(1.0 + np.sum(p * p, axis=-1) / (K.ME * K.C) ** 2)
+
+
+def kinetic(p):
+    """Kinetic energy (gamma - 1) m c^2 written as p^2 / ((gamma + 1) m),
+    which has no cancellation at low energy."""
+    return np.sum(p * p, axis=-1) / ((gamma_of(p) + 1.0) * K.ME)
+
+
+def momentum_of_energy(eps):
+    """|p| of an electron of kinetic energy eps: p c = sqrt(eps (eps + 2 m c^2))."""
+    return np.sqrt(eps * (eps + 2.0 * K.MEC2)) / K.C
+
+
+def with_energy(p, eps):
+    """Rescale momenta p to kinetic energies eps keeping their directions."""
+    pm = np.sqrt(np.sum(p * p, axis=-1))
+    scale = np.where(pm > 0.0, momentum_of_energy(np.maximum(eps, 0.0)) / np.where(pm > 0, pm, 1.0), 0.0)
+    return p * scale[:, None]
+
+
+def a0_of(I0, wavelength):
+    """Normalised vector potential, eq. (a0): a0 = 8.5e-6 sqrt(I0 lambda^2), SI."""
+    return 8.5e-6 * math.sqrt(I0 * wavelength * wavelength)
+
+
+# --------------------------------------------------------------------------
+# Yee-staggered linear weighting (gather and deposit share it)
+# --------------------------------------------------------------------------
+def _axis(X, n, staggered):
+    """Indices, signs and weights along one axis for a position X in cell
+    units: (i0, i1, f, s0, s1) with weight 1-f on i0 and f on i1.  Node
+    quantities sit at integers, staggered ones at half-integers.  A staggered
+    index one past either end is a mirror ghost: it maps to the nearest valid
+    index with sign -1 (odd about the wall)."""
+    Xs = X - 0.5 if staggered else X
+    i0 = np.floor(Xs).astype(np.int64)
+    f = Xs - i0
+    i1 = i0 + 1
+    s0 = np.ones_like(f)
+    s1 = np.ones_like(f)
+    if staggered:
+        s0 = np.where(i0 < 0, -1.0, 1.0)
+        s1 = np.where(i1 > n - 1, -1.0, 1.0)
+        i0 = np.clip(i0, 0, n - 1)
+        i1 = np.clip(i1, 0, n - 1)
+    return i0, i1, f, s0, s1
+
+
+# staggering (x, y, z) of the six field components and of j_h
+STAG_E = ((True, False, False), (False, True, False), (False, False, True))
+STAG_B = ((False, True, True), (True, False, True), (True, True, False))
+
+
+def stencil(pos, dx, dims, stag):
+    """Per-component stencil: list over components of three axis tuples."""
+    X = pos / dx
+    return [[_axis(X[:, d], dims[d], s[d]) for d in range(3)] for s in stag]
+
+
+def _corners(st):
+    """The 8 (index, weight) corners of one component's stencil."""
+    (ix0, ix1, fx, sx0, sx1), (iy0, iy1, fy, sy0, sy1), (iz0, iz1, fz, sz0, sz1) = st
+    for ix, wx in ((ix0, sx0 * (1.0 - fx)), (ix1, sx1 * fx)):
+        for iy, wy in ((iy0, sy0 * (1.0 - fy)), (iy1, sy1 * fy)):
+            for iz, wz in ((iz0, sz0 * (1.0 - fz)), (iz1, sz1 * fz)):
+                yield (ix, iy, iz), wx * wy * wz
+
+
+def interp(F, st):
+    """Trilinear interpolation of one component array with stencil st."""
+    v = 0.0
+    for idx, wgt in _corners(st):
+        v = v + wgt * F[idx]
+    return v
+
+
+def gather(pos, E, B, dx, dims):
+    """E and B at the particle positions (n, 3) each."""
+    se = stencil(pos, dx, dims, STAG_E)
+    sb = stencil(pos, dx, dims, STAG_B)
+    Ep = np.stack([interp(E[c], se[c]) for c in range(3)], axis=-1)
+    Bp = np.stack([interp(B[c], sb[c]) for c in range(3)], axis=-1)
+    return Ep, Bp
+
+
+def deposit(j, pos, vel, w, dx, dims):
+    """j_h += q w v S(x) / dx^3 on the E positions with the gather's weights
+    (a ghost's share goes to its mirror index with the ghost's sign)."""
+    se = stencil(pos, dx, dims, STAG_E)
+    amp = Q_E * w / dx ** 3
+    for c in range(3):
+        for idx, wgt in _corners(se[c]):
+            np.add.at(j[c], idx, amp * vel[:, c] * wgt)
+
+
+# --------------------------------------------------------------------------
+# Boris push (q = -e)
+# --------------------------------------------------------------------------
+def boris(p, Ep, Bp, dt):
+    """Relativistic Boris rotation: half electric kick, magnetic rotation with
+    t = q B dt / (2 gamma m), s = 2 t / (1 + t^2), half electric kick."""
+    pm = p + 0.5 * Q_E * dt * Ep
+    g = gamma_of(pm)
+    t = (0.5 * Q_E * dt / (g * K.ME))[:, None] * Bp
+    s = 2.0 * t / (1.0 + np.sum(t * t, axis=-1))[:, None]
+    pp = pm + np.cross(pm, t)
+    pplus = pm + np.cross(pp, s)
+    return pplus + 0.5 * Q_E * dt * Ep
+
+
+# --------------------------------------------------------------------------
+# rotations about the momentum direction
+# --------------------------------------------------------------------------
+def rotate(p, dtheta, phi):
+    """Turn the directions of p by polar angle dtheta at azimuth phi, keeping
+    |p|.  Basis: a = unit(phat x e_m), with e_m the axis of the smallest
+    |phat_i| (ties -> lowest index), b = phat x a;
+    phat' = cos(dtheta) phat + sin(dtheta) (cos(phi) a + sin(phi) b)."""
+    pm = np.sqrt(np.sum(p * p, axis=-1))
+    ph = p / pm[:, None]
+    m = np.argmin(np.abs(ph), axis=-1)
+    em = np.zeros_like(ph)
+    em[np.arange(len(m)), m] = 1.0
+    a = np.cross(ph, em)
+    a /= np.sqrt(np.sum(a * a, axis=-1))[:, None]
+    b = np.cross(ph, a)
+    d = (np.cos(dtheta)[:, None] * ph
+         + np.sin(dtheta)[:, None] * (np.cos(phi)[:, None] * a + np.sin(phi)[:, None] * b))
+    d /= np.sqrt(np.sum(d * d, axis=-1))[:, None]
+    return d * pm[:, None]
+
+
+# --------------------------------------------------------------------------
+# collisions
+# --------------------------------------------------------------------------
+def stopping_ion(eps, p, Z, n_i, I_ex):
+    """Continuous ionisation stopping power eq. (stop_ion) [J/m], clamped >= 0:
+    Z n_i e^4/(4 pi eps0^2 m v^2) (ln(eps/I) + ln(gamma+1)/2 + 0.909/gamma^2
+    - 0.818/gamma - 0.246)."""
+    g = gamma_of(p)
+    v2 = np.sum(p * p, axis=-1) / (g * K.ME) ** 2
+    L = (np.log(np.maximum(eps, 1e-300) / I_ex) + 0.5 * np.log(g + 1.0)
+         + 0.909 / g ** 2 - 0.818 / g - 0.246)
+    S = Z * n_i * K.E ** 4 / (4.0 * math.pi * K.EPS0 ** 2 * K.ME * v2) * L
+    return np.maximum(S, 0.0)
+
+
+def davies_sigma2(p, Z, n_i, dt):
+    """Variance of the Davies deflection over dt (App. B):
+    Z^2 e^4 n_i gamma m/(2 pi eps0^2 p^3) ln(4 eps0 h p/(Z^1/3 m e^2)) dt,
+    logarithm clamped at zero."""
+    g = gamma_of(p)
+    pm = np.sqrt(np.sum(p * p, axis=-1))
+    lg = np.log(4.0 * K.EPS0 * K.H * pm / (Z ** (1.0 / 3.0) * K.ME * K.E ** 2))
+    return (Z * Z * K.E ** 4 * n_i * g * K.ME / (2.0 * math.pi * K.EPS0 ** 2 * pm ** 3)
+            * np.maximum(lg, 0.0) * dt)
+
+
+def box_muller(u0, u1):
+    """Standard normal deviate from two uniforms."""
+    return np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * math.pi * u1)
+
+
+def photon_polar(gamma, r):
+    """Photon polar angle about the electron direction (stand-in for the Tsai
+    sampler, which the paper cites without printing): inverse CDF of
+    dN/dOmega ~ (1 + gamma^2 theta^2)^-2, theta = sqrt(r/(1-r))/gamma, capped at pi."""
+    return np.minimum(np.sqrt(r / (1.0 - r)) / gamma, math.pi)
+
+
+# --------------------------------------------------------------------------
+# injection (App. B: exponential spectrum; Sec. II.B: Gaussian spot, cone)
+# --------------------------------------------------------------------------
+def injection_schedule(src, dt):
+    """(first step, number of steps) of a source: uniform count per step over
+    [t_start, t_end), the remainder going to the earliest steps."""
+    s0 = int(math.floor(src["t_start"] / dt + 0.5))
+    ns = max(1, int(math.floor((src["t_end"] - src["t_start"]) / dt + 0.5)))
+    return s0, ns
+
+
+def default_weight(src, I0):
+    """Real electrons per macro-electron: the injected hot-electron energy
+    I0 <f> (pi r_fwhm^2/4) tau eta_l2e (eq. N_cell summed over the spot with a
+    flat time envelope) divided by N_macro T_hot.  <f> = 1/(2 ln 2) is the
+    mean of f = 2^-(2r/r_fwhm)^2 over the disc f >= 1/2."""
+    if src["weight"] > 0.0:
+        return src["weight"]
+    f_mean = 1.0 / (2.0 * math.log(2.0))
+    tau = src["t_end"] - src["t_start"]
+    energy = I0 * f_mean * (math.pi * src["r_fwhm"] ** 2 / 4.0) * tau * src["eta_l2e"]
+    return energy / (src["n_macro"] * src["T_hot"])
+
+
+def inject(src, first_id, count, step, seed, x_lo, I0):
+    """`count` macro-electrons with ids first_id.. at step `step`.
+      radius: r^2 = -2 s^2 ln(1 - u/2), s^2 = r_fwhm^2/(8 ln 2)  (f >= 1/2 disc)
+      energy: eps = -T_hot ln(1 - u)
+      direction: cos(theta) = 1 - u (1 - cos(theta_max)), phi = 2 pi u, about +x
+      optical depth: tau = -ln(1 - u)
+    Returns pos, p, w, tau, ids."""
+    ids = (np.arange(count, dtype=np.uint64) + np.uint64(first_id)).astype(np.uint64)
+    a0, a1, a2, a3 = P.uniforms(ids, seed, step, P.SLOT_INJECT_A)
+    b0, b1, _, _ = P.uniforms(ids, seed, step, P.SLOT_INJECT_B)
+    s2 = src["r_fwhm"] ** 2 / (8.0 * math.log(2.0))
+    r = np.sqrt(-2.0 * s2 * np.log(1.0 - 0.5 * a0))
+    ps = 2.0 * math.pi * a1
+    pos = np.stack([np.full(count, x_lo), src["y0"] + r * np.cos(ps),
+                    src["z0"] + r * np.sin(ps)], axis=-1)
+    eps = -src["T_hot"] * np.log(1.0 - a2)
+    ct = 1.0 - a3 * (1.0 - math.cos(src["half_angle"]))
+    st = np.sqrt(np.maximum(1.0 - ct * ct, 0.0))
+    pc = 2.0 * math.pi * b0
+    d = np.stack([ct, st * np.cos(pc), st * np.sin(pc)], axis=-1)
+    p = d * momentum_of_energy(eps)[:, None]
+    tau = -np.log(1.0 - b1)
+    w = np.full(count, default_weight(src, I0))
+    return pos, p, w, tau, ids.astype(np.uint32)
