@@ -1,0 +1,310 @@
+/*
+ * hyb.h -- C ABI of the MI355X hybrid-PIC library.
+ *
+ * The library advances the hybrid particle-in-cell step of Morris, Robinson
+ * and Ridgers, "Highly efficient conversion of laser energy to hard X-rays in
+ * high intensity laser-solid simulations" (arXiv 2107.01723): hot
+ * macro-electrons crossing a cold resistive solid (Sec. II, App. A, App. B).
+ *
+ * Conventions of every entry point:
+ *  - Units are SI at the boundary (m, s, J, K, kg m^-3, W m^-2, T, V m^-1).
+ *  - Nothing throws across the ABI; every call returns a hyb_status.  On an
+ *    error the run keeps its previous state and hyb_last_error(run) holds a
+ *    message.  Errors of work already enqueued on the device surface at the
+ *    next synchronising call (hyb_tally, hyb_get_state) as HYB_EDEVICE.
+ *  - The library owns all device memory of a run.  It allocates through the
+ *    caller's allocator callback when one is given (hipMalloc otherwise) and
+ *    frees it in hyb_free.  All host buffers belong to the caller.
+ *  - Device work is enqueued on the caller's stream (hyb_device.stream, a
+ *    hipStream_t; NULL = the default stream) and the call returns without
+ *    waiting, except where a function says it synchronises.
+ *  - A run is not thread-safe: calls on one run must be serialised.
+ *
+ * Grid layout used by hyb_state: nx*ny*nz cubic cells of side dx; nodes
+ * (i, j, k), 0 <= i <= nx.  Every field component is an array of
+ * (nx+1)*(ny+1)*(nz+1) doubles indexed i + (nx+1)*(j + (ny+1)*k), with the
+ * Yee positions
+ *   Ex (i+1/2, j, k)   Ey (i, j+1/2, k)   Ez (i, j, k+1/2)     (j_h alike)
+ *   Bx (i, j+1/2, k+1/2)   By (i+1/2, j, k+1/2)   Bz (i+1/2, j+1/2, k)
+ * and entries past a staggered range are zero.  Cell arrays have nx*ny*nz
+ * entries indexed i + nx*(j + ny*k).  The three components of E, B or j are
+ * stored one after the other (component-major).
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HYB_OK = 0,
+  HYB_EINVAL = 1,    /* an argument or configuration value is out of range */
+  HYB_ENOMEM = 2,    /* device or host allocation failed */
+  HYB_ENOSPACE = 3,  /* the particle capacity (max_particles) would be exceeded */
+  HYB_EDEVICE = 4,   /* a HIP call failed */
+  HYB_ESTATE = 5,    /* the call does not fit the run's current state */
+  HYB_ENUMERIC = 6,  /* a non-finite value was found */
+  HYB_EBUSY = 7      /* serving engine: no slot or not enough device memory now */
+} hyb_status;
+
+enum { HYB_FP64 = 0, HYB_FP32_MIXED = 1 };
+enum { HYB_TABLE_CSBH = 0, HYB_TABLE_FLAT = 1 };
+
+/* physics toggles (hyb_config.physics); HYB_PHYS_ALL is the method */
+enum {
+  HYB_PHYS_FIELDS = 1 << 0,    /* push in the gathered E and B */
+  HYB_PHYS_ION = 1 << 1,       /* continuous ionisation loss, eq. (stop_ion) */
+  HYB_PHYS_BREM = 1 << 2,      /* bremsstrahlung, optical-depth method (App. B) */
+  HYB_PHYS_SCATTER = 1 << 3,   /* Davies elastic scatter (App. B) */
+  HYB_PHYS_EVOLVE_E = 1 << 4,  /* E from eq. (Ampere_Maxwell) each sub-cycle */
+  HYB_PHYS_EVOLVE_B = 1 << 5,  /* B from eq. (Faraday_Lens) */
+  HYB_PHYS_HEAT = 1 << 6,      /* App. A heating, exchange and resistivity */
+  HYB_PHYS_ALL = 0x7F
+};
+
+/* energy ledger terms (hyb_tally_out.ledger), J */
+enum {
+  HYB_L_INJECTED = 0,     /* kinetic energy of injected electrons */
+  HYB_L_FIELD_LOSS = 1,   /* work done by E against electrons */
+  HYB_L_FIELD_GAIN = 2,   /* work done by E on electrons */
+  HYB_L_IONISATION = 3,   /* continuous ionisation loss */
+  HYB_L_STOPPED = 4,      /* energy of electrons removed below e_min */
+  HYB_L_RAD_DISCRETE = 5, /* energy of emitted macro-photons */
+  HYB_L_RAD_SUBCUT = 6,   /* continuous radiation below k_cut */
+  HYB_L_ESCAPED = 7,      /* energy of escaping electrons */
+  HYB_L_REFLUX = 8,       /* energy lost in reflux events */
+  HYB_L_PHOTON_THR = 9,   /* photon energy at or above tally_Ethr (part of term 5) */
+  HYB_L_RESIDUAL = 10,    /* rounding residual: change of the stored kinetic energy
+                             that no process explains (elastic rotations, sub-cut
+                             loss below the precision of the particle state) */
+  HYB_LEDGER_N = 11
+};
+
+/* event counters (hyb_tally_out.counters) */
+enum {
+  HYB_C_INJECTED = 0, HYB_C_EMITTED = 1, HYB_C_REFLUX = 2, HYB_C_ESCAPED = 3,
+  HYB_C_STOPPED = 4, HYB_COUNTER_N = 5
+};
+
+/* Run configuration (copied by hyb_init).  The solid is one element filling
+ * the slab x_lo <= x < x_hi over the whole y, z extent of the grid (App. A
+ * "solid"); x_lo and x_hi must lie on cell faces.  The slab is also the
+ * particle box: electrons leaving it escape or reflux (Sec. II.A). */
+typedef struct hyb_config {
+  int32_t nx, ny, nz;       /* cells; nx < 2048, ny < 1024, nz < 2048 */
+  double dx;                /* cell side [m] */
+  double dt;                /* time step [s] */
+  int32_t precision;        /* HYB_FP64 or HYB_FP32_MIXED */
+  double Z, A, rho;         /* atomic number, molar mass [g/mol], density [kg/m^3] */
+  double I_ex;              /* mean excitation energy [J]; 0 -> 11 eV * Z (Sec. III.B) */
+  double x_lo, x_hi;        /* slab x-extent [m] */
+  double T0;                /* initial electron and ion temperature [K] */
+  double lambda1, lambda2;  /* reduced Lee-More fit parameters (App. A: 7, 3.5) */
+  double I0;                /* peak laser intensity [W/m^2] -> a0, eq. (a0) */
+  double wavelength;        /* laser wavelength [m] */
+  double kappa_esc;         /* escape above kappa_esc a0 m c^2 (Sec. II.A: 2) */
+  double kappa_tnsa;        /* reflux |p| loss kappa_tnsa a0 m c (Sec. II.A: 2.7e-3) */
+  double sigma_dtheta;      /* reflux scatter range [rad] (Sec. II.A: 23 deg) */
+  double reflux_ke_frac;    /* > 0: lose this fraction of kinetic energy per reflux
+                               instead of the momentum loss above */
+  double brem_boost;        /* cross-section multiplier B >= 1 (Sec. II.B: 10) */
+  double k_cut;             /* lowest emitted photon energy [J] */
+  int32_t table_shape;      /* HYB_TABLE_CSBH or HYB_TABLE_FLAT spectral shape */
+  int32_t table_nT, table_nr; /* rows (electron energy) and columns (variate) */
+  double table_emax;        /* top table energy [J] */
+  double e_min;             /* electrons below this kinetic energy are removed [J] */
+  int32_t tally_nE, tally_ntheta; /* photon tally bins (energy x angle to +x) */
+  double tally_Elo, tally_Ehi;    /* log-uniform energy bins [J] */
+  double tally_Ethr;        /* threshold of the conversion efficiency [J] (1 MeV) */
+  int32_t series_len;       /* steps recorded in the per-step emission series */
+  uint32_t seed;            /* run seed of the counter-based random stream */
+  int64_t max_particles;    /* particle capacity */
+  uint32_t physics;         /* HYB_PHYS_* bits */
+  double eta_fixed;         /* > 0: hold the solid's resistivity at this value */
+  int32_t n_sub;            /* field sub-cycles per step; 0 = from the stability scan */
+  int32_t sort_every;       /* cell-sort and compact particles every this many steps; 0 = never */
+} hyb_config;
+
+/* An injection source (App. B, Sec. II.B): n_macro electrons spread evenly
+ * over the steps of [t_start, t_end), placed on the slab's front face in a
+ * Gaussian spot truncated at f >= 1/2, with exponential kinetic energies of
+ * mean T_hot and directions uniform in a cone about +x. */
+typedef struct hyb_source {
+  int64_t n_macro;
+  double t_start, t_end;    /* [s] */
+  double y0, z0;            /* spot centre [m] */
+  double r_fwhm;            /* spot full width at half maximum [m] */
+  double T_hot;             /* mean kinetic energy [J] */
+  double half_angle;        /* cone half-angle [rad] */
+  double eta_l2e;           /* laser-to-electron efficiency (weight rule) */
+  double weight;            /* real electrons per macro-electron; 0 -> from I0 */
+} hyb_source;
+
+typedef void* (*hyb_alloc_fn)(size_t bytes, void* user);
+typedef void (*hyb_free_fn)(void* ptr, void* user);
+
+typedef struct hyb_device {
+  int32_t device;           /* HIP device ordinal */
+  void* stream;             /* hipStream_t for all enqueued work; NULL = default */
+  hyb_alloc_fn alloc;       /* optional device allocator (NULL -> hipMalloc) */
+  hyb_free_fn free;         /* its matching free */
+  void* user;               /* passed to alloc/free */
+} hyb_device;
+
+/* Results copied out by hyb_tally.  Pointer members are caller-owned
+ * buffers (NULL skips them); scalar members are filled in. */
+typedef struct hyb_tally_out {
+  double* hist_E;           /* [tally_nE*tally_ntheta] photon energy per bin [J],
+                               energy index major */
+  double* hist_N;           /* same bins, real photon number */
+  double* series;           /* [series_len] photon energy >= tally_Ethr per step [J] */
+  double flow[4];           /* under-range energy, number; over-range energy, number */
+  double ledger[HYB_LEDGER_N];
+  double kinetic;           /* kinetic energy of the electrons still alive [J] */
+  double conversion;        /* ledger[PHOTON_THR] / ledger[INJECTED] (eta_e->gamma) */
+  int64_t counters[HYB_COUNTER_N];
+  int64_t n_alive;          /* electrons alive */
+  int64_t step;             /* steps completed */
+} hyb_tally_out;
+
+/* Full state for checkpoint/restore and tests (host memory, SI). */
+typedef struct hyb_state {
+  int64_t n;                /* particles: set_state reads n; get_state writes n */
+  int64_t capacity;         /* get_state: length of the particle buffers */
+  double* pos;              /* [n*3] x, y, z per particle [m] */
+  double* mom;              /* [n*3] momentum [kg m/s] */
+  double* w;                /* [n] real electrons per macro-electron */
+  double* tau;              /* [n] remaining optical depth to the next emission */
+  uint32_t* id;             /* [n] particle ids (random-stream keys) */
+  double* E;                /* [3*nodes] V/m */
+  double* B;                /* [3*nodes] T */
+  double* J;                /* [3*nodes] A/m^2, get only: the last step's hot current */
+  double* Te;               /* [cells] K */
+  double* Ti;               /* [cells] K */
+  double* eta;              /* [cells] Ohm m */
+  double* ion_heat;         /* [cells] J, get only: the last step's collisional deposit */
+  int64_t step;             /* steps completed */
+  int64_t next_id;          /* next particle id (set_state: ids of later sources) */
+} hyb_state;
+
+/* Derived run quantities (for tests and reports). */
+typedef struct hyb_run_info {
+  int32_t n_sub;            /* field sub-cycles per step */
+  double a0;                /* eq. (a0) */
+  double eps_esc;           /* escape energy [J] */
+  double n_i;               /* ion density [m^-3] */
+  double c_z;               /* bremsstrahlung prefactor C_Z [m^2] */
+  double w_ref;             /* weight of the fixed-point accumulator unit */
+  int64_t nodes, cells;
+  int64_t bytes;            /* device memory held by the run */
+} hyb_run_info;
+
+typedef struct hyb_run hyb_run;
+typedef struct hyb_engine hyb_engine;
+
+/* Validate cfg, build the bremsstrahlung tables, allocate the run on
+ * dev->device and set the initial solid (T = T0, eta(T0), E = B = 0).
+ * Synchronises the stream.  HYB_EINVAL for a bad configuration, HYB_ENOMEM
+ * when the allocation fails. */
+hyb_status hyb_init(const hyb_config* cfg, const hyb_device* dev, hyb_run** out);
+
+/* Schedule an injection source; ids n..n+n_macro-1 go to its electrons in
+ * step order.  No device work.  HYB_ENOSPACE when all sources together
+ * exceed max_particles; HYB_EINVAL when the spot leaves the slab face or the
+ * window is empty; HYB_ESTATE when the run already started past t_start. */
+hyb_status hyb_inject(hyb_run* run, const hyb_source* src);
+
+/* Enqueue nsteps full hybrid-PIC steps (inject, push and collide, deposit,
+ * Ohm + Faraday sub-cycles, heating, tallies; optional cell sort). */
+hyb_status hyb_step(hyb_run* run, int32_t nsteps);
+
+/* Copy out tallies, ledger, counters and the alive kinetic energy.
+ * Synchronises the stream. */
+hyb_status hyb_tally(hyb_run* run, hyb_tally_out* out);
+
+/* Copy the whole state to host buffers (particles in internal order).
+ * HYB_ENOSPACE when st->capacity is too small (st->n holds the need).
+ * Synchronises the stream. */
+hyb_status hyb_get_state(hyb_run* run, hyb_state* st);
+
+/* Replace particles, fields, temperatures, resistivity, step and next id
+ * (NULL field/cell pointers keep the current arrays).  Clears the step's
+ * current and heat buffers.  Synchronises the stream. */
+hyb_status hyb_set_state(hyb_run* run, const hyb_state* st);
+
+hyb_status hyb_run_info_get(const hyb_run* run, hyb_run_info* info);
+
+/* Copy the FP64 master bremsstrahlung table: X [nT*nr] (inverse CDF in
+ * x = ln(k/k_cut)/ln(eps/k_cut)), SIG [nT] (sigma/C_Z), SUB [nT] (sub-cut
+ * stopping / C_Z, J).  Any pointer may be NULL. */
+hyb_status hyb_table_get(const hyb_run* run, double* X, double* SIG, double* SUB);
+
+/* Kernel timing for roofline reports: when enabled, hyb_step records HIP
+ * events around every launch of the particle kernel on the run's stream.
+ * hyb_timing_get synchronises and returns the total milliseconds and count. */
+hyb_status hyb_timing_enable(hyb_run* run, int32_t on);
+hyb_status hyb_timing_get(hyb_run* run, double* total_ms, int64_t* launches);
+
+/* Capture one step as a HIP graph and replay it in hyb_step (1) or launch
+ * kernels directly (0, default). */
+hyb_status hyb_use_graph(hyb_run* run, int32_t on);
+
+/* Device bytes hyb_init would allocate for cfg. */
+hyb_status hyb_footprint(const hyb_config* cfg, int64_t* bytes);
+
+void hyb_free(hyb_run* run);
+
+/* Message of the last failed call on this run; with run == NULL, of the last
+ * failed call of this thread (e.g. hyb_init, which returns no handle). */
+const char* hyb_last_error(const hyb_run* run);
+const char* hyb_status_string(hyb_status s);
+
+/* sizeof of the ABI structs, for bindings to check their layouts:
+ * config, source, device, tally_out, state, run_info. */
+void hyb_abi_sizes(int64_t sizes[6]);
+
+/* ---------------- serving engine (continuous batching) -------------------
+ * Independent runs share one device.  Each engine tick advances every
+ * resident unfinished run by one step with batched kernels: one launch per
+ * phase covers all resident runs, so runs admitted while others are running
+ * overlap on the device.  Each tick is captured as a HIP graph and replayed
+ * until the set of resident runs changes.  Results of a run are bitwise the
+ * same alone and in any mix (integer accumulators, per-particle random
+ * streams). */
+
+/* hbm_budget: bytes the engine may hold for runs (0 = 90 % of free memory);
+ * max_runs: resident run slots. */
+hyb_status hyb_engine_create(const hyb_device* dev, int64_t hbm_budget, int32_t max_runs,
+                             hyb_engine** out);
+
+/* Admit a run with its sources and step count.  HYB_EBUSY when no slot is
+ * free or its footprint does not fit the budget now; HYB_EINVAL for a bad
+ * configuration.  The run handle serves hyb_tally / hyb_get_state /
+ * hyb_run_info_get; it must not be passed to hyb_step or hyb_free. */
+hyb_status hyb_engine_admit(hyb_engine* eng, const hyb_config* cfg, const hyb_source* srcs,
+                            int32_t nsrc, int32_t nsteps, hyb_run** out);
+
+/* Enqueue ticks; a run that has done its steps stops advancing. */
+hyb_status hyb_engine_step(hyb_engine* eng, int32_t nticks);
+
+/* Runs that have finished all their steps and are not yet retired
+ * (synchronises the stream). */
+hyb_status hyb_engine_poll(hyb_engine* eng, hyb_run** done, int32_t cap, int32_t* ndone);
+
+/* Release a run's slot and memory; the handle becomes invalid. */
+hyb_status hyb_engine_retire(hyb_engine* eng, hyb_run* run);
+
+/* Resident runs and bytes in use. */
+hyb_status hyb_engine_stats(const hyb_engine* eng, int32_t* resident, int64_t* bytes_used,
+                            int64_t* budget);
+
+void hyb_engine_free(hyb_engine* eng);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYB_H */

@@ -73,9 +73,9 @@ STAG_E = ((True, False, False), (False, True, False), (False, False, True))
 STAG_B = ((False, True, True), (True, False, True), (True, True, False))
 
 
-def stencil(pos, dx, dims, stag):
-    """Per-component stencil: list over components of three axis tuples."""
-    X = pos / dx
+def stencil(X, dims, stag):
+    """Per-component stencil for positions X in cell units (x / dx): a list
+    over components of three axis tuples."""
     return [[_axis(X[:, d], dims[d], s[d]) for d in range(3)] for s in stag]
 
 
@@ -96,19 +96,20 @@ def interp(F, st):
     return v
 
 
-def gather(pos, E, B, dx, dims):
-    """E and B at the particle positions (n, 3) each."""
-    se = stencil(pos, dx, dims, STAG_E)
-    sb = stencil(pos, dx, dims, STAG_B)
+def gather(X, E, B, dims):
+    """E and B at particle positions X (cell units), (n, 3) each."""
+    se = stencil(X, dims, STAG_E)
+    sb = stencil(X, dims, STAG_B)
     Ep = np.stack([interp(E[c], se[c]) for c in range(3)], axis=-1)
     Bp = np.stack([interp(B[c], sb[c]) for c in range(3)], axis=-1)
     return Ep, Bp
 
 
-def deposit(j, pos, vel, w, dx, dims):
+def deposit(j, X, vel, w, dx, dims):
     """j_h += q w v S(x) / dx^3 on the E positions with the gather's weights
-    (a ghost's share goes to its mirror index with the ghost's sign)."""
-    se = stencil(pos, dx, dims, STAG_E)
+    (a ghost's share goes to its mirror index with the ghost's sign).
+    X in cell units."""
+    se = stencil(X, dims, STAG_E)
     amp = Q_E * w / dx ** 3
     for c in range(3):
         for idx, wgt in _corners(se[c]):
@@ -214,21 +215,22 @@ def default_weight(src, I0):
     return energy / (src["n_macro"] * src["T_hot"])
 
 
-def inject(src, first_id, count, step, seed, x_lo, I0):
+def inject(src, first_id, count, step, seed, ix_lo, dx, I0):
     """`count` macro-electrons with ids first_id.. at step `step`.
       radius: r^2 = -2 s^2 ln(1 - u/2), s^2 = r_fwhm^2/(8 ln 2)  (f >= 1/2 disc)
       energy: eps = -T_hot ln(1 - u)
       direction: cos(theta) = 1 - u (1 - cos(theta_max)), phi = 2 pi u, about +x
       optical depth: tau = -ln(1 - u)
-    Returns pos, p, w, tau, ids."""
+    Positions are returned in cell units (x / dx); the slab front face is the
+    integer ix_lo.  Returns X, p, w, tau, ids."""
     ids = (np.arange(count, dtype=np.uint64) + np.uint64(first_id)).astype(np.uint64)
     a0, a1, a2, a3 = P.uniforms(ids, seed, step, P.SLOT_INJECT_A)
     b0, b1, _, _ = P.uniforms(ids, seed, step, P.SLOT_INJECT_B)
     s2 = src["r_fwhm"] ** 2 / (8.0 * math.log(2.0))
     r = np.sqrt(-2.0 * s2 * np.log(1.0 - 0.5 * a0))
     ps = 2.0 * math.pi * a1
-    pos = np.stack([np.full(count, x_lo), src["y0"] + r * np.cos(ps),
-                    src["z0"] + r * np.sin(ps)], axis=-1)
+    pos = np.stack([np.full(count, float(ix_lo)), (src["y0"] + r * np.cos(ps)) / dx,
+                    (src["z0"] + r * np.sin(ps)) / dx], axis=-1)
     eps = -src["T_hot"] * np.log(1.0 - a2)
     ct = 1.0 - a3 * (1.0 - math.cos(src["half_angle"]))
     st = np.sqrt(np.maximum(1.0 - ct * ct, 0.0))

@@ -17,6 +17,8 @@ the reading both implementations follow):
  10. n_sub sub-cycles of Ohm + Faraday (App. A)
  11. Ohmic + ionisation heating, electron-ion exchange, resistivity (App. A)
 The heat of a particle goes to the cell that contains x^n.
+Positions are held in cell units X = x / dx so that the slab faces and the
+walls are exact integers.
 """
 from __future__ import annotations
 
@@ -40,7 +42,7 @@ PHYS_EVOLVE_B = 1 << 5
 PHYS_HEAT = 1 << 6
 
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
-               "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr")
+               "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr", "residual")
 COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped")
 
 
@@ -67,8 +69,8 @@ class OracleRun:
             raise ValueError("slab faces must lie on cell faces")
         if not (0 <= self.ix_lo < self.ix_hi <= self.nx):
             raise ValueError("slab outside the grid")
-        self.box_lo = np.array([self.ix_lo * self.dx, 0.0, 0.0])
-        self.box_hi = np.array([self.ix_hi * self.dx, self.ny * self.dx, self.nz * self.dx])
+        self.box_lo = np.array([float(self.ix_lo), 0.0, 0.0])          # cell units
+        self.box_hi = np.array([float(self.ix_hi), float(self.ny), float(self.nz)])
         self.n_sub = int(c["n_sub"]) if c["n_sub"] > 0 else S.n_sub_auto(
             self.dt, self.dx, self.Z, self.A, self.rho, c["T0"], c["lambda1"], c["lambda2"])
         shape = (self.nx + 1, self.ny + 1, self.nz + 1)
@@ -83,8 +85,8 @@ class OracleRun:
         self.eta = np.zeros(cs)
         self.eta[self.solid] = self._eta_of(self.Te[self.solid], self.Ti[self.solid])
         self.ion_heat = np.zeros(cs)
-        # particles (kept in id order)
-        self.pos = np.zeros((0, 3))
+        # particles (kept in id order); X in cell units
+        self.X = np.zeros((0, 3))
         self.p = np.zeros((0, 3))
         self.w = np.zeros(0)
         self.tau = np.zeros(0)
@@ -133,10 +135,10 @@ class OracleRun:
             src = dict(s)
             src["weight"] = s["_w"]
             pos, p, w, tau, ids = PT.inject(src, first, cnt, n, self.cfg["seed"],
-                                            self.box_lo[0], self.cfg["I0"])
+                                            self.ix_lo, self.dx, self.cfg["I0"])
             self.ledger["injected"] += float(np.sum(w * PT.kinetic(p)))
             self.counters["n_injected"] += cnt
-            self.pos = np.concatenate([self.pos, pos])
+            self.X = np.concatenate([self.X, pos])
             self.p = np.concatenate([self.p, p])
             self.w = np.concatenate([self.w, w])
             self.tau = np.concatenate([self.tau, tau])
@@ -175,7 +177,7 @@ class OracleRun:
         self._inject(n)
 
         idx = np.nonzero(self.alive)[0]
-        pos = self.pos[idx].copy()
+        pos = self.X[idx].copy()
         p = self.p[idx].copy()
         w = self.w[idx]
         tau = self.tau[idx].copy()
@@ -185,7 +187,7 @@ class OracleRun:
         # push
         eps0 = PT.kinetic(p)
         if phys & PHYS_FIELDS:
-            Ep, Bp = PT.gather(pos, self.E, self.B, dx, self.dims)
+            Ep, Bp = PT.gather(pos, self.E, self.B, self.dims)
         else:
             Ep = np.zeros((m, 3))
             Bp = np.zeros((m, 3))
@@ -200,12 +202,12 @@ class OracleRun:
         # deposit (x^n, pushed velocity)
         self.j = tuple(np.zeros_like(a) for a in self.E)
         PT.deposit(self.j, pos, vel, w, dx, self.dims)
-        cell = tuple(np.clip(np.floor(pos[:, d] / dx).astype(np.int64), 0, self.dims[d] - 1)
+        cell = tuple(np.clip(np.floor(pos[:, d]).astype(np.int64), 0, self.dims[d] - 1)
                      for d in range(3))
         self.ion_heat = np.zeros_like(self.Te)
 
         # move
-        pos = pos + vel * dt
+        pos = pos + vel * (dt / dx)
 
         # ionisation
         if phys & PHYS_ION:
@@ -231,7 +233,8 @@ class OracleRun:
             if np.any(emit):
                 kph[emit] = self.table.sample_k(eps2[emit], u_c[3][emit])
             p_pre = p.copy()
-            p = PT.with_energy(p, np.maximum(eps2 - kph / B_ - sub, 0.0))
+            sub_a = np.minimum(sub, eps2 - kph / B_)      # sub-cut loss actually applied
+            p = PT.with_energy(p, eps2 - kph / B_ - sub_a)
             u_p = P.uniforms(ids, c["seed"], n, P.SLOT_PHOTON)
             tau = np.where(emit, -np.log(1.0 - u_p[2]), tau)
             if np.any(emit):
@@ -244,12 +247,12 @@ class OracleRun:
             else:
                 self.last_photons = dict(ids=ids[:0], k=kph[:0], w=w[:0], dir=np.zeros((0, 3)))
             self.counters["n_emitted"] += int(np.sum(emit))
-            B_eff = B_
+            eps3 = PT.kinetic(p)
+            L["rad_discrete"] += float(np.sum(w * kph / B_))
+            L["rad_subcut"] += float(np.sum(w * sub_a))
+            L["residual"] += float(np.sum(w * ((eps2 - eps3) - kph / B_ - sub_a)))
         else:
-            B_eff = 1.0
-        eps3 = PT.kinetic(p)
-        L["rad_discrete"] += float(np.sum(w * kph / B_eff))
-        L["rad_subcut"] += float(np.sum(w * ((eps2 - eps3) - kph / B_eff)))
+            eps3 = eps2
 
         # Davies elastic scatter
         if phys & PHYS_SCATTER:
@@ -259,6 +262,10 @@ class OracleRun:
                 s2 = PT.davies_sigma2(p[moving], self.Z, self.n_i, dt)
                 dth = PT.box_muller(u_c[0][moving], u_c[1][moving]) * np.sqrt(s2)
                 p[moving] = PT.rotate(p[moving], dth, 2.0 * math.pi * u_c[2][moving])
+                # elastic: a change of the kinetic energy is rounding, booked apart
+                e_r = PT.kinetic(p)
+                L["residual"] += float(np.sum(w * (eps3 - e_r)))
+                eps3 = e_r
         eps_cur = eps3.copy()
 
         # boundaries
@@ -308,6 +315,9 @@ class OracleRun:
             if np.any(rot):
                 p[rot] = PT.rotate(p[rot], (u_r[0][rot] - 0.5) * sig,
                                    2.0 * math.pi * u_r[1][rot])
+                e_r = PT.kinetic(p[rot])
+                L["residual"] += float(np.sum(w[rot] * (eps_cur[rot] - e_r)))
+                eps_cur[rot] = e_r
             p[live & below, d] = np.abs(p[live & below, d])
             p[live & above, d] = -np.abs(p[live & above, d])
 
@@ -318,7 +328,7 @@ class OracleRun:
         np.add.at(self.ion_heat, tuple(ci[stop] for ci in cell), w[stop] * eps_cur[stop])
         alive &= ~stop
 
-        self.pos[idx] = pos
+        self.X[idx] = pos
         self.p[idx] = p
         self.tau[idx] = tau
         self.alive[idx] = alive
@@ -354,17 +364,23 @@ class OracleRun:
         """|injected - (kinetic + losses - gains)| / injected."""
         L = self.ledger
         out = (self.kinetic_total() + L["field_loss"] - L["field_gain"] + L["ionisation"]
-               + L["stopped"] + L["rad_discrete"] + L["rad_subcut"] + L["escaped"] + L["reflux"])
+               + L["stopped"] + L["rad_discrete"] + L["rad_subcut"] + L["escaped"] + L["reflux"]
+               + L["residual"])
         return abs(L["injected"] - out) / max(L["injected"], 1e-300)
 
     def conversion_efficiency(self):
         """Photon energy above the threshold over injected kinetic energy (eta_e->gamma)."""
         return self.ledger["photon_thr"] / max(self.ledger["injected"], 1e-300)
 
+    @property
+    def pos(self):
+        """Positions in metres."""
+        return self.X * self.dx
+
     def state(self):
-        """Alive particles (in id order), fields, temperatures."""
+        """Alive particles (in id order, positions in metres), fields, temperatures."""
         a = self.alive
-        return dict(pos=self.pos[a].copy(), p=self.p[a].copy(), w=self.w[a].copy(),
+        return dict(pos=self.X[a] * self.dx, p=self.p[a].copy(), w=self.w[a].copy(),
                     tau=self.tau[a].copy(), ids=self.ids[a].copy(),
                     E=tuple(x.copy() for x in self.E), B=tuple(x.copy() for x in self.B),
                     j=tuple(x.copy() for x in self.j),
@@ -373,14 +389,14 @@ class OracleRun:
                     next_id=self.next_id)
 
     def set_state(self, st):
-        self.pos = np.array(st["pos"], dtype=np.float64).reshape(-1, 3)
+        self.X = np.array(st["pos"], dtype=np.float64).reshape(-1, 3) / self.dx
         self.p = np.array(st["p"], dtype=np.float64).reshape(-1, 3)
         self.w = np.array(st["w"], dtype=np.float64)
         self.tau = np.array(st["tau"], dtype=np.float64)
         self.ids = np.array(st["ids"], dtype=np.uint32)
         order = np.argsort(self.ids, kind="stable")
-        self.pos, self.p, self.w, self.tau, self.ids = (a[order] for a in
-                                                         (self.pos, self.p, self.w, self.tau, self.ids))
+        self.X, self.p, self.w, self.tau, self.ids = (a[order] for a in
+                                                       (self.X, self.p, self.w, self.tau, self.ids))
         self.alive = np.ones(len(self.ids), dtype=bool)
         for key in ("E", "B"):
             if key in st and st[key] is not None:

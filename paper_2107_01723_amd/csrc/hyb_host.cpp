@@ -1,0 +1,1098 @@
+// Host runtime of the MI355X hybrid-PIC library: the C ABI of include/hyb.h.
+//
+// A run owns one device allocation carved into fields, cell arrays,
+// double-buffered structure-of-arrays particles, tables and accumulators,
+// plus a device-resident run descriptor.  Steps are enqueued on the
+// caller's stream as batched kernels (a batch of one here, many in the
+// serving engine), optionally captured once as a HIP graph.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hyb.h"
+#include "hyb_internal.h"
+#include "hyb_kernels.h"
+#include "hyb_solid.h"
+#include "hyb_tables.h"
+
+using namespace hyb;
+
+namespace {
+
+constexpr int kRedBlocks = 1024;   // partial-sum slots of the kinetic reduction
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Sizes of everything a run keeps in device memory.
+struct Layout {
+  size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta, off_heat;
+  size_t off_part[2][10];
+  size_t off_tabX, off_tabSIG, off_tabSUB;
+  size_t off_acc_led, off_acc_hist, off_events, off_tot_led, off_tot_led_c, off_tot_hist, off_tot_hist_c;
+  size_t off_series, off_ctr, off_src, off_sort_cnt, off_sort_blk, off_red, off_desc;
+  size_t total;
+};
+
+Layout make_layout(const hyb_config& c) {
+  Layout L{};
+  const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
+  const size_t nodes = (size_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+  const size_t cells = (size_t)c.nx * c.ny * c.nz;
+  const size_t cap = (size_t)c.max_particles;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  for (int d = 0; d < 3; ++d) L.off_E[d] = take(nodes * ts);
+  for (int d = 0; d < 3; ++d) L.off_B[d] = take(nodes * ts);
+  for (int d = 0; d < 3; ++d) L.off_J[d] = take(nodes * 8);
+  L.off_Te = take(cells * 8);
+  L.off_Ti = take(cells * 8);
+  L.off_eta = take(cells * 8);
+  L.off_heat = take(cells * 8);
+  for (int b = 0; b < 2; ++b) {
+    L.off_part[b][0] = take(cap * 4);                       // cell
+    for (int f = 1; f < 9; ++f) L.off_part[b][f] = take(cap * ts);
+    L.off_part[b][9] = take(cap * 4);                       // id
+  }
+  const size_t tabn = (size_t)c.table_nT * c.table_nr;
+  L.off_tabX = take(tabn * ts);
+  L.off_tabSIG = take((size_t)c.table_nT * ts);
+  L.off_tabSUB = take((size_t)c.table_nT * ts);
+  const size_t nh = 2 * (size_t)c.tally_nE * c.tally_ntheta + 4;
+  L.off_acc_led = take(16 * 8);
+  L.off_acc_hist = take(nh * 8);
+  L.off_events = take(16 * 8);
+  L.off_tot_led = take(16 * 8);
+  L.off_tot_led_c = take(16 * 8);
+  L.off_tot_hist = take(nh * 8);
+  L.off_tot_hist_c = take(nh * 8);
+  L.off_series = take((size_t)std::max(1, c.series_len) * 8);
+  L.off_ctr = take(sizeof(Counters));
+  L.off_src = take(sizeof(SourceDesc) * kMaxSources);
+  L.off_sort_cnt = take((cells + 1) * 4);
+  L.off_sort_blk = take(65536 * 4);
+  L.off_red = take(2 * kRedBlocks * 8);
+  L.off_desc = take(sizeof(RunDesc));
+  L.total = o;
+  return L;
+}
+
+double cz_of(double Z) {
+  const double alpha = kE * kE / (4.0 * kPi * kEps0 * kHbar * kC);
+  const double re = kE * kE / (4.0 * kPi * kEps0 * kMec2);
+  return 16.0 / 3.0 * alpha * re * re * Z * Z * log(1.4 / alpha * pow(Z, -1.0 / 3.0));
+}
+
+int clampi(long long v, int lo, int hi) { return (int)std::max<long long>(lo, std::min<long long>(hi, v)); }
+
+}  // namespace
+
+struct hyb_engine;
+
+struct hyb_run {
+  hyb_config cfg{};
+  hyb_device dev{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hyb_engine* eng = nullptr;
+  int slot = -1;
+  void* base = nullptr;
+  size_t bytes = 0;
+  Layout lay{};
+  RunDesc h{};
+  RunDesc* d_desc = nullptr;
+  std::vector<SourceDesc> srcs;
+  std::vector<double> tabX, tabSIG, tabSUB;
+  // single-run launch plans
+  LaunchSet L;
+  BlockMap* d_maps = nullptr;
+  size_t maps_bytes = 0;
+  int64_t next_id = 0, scheduled = 0;
+  double w_ref = 0.0;
+  bool w_locked = false;
+  int64_t host_step = 0;
+  int32_t nsteps_engine = 0;
+  std::string err;
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  double t_ms = 0.0;
+  int64_t t_n = 0;
+  int64_t solid_cells = 0;
+};
+
+static thread_local std::string g_err;   // last error of a call that has no run handle
+
+static hyb_status fail(hyb_run* r, hyb_status s, const std::string& msg) {
+  if (r) r->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(r, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((r), HYB_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// configuration
+// ---------------------------------------------------------------------------
+static std::string validate(const hyb_config& c) {
+  if (c.nx < 2 || c.ny < 2 || c.nz < 2) return "nx, ny, nz must be >= 2";
+  if (c.nx >= 2048 || c.ny >= 1024 || c.nz >= 2048) return "grid too large for the packed cell index";
+  const double nodes = (double)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+  if (nodes >= 2147483647.0) return "grid has too many nodes";
+  if (!(c.dx > 0) || !(c.dt > 0)) return "dx and dt must be positive";
+  if (c.precision != HYB_FP64 && c.precision != HYB_FP32_MIXED) return "precision must be HYB_FP64 or HYB_FP32_MIXED";
+  if (!(c.Z >= 1) || !(c.A > 0) || !(c.rho > 0)) return "bad solid (Z, A, rho)";
+  const double lo = c.x_lo / c.dx, hi = c.x_hi / c.dx;
+  if (fabs(lo - llround(lo)) > 1e-6 || fabs(hi - llround(hi)) > 1e-6) return "slab faces must lie on cell faces";
+  if (llround(lo) < 0 || llround(hi) > c.nx || llround(lo) >= llround(hi)) return "slab outside the grid";
+  if (!(c.T0 > 0)) return "T0 must be positive";
+  if (!(c.lambda1 > 0) || !(c.lambda2 > 0)) return "lambda1, lambda2 must be positive";
+  if (!(c.I0 > 0) || !(c.wavelength > 0)) return "I0 and wavelength must be positive";
+  if (!(c.kappa_esc > 0) || c.kappa_tnsa < 0 || c.sigma_dtheta < 0) return "bad reflux parameters";
+  if (c.reflux_ke_frac < 0 || c.reflux_ke_frac >= 1) return "reflux_ke_frac must be in [0, 1)";
+  if (!(c.brem_boost >= 1)) return "brem_boost must be >= 1";
+  if (!(c.k_cut > 0) || !(c.table_emax > c.k_cut)) return "need 0 < k_cut < table_emax";
+  if (c.table_shape != HYB_TABLE_CSBH && c.table_shape != HYB_TABLE_FLAT) return "unknown table shape";
+  if (c.table_nT < 2 || c.table_nr < 2 || (double)c.table_nT * c.table_nr > 1e7) return "bad table size";
+  if (!(c.e_min > c.k_cut)) return "e_min must exceed k_cut";
+  if (c.tally_nE < 1 || c.tally_ntheta < 1 || !(c.tally_Ehi > c.tally_Elo) || !(c.tally_Elo > 0)) return "bad tally bins";
+  if (c.series_len < 0) return "series_len must be >= 0";
+  if (c.max_particles < 1 || c.max_particles > 2000000000LL) return "max_particles out of range";
+  if ((c.physics & ~0x7Fu) != 0) return "unknown physics bits";
+  if (c.eta_fixed < 0) return "eta_fixed must be >= 0";
+  if (c.n_sub < 0 || c.n_sub > 1000) return "n_sub out of range";
+  if (c.sort_every < 0) return "sort_every must be >= 0";
+  return "";
+}
+
+static int n_sub_auto(const hyb_config& c, double n_i) {
+  double eta_max = 0.0;
+  const double a = log10(c.T0), b = 9.0;
+  for (int i = 0; i < 400; ++i) {
+    const double T = i == 399 ? 1e9 : pow(10.0, a + i * (b - a) / 399.0);
+    eta_max = fmax(eta_max, resistivity(T, T, c.Z, c.A, c.rho, n_i, c.lambda1, c.lambda2));
+  }
+  const double dt_max = 0.9 * kMu0 * c.dx * c.dx / (6.0 * eta_max);
+  return std::max(1, (int)ceil(c.dt / dt_max));
+}
+
+static void set_units(RunDesc& h, double w_ref) {
+  h.w_ref = w_ref;
+  h.j_unit = kE * w_ref * kC / (h.dx * h.dx * h.dx) / kJScale;
+  h.heat_unit = w_ref * kMec2 / kHeatScale;
+  h.led_unit = w_ref * kMec2 / kLedScale;
+  h.cnt_unit = w_ref / kLedScale;
+}
+
+static void fill_desc(hyb_run* r) {
+  const hyb_config& c = r->cfg;
+  RunDesc& h = r->h;
+  h.nx = c.nx; h.ny = c.ny; h.nz = c.nz;
+  h.ix_lo = (int)llround(c.x_lo / c.dx);
+  h.ix_hi = (int)llround(c.x_hi / c.dx);
+  h.precision = c.precision;
+  h.physics = c.physics;
+  h.seed = c.seed;
+  h.nodes = (long long)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+  h.cells = (long long)c.nx * c.ny * c.nz;
+  h.capacity = c.max_particles;
+  h.dx = c.dx; h.dt = c.dt;
+  const double n_i = c.rho / (c.A * kAmu);
+  const double I_ex = c.I_ex > 0 ? c.I_ex : 11.0 * kE * c.Z;
+  const double a0 = 8.5e-6 * sqrt(c.I0 * c.wavelength * c.wavelength);
+  const double cz = cz_of(c.Z);
+  h.n_sub = c.n_sub > 0 ? c.n_sub : n_sub_auto(c, n_i);
+  h.e_kick = -kE * c.dt / (2.0 * kMe * kC);
+  h.b_rot = -kE * c.dt / (2.0 * kMe);
+  h.cdt_dx = kC * c.dt / c.dx;
+  const double e4 = kE * kE * kE * kE;
+  h.c_ion = c.Z * n_i * e4 * c.dt / (4.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
+  h.ln_iex = log(I_ex / kMec2);
+  h.k_brem = c.brem_boost * n_i * cz * kC * c.dt;
+  h.k_sub = n_i * cz * kC * c.dt;
+  h.inv_boost = 1.0 / c.brem_boost;
+  h.c_dav = c.Z * c.Z * e4 * n_i * c.dt / (2.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
+  h.l_dav = 4.0 * kEps0 * kH * kC / (pow(c.Z, 1.0 / 3.0) * kE * kE);
+  h.eps_esc = c.kappa_esc * a0;
+  h.du_tnsa = c.kappa_tnsa * a0;
+  h.reflux_ke_mode = c.reflux_ke_frac > 0 ? 1 : 0;
+  h.keep_frac = 1.0 - c.reflux_ke_frac;
+  h.sigma_dth = c.sigma_dtheta;
+  h.e_min = c.e_min / kMec2;
+  h.tab_nT = c.table_nT;
+  h.tab_nr = c.table_nr;
+  h.tab_kcut = c.k_cut / kMec2;
+  h.tab_ln_kcut = log(c.k_cut / kMec2);
+  h.tab_s_scale = (c.table_nT - 1) / log(c.table_emax / c.k_cut);
+  h.nE = c.tally_nE;
+  h.nth = c.tally_ntheta;
+  h.series_len = c.series_len;
+  h.ln_Elo = log(c.tally_Elo / kMec2);
+  h.e_bin_scale = c.tally_nE / log(c.tally_Ehi / c.tally_Elo);
+  h.Ethr = c.tally_Ethr / kMec2;
+  h.Z = c.Z; h.A = c.A; h.rho = c.rho; h.n_i = n_i; h.m_i = c.A * kAmu;
+  h.lambda1 = c.lambda1; h.lambda2 = c.lambda2; h.eta_fixed = c.eta_fixed;
+  h.sort_every = c.sort_every;
+  set_units(h, r->w_ref > 0 ? r->w_ref : 1.0);
+  r->solid_cells = (int64_t)(h.ix_hi - h.ix_lo) * c.ny * c.nz;
+}
+
+static void point_desc(hyb_run* r) {
+  char* b = (char*)r->base;
+  const Layout& L = r->lay;
+  RunDesc& h = r->h;
+  for (int d = 0; d < 3; ++d) {
+    h.E[d] = b + L.off_E[d];
+    h.B[d] = b + L.off_B[d];
+    h.J[d] = (long long*)(b + L.off_J[d]);
+  }
+  h.Te = (double*)(b + L.off_Te);
+  h.Ti = (double*)(b + L.off_Ti);
+  h.eta = (double*)(b + L.off_eta);
+  h.ion_heat = (long long*)(b + L.off_heat);
+  for (int k = 0; k < 2; ++k) {
+    PartPtrs& p = h.p[k];
+    p.cell = (uint32_t*)(b + L.off_part[k][0]);
+    p.ox = b + L.off_part[k][1]; p.oy = b + L.off_part[k][2]; p.oz = b + L.off_part[k][3];
+    p.ux = b + L.off_part[k][4]; p.uy = b + L.off_part[k][5]; p.uz = b + L.off_part[k][6];
+    p.wn = b + L.off_part[k][7]; p.tau = b + L.off_part[k][8];
+    p.id = (uint32_t*)(b + L.off_part[k][9]);
+  }
+  h.tab_X = b + L.off_tabX;
+  h.tab_SIG = b + L.off_tabSIG;
+  h.tab_SUB = b + L.off_tabSUB;
+  h.acc_led = (long long*)(b + L.off_acc_led);
+  h.acc_hist = (long long*)(b + L.off_acc_hist);
+  h.events = (long long*)(b + L.off_events);
+  h.tot_led = (double*)(b + L.off_tot_led);
+  h.tot_led_c = (double*)(b + L.off_tot_led_c);
+  h.tot_hist = (double*)(b + L.off_tot_hist);
+  h.tot_hist_c = (double*)(b + L.off_tot_hist_c);
+  h.series = (double*)(b + L.off_series);
+  h.ctr = (Counters*)(b + L.off_ctr);
+  h.src = (const SourceDesc*)(b + L.off_src);
+  h.sort_cnt = (unsigned*)(b + L.off_sort_cnt);
+  h.sort_blk = (unsigned*)(b + L.off_sort_blk);
+  h.red = (double*)(b + L.off_red);
+}
+
+static hyb_status upload_desc(hyb_run* r) {
+  HIPCHK(r, hipMemcpyAsync(r->d_desc, &r->h, sizeof(RunDesc), hipMemcpyHostToDevice, r->stream));
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  return HYB_OK;
+}
+
+static void* dev_alloc(const hyb_device& d, size_t bytes) {
+  if (d.alloc) return d.alloc(bytes, d.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+static void dev_free(const hyb_device& d, void* p) {
+  if (!p) return;
+  if (d.free) d.free(p, d.user);
+  else (void)hipFree(p);
+}
+
+// Launch plans of a batch.  Particle plans get a multiple of 8 blocks per run
+// so the XCD split inside the particle kernel stays aligned.
+struct PlanSpec { std::vector<BlockMap> zero, inject, particle, grid, cells, fin, adv; };
+
+static void add_run_plans(PlanSpec& ps, int run, const RunDesc& h) {
+  auto add = [&](std::vector<BlockMap>& v, int nb) {
+    for (int b = 0; b < nb; ++b) v.push_back(BlockMap{run, b, nb, 0});
+  };
+  const long long cap = h.capacity;
+  add(ps.zero, clampi((3 * h.nodes + h.cells + 1023) / 1024, 1, 4096));
+  add(ps.inject, clampi((cap / 16 + 255) / 256, 1, 512));
+  // the particle plan must start on a multiple of 8 blocks
+  while (ps.particle.size() % 8) ps.particle.push_back(BlockMap{run, 0, 0, -1});
+  int npb = clampi((cap + 255) / 256, 8, 4096);
+  npb = (npb + 7) / 8 * 8;
+  add(ps.particle, npb);
+  add(ps.grid, clampi((h.nodes + 511) / 512, 1, 4096));
+  const long long sc = (long long)(h.ix_hi - h.ix_lo) * h.ny * h.nz;
+  add(ps.cells, clampi((sc + 255) / 256, 1, 4096));
+  add(ps.fin, clampi((2LL * h.nE * h.nth + 4 + 255) / 256, 1, 256));
+  add(ps.adv, 1);
+}
+
+static hyb_status upload_plans(hyb_run* owner, hipStream_t s, const PlanSpec& ps, LaunchSet& L,
+                               BlockMap** d_maps, size_t* maps_bytes, const hyb_device& dev) {
+  std::vector<BlockMap> all;
+  std::vector<std::pair<Plan*, const std::vector<BlockMap>*>> parts = {
+      {&L.zero, &ps.zero}, {&L.inject, &ps.inject}, {&L.particle, &ps.particle}, {&L.grid, &ps.grid},
+      {&L.cells, &ps.cells}, {&L.fin, &ps.fin}, {&L.adv, &ps.adv}};
+  std::vector<size_t> offs;
+  for (auto& p : parts) {
+    offs.push_back(all.size());
+    all.insert(all.end(), p.second->begin(), p.second->end());
+  }
+  const size_t need = all.size() * sizeof(BlockMap);
+  if (need > *maps_bytes) {
+    if (*d_maps) dev_free(dev, *d_maps);
+    *d_maps = (BlockMap*)dev_alloc(dev, need);
+    if (!*d_maps) { *maps_bytes = 0; return fail(owner, HYB_ENOMEM, "block map allocation failed"); }
+    *maps_bytes = need;
+  }
+  HIPCHK(owner, hipMemcpyAsync(*d_maps, all.data(), need, hipMemcpyHostToDevice, s));
+  HIPCHK(owner, hipStreamSynchronize(s));
+  for (size_t k = 0; k < parts.size(); ++k) {
+    parts[k].first->map = *d_maps + offs[k];
+    parts[k].first->nb = (int)parts[k].second->size();
+  }
+  return HYB_OK;
+}
+
+// Allocate and initialise a run's device state (no plans).
+static hyb_status create_run(const hyb_config* cfg, const hyb_device* dev, hyb_run** out) {
+  if (!cfg || !dev || !out) return HYB_EINVAL;
+  *out = nullptr;
+  const std::string v = validate(*cfg);
+  hyb_run* r = new hyb_run();
+  r->cfg = *cfg;
+  r->dev = *dev;
+  r->stream = (hipStream_t)dev->stream;
+  if (!v.empty()) {
+    hyb_status st = fail(r, HYB_EINVAL, v);
+    *out = r;
+    return st;
+  }
+  hipError_t e = hipSetDevice(dev->device);
+  if (e != hipSuccess) { *out = r; return fail(r, HYB_EDEVICE, hipGetErrorString(e)); }
+  r->lay = make_layout(*cfg);
+  r->bytes = r->lay.total;
+  r->base = dev_alloc(r->dev, r->bytes);
+  if (!r->base) { *out = r; return fail(r, HYB_ENOMEM, "device allocation failed"); }
+  fill_desc(r);
+  point_desc(r);
+  r->d_desc = (RunDesc*)((char*)r->base + r->lay.off_desc);
+  // tables
+  build_brem_table(cfg->k_cut, cfg->table_emax, cfg->table_nT, cfg->table_nr, cfg->table_shape, r->tabX,
+                   r->tabSIG, r->tabSUB);
+  const hyb_config& c = *cfg;
+  const size_t ncells = (size_t)r->h.cells, nodes = (size_t)r->h.nodes;
+  *out = r;
+  // zero everything, then fill tables and the initial solid
+  HIPCHK(r, hipMemsetAsync(r->base, 0, r->bytes, r->stream));
+  std::vector<double> subm(r->tabSUB.size());
+  for (size_t j = 0; j < subm.size(); ++j) subm[j] = r->tabSUB[j] / kMec2;
+  auto put_typed = [&](void* dst, const std::vector<double>& v) -> hipError_t {
+    if (c.precision == HYB_FP64) return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    std::vector<float> f(v.begin(), v.end());
+    return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+  };
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  HIPCHK(r, put_typed((void*)r->h.tab_X, r->tabX));
+  HIPCHK(r, put_typed((void*)r->h.tab_SIG, r->tabSIG));
+  HIPCHK(r, put_typed((void*)r->h.tab_SUB, subm));
+  {
+    std::vector<double> T(ncells, c.T0), eta(ncells, 0.0);
+    const double e0 = c.eta_fixed > 0 ? c.eta_fixed
+                                      : resistivity(c.T0, c.T0, c.Z, c.A, c.rho, r->h.n_i, c.lambda1, c.lambda2);
+    for (int k = 0; k < c.nz; ++k)
+      for (int j = 0; j < c.ny; ++j)
+        for (int i = r->h.ix_lo; i < r->h.ix_hi; ++i) eta[i + (size_t)c.nx * (j + (size_t)c.ny * k)] = e0;
+    HIPCHK(r, hipMemcpy(r->h.Te, T.data(), ncells * 8, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(r->h.Ti, T.data(), ncells * 8, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(r->h.eta, eta.data(), ncells * 8, hipMemcpyHostToDevice));
+  }
+  (void)nodes;
+  Counters ctr{};
+  ctr.active = 1;
+  HIPCHK(r, hipMemcpy(r->h.ctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice));
+  return HYB_OK;
+}
+
+static void destroy_run(hyb_run* r) {
+  if (!r) return;
+  (void)hipStreamSynchronize(r->stream);
+  if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+  if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
+  for (auto& p : r->ev_pool) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  if (r->d_maps) dev_free(r->dev, r->d_maps);
+  if (r->base) dev_free(r->dev, r->base);
+  delete r;
+}
+
+// ---------------------------------------------------------------------------
+// sources
+// ---------------------------------------------------------------------------
+static hyb_status add_source(hyb_run* r, const hyb_source* s) {
+  const hyb_config& c = r->cfg;
+  if (!s) return fail(r, HYB_EINVAL, "null source");
+  if ((int)r->srcs.size() >= kMaxSources) return fail(r, HYB_EINVAL, "too many sources");
+  if (s->n_macro < 1) return fail(r, HYB_EINVAL, "n_macro must be >= 1");
+  if (!(s->t_end > s->t_start) || s->t_start < 0) return fail(r, HYB_EINVAL, "empty injection window");
+  if (!(s->T_hot > 0) || !(s->r_fwhm > 0) || !(s->half_angle >= 0) || s->half_angle > kPi)
+    return fail(r, HYB_EINVAL, "bad source parameters");
+  const double Ly = c.ny * c.dx, Lz = c.nz * c.dx, rr = 0.5 * s->r_fwhm;
+  if (s->y0 - rr < 0 || s->y0 + rr >= Ly || s->z0 - rr < 0 || s->z0 + rr >= Lz)
+    return fail(r, HYB_EINVAL, "spot leaves the slab face");
+  if (r->scheduled + s->n_macro > c.max_particles) return fail(r, HYB_ENOSPACE, "sources exceed max_particles");
+  const long long s0 = (long long)floor(s->t_start / c.dt + 0.5);
+  const long long ns = std::max(1LL, (long long)floor((s->t_end - s->t_start) / c.dt + 0.5));
+  if (s0 < r->host_step) return fail(r, HYB_ESTATE, "source starts before the current step");
+  double w = s->weight;
+  if (!(w > 0)) {
+    if (!(s->eta_l2e > 0)) return fail(r, HYB_EINVAL, "eta_l2e must be positive");
+    const double f_mean = 1.0 / (2.0 * log(2.0));
+    const double energy = c.I0 * f_mean * (kPi * s->r_fwhm * s->r_fwhm / 4.0) * (s->t_end - s->t_start) * s->eta_l2e;
+    w = energy / ((double)s->n_macro * s->T_hot);
+  }
+  if (!r->w_locked && r->host_step == 0) {
+    r->w_ref = std::max(r->w_ref, w);
+  }
+  const double wref = r->w_ref > 0 ? r->w_ref : w;
+  if (w / wref > 64.0) return fail(r, HYB_EINVAL, "source weight too large for the accumulator scale");
+  SourceDesc d{};
+  d.s0 = s0;
+  d.ns = ns;
+  d.base = s->n_macro / ns;
+  d.rem = s->n_macro % ns;
+  d.id0 = r->next_id;
+  d.y0 = s->y0 / c.dx;
+  d.z0 = s->z0 / c.dx;
+  d.sig2 = (s->r_fwhm * s->r_fwhm / (8.0 * log(2.0))) / (c.dx * c.dx);
+  d.t_hot = s->T_hot / kMec2;
+  d.one_minus_cos = 1.0 - cos(s->half_angle);
+  d.wn = w;   // absolute here; divided by w_ref when uploaded
+  r->srcs.push_back(d);
+  r->next_id += s->n_macro;
+  r->scheduled += s->n_macro;
+  return HYB_OK;
+}
+
+static hyb_status upload_sources(hyb_run* r) {
+  if (r->w_ref <= 0) r->w_ref = 1.0;
+  set_units(r->h, r->w_ref);
+  std::vector<SourceDesc> v = r->srcs;
+  for (auto& d : v) d.wn /= r->w_ref;
+  r->h.nsrc = (int)v.size();
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  if (!v.empty())
+    HIPCHK(r, hipMemcpy((void*)r->h.src, v.data(), v.size() * sizeof(SourceDesc), hipMemcpyHostToDevice));
+  return upload_desc(r);
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+// ---------------------------------------------------------------------------
+static hyb_status ensure_single_plans(hyb_run* r) {
+  if (r->L.particle.nb > 0) return HYB_OK;
+  PlanSpec ps;
+  add_run_plans(ps, 0, r->h);
+  r->L.runs = r->d_desc;
+  r->L.nruns = 1;
+  return upload_plans(r, r->stream, ps, r->L, &r->d_maps, &r->maps_bytes, r->dev);
+}
+
+static hyb_status step_direct(hyb_run* r, int32_t nsteps) {
+  for (int32_t s = 0; s < nsteps; ++s) {
+    LaunchSet L = r->L;
+    if (r->timing) {
+      if (r->ev_used >= r->ev_pool.size()) {
+        hipEvent_t a, b;
+        HIPCHK(r, hipEventCreate(&a));
+        HIPCHK(r, hipEventCreate(&b));
+        r->ev_pool.push_back({a, b});
+      }
+      L.ev_start = r->ev_pool[r->ev_used].first;
+      L.ev_stop = r->ev_pool[r->ev_used].second;
+      r->ev_used++;
+    }
+    launch_step(L, r->stream, r->cfg.precision, r->h.n_sub);
+    HIPCHK(r, hipGetLastError());
+  }
+  return HYB_OK;
+}
+
+static hyb_status step_graph(hyb_run* r, int32_t nsteps) {
+  if (!r->gexec) {
+    if (!r->cap_stream) HIPCHK(r, hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking));
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    hipGraph_t g = nullptr;
+    HIPCHK(r, hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeThreadLocal));
+    LaunchSet L = r->L;
+    launch_step(L, r->cap_stream, r->cfg.precision, r->h.n_sub);
+    HIPCHK(r, hipStreamEndCapture(r->cap_stream, &g));
+    HIPCHK(r, hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0));
+    HIPCHK(r, hipGraphDestroy(g));
+  }
+  for (int32_t s = 0; s < nsteps; ++s) HIPCHK(r, hipGraphLaunch(r->gexec, r->stream));
+  return HYB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hyb_status_string(hyb_status s) {
+  switch (s) {
+    case HYB_OK: return "ok";
+    case HYB_EINVAL: return "invalid argument";
+    case HYB_ENOMEM: return "out of memory";
+    case HYB_ENOSPACE: return "particle capacity exceeded";
+    case HYB_EDEVICE: return "device error";
+    case HYB_ESTATE: return "invalid state";
+    case HYB_ENUMERIC: return "non-finite value";
+    case HYB_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* hyb_last_error(const hyb_run* run) { return run ? run->err.c_str() : g_err.c_str(); }
+
+void hyb_abi_sizes(int64_t sizes[6]) {
+  sizes[0] = sizeof(hyb_config);
+  sizes[1] = sizeof(hyb_source);
+  sizes[2] = sizeof(hyb_device);
+  sizes[3] = sizeof(hyb_tally_out);
+  sizes[4] = sizeof(hyb_state);
+  sizes[5] = sizeof(hyb_run_info);
+}
+
+hyb_status hyb_footprint(const hyb_config* cfg, int64_t* bytes) {
+  if (!cfg || !bytes) return HYB_EINVAL;
+  if (!validate(*cfg).empty()) return HYB_EINVAL;
+  *bytes = (int64_t)make_layout(*cfg).total;
+  return HYB_OK;
+}
+
+hyb_status hyb_init(const hyb_config* cfg, const hyb_device* dev, hyb_run** out) {
+  if (!out) return HYB_EINVAL;
+  hyb_run* r = nullptr;
+  hyb_status st = create_run(cfg, dev, &r);
+  if (st != HYB_OK) {
+    // the message stays reachable through hyb_last_error(NULL)
+    destroy_run(r);
+    *out = nullptr;
+    return st;
+  }
+  st = upload_desc(r);
+  if (st != HYB_OK) { destroy_run(r); *out = nullptr; return st; }
+  *out = r;
+  return HYB_OK;
+}
+
+hyb_status hyb_inject(hyb_run* r, const hyb_source* src) {
+  if (!r) return HYB_EINVAL;
+  if (r->eng) return fail(r, HYB_ESTATE, "engine runs take their sources at admission");
+  hyb_status st = add_source(r, src);
+  if (st != HYB_OK) return st;
+  return upload_sources(r);
+}
+
+hyb_status hyb_step(hyb_run* r, int32_t nsteps) {
+  if (!r) return HYB_EINVAL;
+  if (r->eng) return fail(r, HYB_ESTATE, "engine runs advance through hyb_engine_step");
+  if (nsteps < 0) return fail(r, HYB_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return HYB_OK;
+  if (!r->w_locked) {
+    r->w_locked = true;
+    if (r->w_ref <= 0) r->w_ref = 1.0;
+    hyb_status st = upload_sources(r);
+    if (st != HYB_OK) return st;
+  }
+  hyb_status st = ensure_single_plans(r);
+  if (st != HYB_OK) return st;
+  HIPCHK(r, hipSetDevice(r->dev.device));
+  st = (r->use_graph && !r->timing) ? step_graph(r, nsteps) : step_direct(r, nsteps);
+  if (st == HYB_OK) r->host_step += nsteps;
+  return st;
+}
+
+hyb_status hyb_use_graph(hyb_run* r, int32_t on) {
+  if (!r) return HYB_EINVAL;
+  r->use_graph = on != 0;
+  return HYB_OK;
+}
+
+hyb_status hyb_timing_enable(hyb_run* r, int32_t on) {
+  if (!r) return HYB_EINVAL;
+  r->timing = on != 0;
+  return HYB_OK;
+}
+
+hyb_status hyb_timing_get(hyb_run* r, double* total_ms, int64_t* launches) {
+  if (!r) return HYB_EINVAL;
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  for (size_t k = 0; k < r->ev_used; ++k) {
+    float ms = 0.f;
+    HIPCHK(r, hipEventElapsedTime(&ms, r->ev_pool[k].first, r->ev_pool[k].second));
+    r->t_ms += ms;
+    r->t_n += 1;
+  }
+  r->ev_used = 0;
+  if (total_ms) *total_ms = r->t_ms;
+  if (launches) *launches = r->t_n;
+  r->t_ms = 0.0;
+  r->t_n = 0;
+  return HYB_OK;
+}
+
+hyb_status hyb_run_info_get(const hyb_run* r, hyb_run_info* info) {
+  if (!r || !info) return HYB_EINVAL;
+  const hyb_config& c = r->cfg;
+  info->n_sub = r->h.n_sub;
+  info->a0 = 8.5e-6 * sqrt(c.I0 * c.wavelength * c.wavelength);
+  info->eps_esc = r->h.eps_esc * kMec2;
+  info->n_i = r->h.n_i;
+  info->c_z = cz_of(c.Z);
+  info->w_ref = r->h.w_ref;
+  info->nodes = r->h.nodes;
+  info->cells = r->h.cells;
+  info->bytes = (int64_t)r->bytes;
+  return HYB_OK;
+}
+
+hyb_status hyb_table_get(const hyb_run* r, double* X, double* SIG, double* SUB) {
+  if (!r) return HYB_EINVAL;
+  if (X) memcpy(X, r->tabX.data(), r->tabX.size() * 8);
+  if (SIG) memcpy(SIG, r->tabSIG.data(), r->tabSIG.size() * 8);
+  if (SUB) memcpy(SUB, r->tabSUB.data(), r->tabSUB.size() * 8);
+  return HYB_OK;
+}
+
+hyb_status hyb_tally(hyb_run* r, hyb_tally_out* out) {
+  if (!r || !out) return HYB_EINVAL;
+  HIPCHK(r, hipSetDevice(r->dev.device));
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  const int nbin = r->cfg.tally_nE * r->cfg.tally_ntheta;
+  std::vector<double> hist(2 * (size_t)nbin + 4);
+  HIPCHK(r, hipMemcpy(hist.data(), r->h.tot_hist, hist.size() * 8, hipMemcpyDeviceToHost));
+  if (out->hist_E) memcpy(out->hist_E, hist.data(), (size_t)nbin * 8);
+  if (out->hist_N) memcpy(out->hist_N, hist.data() + nbin, (size_t)nbin * 8);
+  for (int k = 0; k < 4; ++k) out->flow[k] = hist[2 * (size_t)nbin + k];
+  double led[16];
+  HIPCHK(r, hipMemcpy(led, r->h.tot_led, 16 * 8, hipMemcpyDeviceToHost));
+  for (int k = 0; k < HYB_LEDGER_N; ++k) out->ledger[k] = led[k];
+  long long ev[16];
+  HIPCHK(r, hipMemcpy(ev, r->h.events, 16 * 8, hipMemcpyDeviceToHost));
+  for (int k = 0; k < HYB_COUNTER_N; ++k) out->counters[k] = ev[k];
+  if (out->series && r->cfg.series_len > 0)
+    HIPCHK(r, hipMemcpy(out->series, r->h.series, (size_t)r->cfg.series_len * 8, hipMemcpyDeviceToHost));
+  Counters ctr;
+  HIPCHK(r, hipMemcpy(&ctr, r->h.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  out->step = ctr.step;
+  // kinetic energy and alive count of the resident particles
+  int nb = clampi((ctr.n_total + 255) / 256, 1, kRedBlocks);
+  const RunDesc* base = r->eng ? r->d_desc : r->d_desc;
+  launch_kinetic(base, 0, nb, r->stream, r->cfg.precision);
+  HIPCHK(r, hipGetLastError());
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  std::vector<double> red(2 * (size_t)nb);
+  HIPCHK(r, hipMemcpy(red.data(), r->h.red, red.size() * 8, hipMemcpyDeviceToHost));
+  double kin = 0.0, alive = 0.0;
+  for (int b = 0; b < nb; ++b) { kin += red[2 * b]; alive += red[2 * b + 1]; }
+  out->kinetic = kin * r->h.w_ref * kMec2;
+  out->n_alive = (int64_t)llround(alive);
+  out->conversion = led[HYB_L_INJECTED] > 0 ? led[HYB_L_PHOTON_THR] / led[HYB_L_INJECTED] : 0.0;
+  return HYB_OK;
+}
+
+hyb_status hyb_get_state(hyb_run* r, hyb_state* st) {
+  if (!r || !st) return HYB_EINVAL;
+  HIPCHK(r, hipSetDevice(r->dev.device));
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  const hyb_config& c = r->cfg;
+  Counters ctr;
+  HIPCHK(r, hipMemcpy(&ctr, r->h.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  const size_t n = (size_t)ctr.n_total;
+  const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
+  const PartPtrs& P = r->h.p[ctr.cur];
+  std::vector<uint32_t> cell(n), id(n);
+  std::vector<char> raw[8];
+  void* src[8] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau};
+  if (n) {
+    HIPCHK(r, hipMemcpy(cell.data(), P.cell, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(r, hipMemcpy(id.data(), P.id, n * 4, hipMemcpyDeviceToHost));
+    for (int f = 0; f < 8; ++f) {
+      raw[f].resize(n * ts);
+      HIPCHK(r, hipMemcpy(raw[f].data(), src[f], n * ts, hipMemcpyDeviceToHost));
+    }
+  }
+  auto val = [&](int f, size_t i) -> double {
+    return ts == 8 ? ((const double*)raw[f].data())[i] : (double)((const float*)raw[f].data())[i];
+  };
+  size_t alive = 0;
+  for (size_t i = 0; i < n; ++i) alive += cell[i] != kDead;
+  st->step = ctr.step;
+  st->next_id = r->next_id;
+  if ((int64_t)alive > st->capacity) {
+    st->n = (int64_t)alive;
+    return fail(r, HYB_ENOSPACE, "state buffers too small");
+  }
+  size_t k = 0;
+  const double mc = kMe * kC;
+  for (size_t i = 0; i < n; ++i) {
+    if (cell[i] == kDead) continue;
+    const uint32_t cc = cell[i];
+    if (st->pos) {
+      st->pos[3 * k + 0] = (cell_i(cc) + val(0, i)) * c.dx;
+      st->pos[3 * k + 1] = (cell_j(cc) + val(1, i)) * c.dx;
+      st->pos[3 * k + 2] = (cell_k(cc) + val(2, i)) * c.dx;
+    }
+    if (st->mom) {
+      st->mom[3 * k + 0] = val(3, i) * mc;
+      st->mom[3 * k + 1] = val(4, i) * mc;
+      st->mom[3 * k + 2] = val(5, i) * mc;
+    }
+    if (st->w) st->w[k] = val(6, i) * r->h.w_ref;
+    if (st->tau) st->tau[k] = val(7, i);
+    if (st->id) st->id[k] = id[i];
+    ++k;
+  }
+  st->n = (int64_t)k;
+  const size_t nodes = (size_t)r->h.nodes, cells = (size_t)r->h.cells;
+  auto get_typed = [&](double* dst, const void* srcp, size_t cnt) -> hipError_t {
+    if (ts == 8) return hipMemcpy(dst, srcp, cnt * 8, hipMemcpyDeviceToHost);
+    std::vector<float> f(cnt);
+    hipError_t e = hipMemcpy(f.data(), srcp, cnt * 4, hipMemcpyDeviceToHost);
+    for (size_t i = 0; i < cnt; ++i) dst[i] = f[i];
+    return e;
+  };
+  for (int d = 0; d < 3; ++d) {
+    if (st->E) HIPCHK(r, get_typed(st->E + d * nodes, r->h.E[d], nodes));
+    if (st->B) HIPCHK(r, get_typed(st->B + d * nodes, r->h.B[d], nodes));
+    if (st->J) {
+      std::vector<long long> j(nodes);
+      HIPCHK(r, hipMemcpy(j.data(), r->h.J[d], nodes * 8, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < nodes; ++i) st->J[d * nodes + i] = (double)j[i] * r->h.j_unit;
+    }
+  }
+  if (st->Te) HIPCHK(r, hipMemcpy(st->Te, r->h.Te, cells * 8, hipMemcpyDeviceToHost));
+  if (st->Ti) HIPCHK(r, hipMemcpy(st->Ti, r->h.Ti, cells * 8, hipMemcpyDeviceToHost));
+  if (st->eta) HIPCHK(r, hipMemcpy(st->eta, r->h.eta, cells * 8, hipMemcpyDeviceToHost));
+  if (st->ion_heat) {
+    std::vector<long long> q(cells);
+    HIPCHK(r, hipMemcpy(q.data(), r->h.ion_heat, cells * 8, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cells; ++i) st->ion_heat[i] = (double)q[i] * r->h.heat_unit;
+  }
+  return HYB_OK;
+}
+
+hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
+  if (!r || !st) return HYB_EINVAL;
+  if (r->eng) return fail(r, HYB_ESTATE, "engine runs do not take a state");
+  const hyb_config& c = r->cfg;
+  if (st->n < 0 || st->n > c.max_particles) return fail(r, HYB_ENOSPACE, "too many particles for max_particles");
+  const size_t n = (size_t)st->n;
+  if (n && (!st->pos || !st->mom || !st->w || !st->tau || !st->id))
+    return fail(r, HYB_EINVAL, "particle arrays missing");
+  {
+    // electrons the sources will still inject from st->step on must fit too
+    int64_t later = 0;
+    for (const SourceDesc& d : r->srcs)
+      for (long long i = std::max(0LL, (long long)st->step - d.s0); i < d.ns; ++i)
+        later += d.base + (i < d.rem ? 1 : 0);
+    if ((int64_t)n + later > c.max_particles)
+      return fail(r, HYB_ENOSPACE, "particles plus later injections exceed max_particles");
+  }
+  HIPCHK(r, hipSetDevice(r->dev.device));
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  // accumulator scale: the largest weight given, unless sources fixed it
+  if (!r->w_locked) {
+    double wm = 0.0;
+    for (size_t i = 0; i < n; ++i) wm = std::max(wm, st->w[i]);
+    if (r->srcs.empty() && wm > 0) r->w_ref = wm;
+    else if (wm > 0) r->w_ref = std::max(r->w_ref, wm);
+    if (r->w_ref <= 0) r->w_ref = 1.0;
+    set_units(r->h, r->w_ref);
+  }
+  const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
+  std::vector<uint32_t> cell(n);
+  std::vector<double> f[8];
+  for (int k = 0; k < 8; ++k) f[k].resize(n);
+  const int lo[3] = {r->h.ix_lo, 0, 0}, hi[3] = {r->h.ix_hi, c.ny, c.nz};
+  for (size_t i = 0; i < n; ++i) {
+    int ci[3];
+    for (int d = 0; d < 3; ++d) {
+      double X = st->pos[3 * i + d] / c.dx;
+      const double Xr = nearbyint(X);
+      if (fabs(X - Xr) < 1e-12 * fmax(1.0, fabs(X))) X = Xr;   // on a cell face: undo x/dx rounding
+      double fl = floor(X);
+      double o = X - fl;
+      if (ts == 4 && (double)(float)o >= 1.0) { fl += 1.0; o = 0.0; }
+      if (!(fl >= lo[d] && fl < hi[d])) return fail(r, HYB_EINVAL, "particle outside the slab box");
+      ci[d] = (int)fl;
+      f[d][i] = o;
+    }
+    cell[i] = pack_cell(ci[0], ci[1], ci[2]);
+    for (int d = 0; d < 3; ++d) f[3 + d][i] = st->mom[3 * i + d] / (kMe * kC);
+    f[6][i] = st->w[i] / r->w_ref;
+    f[7][i] = st->tau[i];
+    for (int k = 3; k < 8; ++k)
+      if (!std::isfinite(f[k][i])) return fail(r, HYB_ENUMERIC, "non-finite particle value");
+  }
+  const PartPtrs& P = r->h.p[0];
+  void* dst[8] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau};
+  auto put_typed = [&](void* d, const double* v, size_t cnt) -> hipError_t {
+    if (ts == 8) return hipMemcpy(d, v, cnt * 8, hipMemcpyHostToDevice);
+    std::vector<float> fl(v, v + cnt);
+    return hipMemcpy(d, fl.data(), cnt * 4, hipMemcpyHostToDevice);
+  };
+  if (n) {
+    HIPCHK(r, hipMemcpy(P.cell, cell.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(P.id, st->id, n * 4, hipMemcpyHostToDevice));
+    for (int k = 0; k < 8; ++k) HIPCHK(r, put_typed(dst[k], f[k].data(), n));
+  }
+  const size_t nodes = (size_t)r->h.nodes, cells = (size_t)r->h.cells;
+  for (int d = 0; d < 3; ++d) {
+    if (st->E) HIPCHK(r, put_typed(r->h.E[d], st->E + d * nodes, nodes));
+    if (st->B) HIPCHK(r, put_typed(r->h.B[d], st->B + d * nodes, nodes));
+    HIPCHK(r, hipMemset(r->h.J[d], 0, nodes * 8));
+  }
+  if (st->Te) HIPCHK(r, hipMemcpy(r->h.Te, st->Te, cells * 8, hipMemcpyHostToDevice));
+  if (st->Ti) HIPCHK(r, hipMemcpy(r->h.Ti, st->Ti, cells * 8, hipMemcpyHostToDevice));
+  if (st->eta) HIPCHK(r, hipMemcpy(r->h.eta, st->eta, cells * 8, hipMemcpyHostToDevice));
+  HIPCHK(r, hipMemset(r->h.ion_heat, 0, cells * 8));
+  HIPCHK(r, hipMemset(r->h.acc_led, 0, 16 * 8));
+  HIPCHK(r, hipMemset(r->h.acc_hist, 0, (2 * (size_t)c.tally_nE * c.tally_ntheta + 4) * 8));
+  Counters ctr{};
+  ctr.n_total = (long long)n;
+  ctr.step = st->step;
+  ctr.cur = 0;
+  ctr.active = 1;
+  HIPCHK(r, hipMemcpy(r->h.ctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice));
+  r->host_step = st->step;
+  if (st->next_id > r->next_id) r->next_id = st->next_id;
+  return upload_desc(r);
+}
+
+void hyb_free(hyb_run* r) {
+  if (!r || r->eng) return;
+  (void)hipSetDevice(r->dev.device);
+  destroy_run(r);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving engine
+// ---------------------------------------------------------------------------
+struct hyb_engine {
+  hyb_device dev{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int64_t budget = 0, used = 0;
+  int32_t max_runs = 0;
+  RunDesc* d_descs[2] = {nullptr, nullptr};      // per precision: [max_runs]
+  std::vector<hyb_run*> slots[2];                 // per precision
+  LaunchSet L[2];
+  BlockMap* d_maps[2] = {nullptr, nullptr};
+  size_t maps_bytes[2] = {0, 0};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool dirty[2] = {true, true};
+  int max_sub[2] = {1, 1};
+  std::string err;
+};
+
+static hyb_status eng_fail(hyb_engine* e, hyb_status s, const std::string& m) {
+  e->err = m;
+  g_err = m;
+  return s;
+}
+
+#define EHIPCHK(e, call)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return eng_fail((e), HYB_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static hyb_status eng_rebuild(hyb_engine* e, int p) {
+  PlanSpec ps;
+  int maxsub = 1, nres = 0;
+  for (int s = 0; s < e->max_runs; ++s) {
+    hyb_run* r = e->slots[p][s];
+    if (!r) continue;
+    add_run_plans(ps, s, r->h);
+    maxsub = std::max(maxsub, r->h.n_sub);
+    ++nres;
+  }
+  if (e->gexec[p]) { (void)hipGraphExecDestroy(e->gexec[p]); e->gexec[p] = nullptr; }
+  e->dirty[p] = false;
+  e->max_sub[p] = maxsub;
+  e->L[p] = LaunchSet{};
+  if (nres == 0) return HYB_OK;
+  e->L[p].runs = e->d_descs[p];
+  e->L[p].nruns = e->max_runs;
+  hyb_run tmp;
+  hyb_status st = upload_plans(&tmp, e->stream, ps, e->L[p], &e->d_maps[p], &e->maps_bytes[p], e->dev);
+  if (st != HYB_OK) return eng_fail(e, st, tmp.err);
+  // capture one tick of this precision group as a graph
+  hipGraph_t g = nullptr;
+  EHIPCHK(e, hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+  launch_step(e->L[p], e->cap_stream, p, maxsub);
+  EHIPCHK(e, hipStreamEndCapture(e->cap_stream, &g));
+  EHIPCHK(e, hipGraphInstantiate(&e->gexec[p], g, nullptr, nullptr, 0));
+  EHIPCHK(e, hipGraphDestroy(g));
+  return HYB_OK;
+}
+
+extern "C" {
+
+hyb_status hyb_engine_create(const hyb_device* dev, int64_t hbm_budget, int32_t max_runs, hyb_engine** out) {
+  if (!dev || !out || max_runs < 1 || max_runs > 4096 || hbm_budget < 0) return HYB_EINVAL;
+  *out = nullptr;
+  if (hipSetDevice(dev->device) != hipSuccess) return HYB_EDEVICE;
+  hyb_engine* e = new hyb_engine();
+  e->dev = *dev;
+  e->stream = (hipStream_t)dev->stream;
+  e->max_runs = max_runs;
+  if (hbm_budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete e; return HYB_EDEVICE; }
+    hbm_budget = (int64_t)(0.9 * (double)fr);
+  }
+  e->budget = hbm_budget;
+  for (int p = 0; p < 2; ++p) {
+    e->slots[p].assign(max_runs, nullptr);
+    e->d_descs[p] = (RunDesc*)dev_alloc(e->dev, sizeof(RunDesc) * max_runs);
+    if (!e->d_descs[p]) { hyb_engine_free(e); return HYB_ENOMEM; }
+    if (hipMemset(e->d_descs[p], 0, sizeof(RunDesc) * max_runs) != hipSuccess) { hyb_engine_free(e); return HYB_EDEVICE; }
+  }
+  if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) { hyb_engine_free(e); return HYB_EDEVICE; }
+  *out = e;
+  return HYB_OK;
+}
+
+hyb_status hyb_engine_admit(hyb_engine* e, const hyb_config* cfg, const hyb_source* srcs, int32_t nsrc,
+                            int32_t nsteps, hyb_run** out) {
+  if (!e || !cfg || !out || nsrc < 0 || nsrc > kMaxSources || (nsrc > 0 && !srcs) || nsteps < 1) return HYB_EINVAL;
+  *out = nullptr;
+  const std::string v = validate(*cfg);
+  if (!v.empty()) return eng_fail(e, HYB_EINVAL, v);
+  const int p = cfg->precision;
+  int slot = -1;
+  for (int s = 0; s < e->max_runs; ++s)
+    if (!e->slots[0][s] && !e->slots[1][s]) { slot = s; break; }
+  const int64_t need = (int64_t)make_layout(*cfg).total;
+  if (slot < 0) return eng_fail(e, HYB_EBUSY, "no free slot");
+  if (e->used + need > e->budget) return eng_fail(e, HYB_EBUSY, "footprint does not fit the budget now");
+  hyb_device d = e->dev;
+  d.stream = e->stream;
+  hyb_run* r = nullptr;
+  hyb_status st = create_run(cfg, &d, &r);
+  if (st != HYB_OK) {
+    e->err = r ? r->err : "create failed";
+    destroy_run(r);
+    return st;
+  }
+  for (int k = 0; k < nsrc; ++k) {
+    st = add_source(r, &srcs[k]);
+    if (st != HYB_OK) { e->err = r->err; destroy_run(r); return st; }
+  }
+  r->w_locked = true;
+  if (r->w_ref <= 0) r->w_ref = 1.0;
+  r->eng = e;
+  r->slot = slot;
+  r->nsteps_engine = nsteps;
+  r->d_desc = e->d_descs[p] + slot;
+  st = upload_sources(r);   // also writes the descriptor into the engine slot
+  if (st != HYB_OK) { e->err = r->err; r->eng = nullptr; destroy_run(r); return st; }
+  Counters ctr{};
+  ctr.active = 1;
+  ctr.steps_left = nsteps;
+  if (hipMemcpy(r->h.ctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice) != hipSuccess) {
+    r->eng = nullptr; destroy_run(r); return eng_fail(e, HYB_EDEVICE, "counter upload failed");
+  }
+  e->slots[p][slot] = r;
+  e->used += need;
+  e->dirty[p] = true;
+  *out = r;
+  return HYB_OK;
+}
+
+hyb_status hyb_engine_step(hyb_engine* e, int32_t nticks) {
+  if (!e || nticks < 0) return HYB_EINVAL;
+  EHIPCHK(e, hipSetDevice(e->dev.device));
+  for (int p = 0; p < 2; ++p)
+    if (e->dirty[p]) {
+      EHIPCHK(e, hipStreamSynchronize(e->stream));
+      hyb_status st = eng_rebuild(e, p);
+      if (st != HYB_OK) return st;
+    }
+  for (int32_t t = 0; t < nticks; ++t)
+    for (int p = 0; p < 2; ++p)
+      if (e->gexec[p]) EHIPCHK(e, hipGraphLaunch(e->gexec[p], e->stream));
+  for (int p = 0; p < 2; ++p)
+    for (hyb_run* r : e->slots[p])
+      if (r) r->host_step += nticks;
+  return HYB_OK;
+}
+
+hyb_status hyb_engine_poll(hyb_engine* e, hyb_run** done, int32_t cap, int32_t* ndone) {
+  if (!e || !ndone || (cap > 0 && !done)) return HYB_EINVAL;
+  EHIPCHK(e, hipStreamSynchronize(e->stream));
+  int32_t k = 0;
+  for (int p = 0; p < 2; ++p)
+    for (hyb_run* r : e->slots[p]) {
+      if (!r) continue;
+      Counters ctr;
+      EHIPCHK(e, hipMemcpy(&ctr, r->h.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+      if (!ctr.active) {
+        if (k < cap) done[k] = r;
+        ++k;
+      }
+    }
+  *ndone = std::min(k, cap);
+  return HYB_OK;
+}
+
+hyb_status hyb_engine_retire(hyb_engine* e, hyb_run* r) {
+  if (!e || !r || r->eng != e) return HYB_EINVAL;
+  EHIPCHK(e, hipStreamSynchronize(e->stream));
+  const int p = r->cfg.precision;
+  e->slots[p][r->slot] = nullptr;
+  e->used -= (int64_t)r->bytes;
+  e->dirty[p] = true;
+  RunDesc zero{};
+  EHIPCHK(e, hipMemcpy(e->d_descs[p] + r->slot, &zero, sizeof(RunDesc), hipMemcpyHostToDevice));
+  r->eng = nullptr;
+  r->stream = e->stream;
+  destroy_run(r);
+  return HYB_OK;
+}
+
+hyb_status hyb_engine_stats(const hyb_engine* e, int32_t* resident, int64_t* bytes_used, int64_t* budget) {
+  if (!e) return HYB_EINVAL;
+  int32_t n = 0;
+  for (int p = 0; p < 2; ++p)
+    for (hyb_run* r : e->slots[p]) n += r != nullptr;
+  if (resident) *resident = n;
+  if (bytes_used) *bytes_used = e->used;
+  if (budget) *budget = e->budget;
+  return HYB_OK;
+}
+
+void hyb_engine_free(hyb_engine* e) {
+  if (!e) return;
+  (void)hipSetDevice(e->dev.device);
+  (void)hipStreamSynchronize(e->stream);
+  for (int p = 0; p < 2; ++p) {
+    for (hyb_run* r : e->slots[p])
+      if (r) { r->eng = nullptr; destroy_run(r); }
+    if (e->gexec[p]) (void)hipGraphExecDestroy(e->gexec[p]);
+    if (e->d_maps[p]) dev_free(e->dev, e->d_maps[p]);
+    if (e->d_descs[p]) dev_free(e->dev, e->d_descs[p]);
+  }
+  if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+  delete e;
+}
+
+}  // extern "C"

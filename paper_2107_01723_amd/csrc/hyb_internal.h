@@ -1,0 +1,274 @@
+// Internal definitions of the MI355X hybrid-PIC library: device-resident run
+// descriptor, fixed-point accumulator scales, counter-based random numbers,
+// table lookups and rotation helpers.  Shared by the kernels and the host
+// runtime; never exposed through the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hyb {
+
+// ---- physical constants (CODATA 2018, SI) --------------------------------
+constexpr double kC = 299792458.0;
+constexpr double kE = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kHbar = 1.054571817e-34;
+constexpr double kH = 6.62607015e-34;
+constexpr double kKb = 1.380649e-23;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMec2 = kMe * kC * kC;
+
+// ---- fixed-point accumulators --------------------------------------------
+// Sums that many threads add into are 64-bit integers, so every sum is exact
+// and independent of the order of the additions (runs are bitwise
+// reproducible alone or batched, with any particle order).
+//   ledger / tallies : 2^32 units per (w_ref m c^2) or per w_ref photons
+//   hot current      : 2^40 units per (e w_ref c / dx^3)
+//   collisional heat : 2^40 units per (w_ref m c^2)
+constexpr double kLedScale = 4294967296.0;          // 2^32
+constexpr double kJScale = 1099511627776.0;         // 2^40
+constexpr double kHeatScale = 1099511627776.0;      // 2^40
+
+enum { L_INJECTED = 0, L_FIELD_LOSS, L_FIELD_GAIN, L_ION, L_STOPPED, L_RAD_D, L_RAD_S,
+       L_ESCAPED, L_REFLUX, L_PHOTON_THR, L_RESIDUAL, L_N };
+enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_N };
+
+enum : uint32_t {
+  PHYS_FIELDS = 1u << 0, PHYS_ION = 1u << 1, PHYS_BREM = 1u << 2, PHYS_SCATTER = 1u << 3,
+  PHYS_EVOLVE_E = 1u << 4, PHYS_EVOLVE_B = 1u << 5, PHYS_HEAT = 1u << 6
+};
+
+constexpr uint32_t kDead = 0xFFFFFFFFu;
+constexpr int kMaxSources = 8;
+
+// packed cell index: 11 bits x, 10 bits y, 11 bits z
+__host__ __device__ __forceinline__ uint32_t pack_cell(int i, int j, int k) {
+  return (uint32_t)i | ((uint32_t)j << 11) | ((uint32_t)k << 21);
+}
+__host__ __device__ __forceinline__ int cell_i(uint32_t c) { return (int)(c & 0x7FFu); }
+__host__ __device__ __forceinline__ int cell_j(uint32_t c) { return (int)((c >> 11) & 0x3FFu); }
+__host__ __device__ __forceinline__ int cell_k(uint32_t c) { return (int)(c >> 21); }
+
+// Injection schedule and sampling parameters of one source (normalised units:
+// lengths in cells, energies in m c^2).
+struct SourceDesc {
+  long long s0, ns, base, rem, id0;
+  double y0, z0;          // spot centre [cells]
+  double sig2;            // r_fwhm^2 / (8 ln 2) [cells^2]
+  double t_hot;           // [m c^2]
+  double one_minus_cos;   // 1 - cos(half angle)
+  double wn;              // weight / w_ref
+};
+
+// Mutable per-run counters (device memory).
+struct Counters {
+  long long n_total;      // particle slots in use in the current buffer
+  long long step;         // steps completed
+  int cur;                // current particle buffer (0 or 1)
+  int active;             // engine: 1 while the run still has steps to do
+  long long steps_left;   // engine: steps still to do
+  long long n_sorted;     // alive particles after the last compaction
+};
+
+// Structure-of-arrays particle storage: packed cell, offsets in the cell,
+// momentum u = p / (m c), weight / w_ref, remaining optical depth, id.
+struct PartPtrs {
+  uint32_t* cell;
+  void* ox; void* oy; void* oz;
+  void* ux; void* uy; void* uz;
+  void* wn; void* tau;
+  uint32_t* id;
+};
+
+// Read-only description of one run (device memory; one per resident run).
+struct RunDesc {
+  int nx, ny, nz, ix_lo, ix_hi;
+  int n_sub, precision, nsrc;
+  uint32_t physics, seed;
+  long long nodes, cells, capacity;
+  double dx, dt;
+  // push and move
+  double e_kick;      // du = e_kick * E  per half step  (q dt / (2 m c), q = -e)
+  double b_rot;       // t  = b_rot * B / gamma          (q dt / (2 m))
+  double cdt_dx;      // cells moved per unit beta
+  // collisions (m c^2 units)
+  double c_ion, ln_iex;
+  double k_brem, k_sub, inv_boost;
+  double c_dav, l_dav;
+  // boundaries
+  double eps_esc, du_tnsa, keep_frac, sigma_dth, e_min;
+  int reflux_ke_mode;
+  // tables (precision of the run)
+  int tab_nT, tab_nr;
+  double tab_ln_kcut, tab_s_scale, tab_kcut;
+  const void* tab_X; const void* tab_SIG; const void* tab_SUB;
+  // photon tally
+  int nE, nth, series_len;
+  double ln_Elo, e_bin_scale, Ethr;
+  // fixed-point units
+  double w_ref;
+  double j_unit;      // A/m^2 per 2^-40 fixed unit of current
+  double heat_unit;   // J per fixed unit of collisional heat
+  double led_unit;    // J per fixed unit of the ledger
+  double cnt_unit;    // photons per fixed unit of the number tally
+  // solid (heat update, FP64)
+  double Z, A, rho, n_i, m_i, lambda1, lambda2, eta_fixed;
+  // arrays
+  void* E[3]; void* B[3];
+  long long* J[3];
+  double* Te; double* Ti; double* eta;
+  long long* ion_heat;
+  PartPtrs p[2];
+  Counters* ctr;
+  const SourceDesc* src;
+  long long* acc_led;       // [L_N] this step
+  long long* acc_hist;      // [2*nE*nth + 4] this step: energy bins, number bins, flow
+  long long* events;        // [C_N] whole run
+  double* tot_led; double* tot_led_c;     // Kahan sum and compensation
+  double* tot_hist; double* tot_hist_c;
+  double* series;
+  // cell sort
+  int sort_every;
+  unsigned* sort_cnt;       // [cells + 1]
+  unsigned* sort_blk;       // block sums of the scan
+  int sort_nblk;
+  double* red;              // per-block partial sums for host-side reductions
+};
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umulhi(a, b);
+#else
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+#endif
+}
+
+__host__ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = mulhi32(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = mulhi32(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// 23-bit uniform strictly inside (0, 1), exact in FP32 and FP64
+template <typename T>
+__host__ __device__ __forceinline__ T uni(uint32_t x) {
+  return ((T)(x >> 9) + (T)0.5) * (T)(1.0 / 8388608.0);
+}
+
+template <typename T> struct Uni4 { T a, b, c, d; };
+
+template <typename T>
+__host__ __device__ __forceinline__ Uni4<T> draws(uint32_t id, uint32_t seed, long long step, uint32_t slot) {
+  U4 r = philox((uint32_t)step, slot, 0u, 0u, id, seed);
+  return Uni4<T>{uni<T>(r.x), uni<T>(r.y), uni<T>(r.z), uni<T>(r.w)};
+}
+
+enum : uint32_t { SLOT_COLLIDE = 0, SLOT_PHOTON = 1, SLOT_REFLUX0 = 2, SLOT_INJ_A = 8, SLOT_INJ_B = 9 };
+
+// ---- math in the run's precision ------------------------------------------
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_cos(float x) { return cosf(x); }
+__device__ __forceinline__ double m_cos(double x) { return cos(x); }
+__device__ __forceinline__ float m_sin(float x) { return sinf(x); }
+__device__ __forceinline__ double m_sin(double x) { return sin(x); }
+__device__ __forceinline__ float m_acos(float x) { return acosf(x); }
+__device__ __forceinline__ double m_acos(double x) { return acos(x); }
+__device__ __forceinline__ float m_floor(float x) { return floorf(x); }
+__device__ __forceinline__ double m_floor(double x) { return floor(x); }
+__device__ __forceinline__ long long to_fixed(float x) { return __float2ll_rn(x); }
+__device__ __forceinline__ long long to_fixed(double x) { return __double2ll_rn(x); }
+
+// kinetic energy [m c^2] of u = p/(m c): u^2 / (1 + gamma), no cancellation
+template <typename T>
+__device__ __forceinline__ T kinetic(T u2, T g) { return u2 / ((T)1 + g); }
+
+// |u| of kinetic energy e [m c^2]
+template <typename T>
+__device__ __forceinline__ T umag_of(T e) { return m_sqrt(e * (e + (T)2)); }
+
+// Turn direction of (ux,uy,uz) by dth at azimuth phi, keeping |u|.  Basis:
+// a = unit(uhat x e_m), e_m the axis of the smallest |uhat_i| (ties -> lowest
+// index), b = uhat x a; uhat' = cos dth uhat + sin dth (cos phi a + sin phi b).
+template <typename T>
+__device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T phi) {
+  const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
+  const T inv = (T)1 / um;
+  const T hx = ux * inv, hy = uy * inv, hz = uz * inv;
+  const T ax_ = fabs(hx), ay_ = fabs(hy), az_ = fabs(hz);
+  T ax, ay, az;
+  if (ax_ <= ay_ && ax_ <= az_) { ax = (T)0; ay = hz; az = -hy; }        // uhat x x
+  else if (ay_ <= az_)          { ax = -hz; ay = (T)0; az = hx; }        // uhat x y
+  else                          { ax = hy; ay = -hx; az = (T)0; }        // uhat x z
+  const T an = (T)1 / m_sqrt(ax * ax + ay * ay + az * az);
+  ax *= an; ay *= an; az *= an;
+  const T bx = hy * az - hz * ay, by = hz * ax - hx * az, bz = hx * ay - hy * ax;
+  const T c = m_cos(dth), s = m_sin(dth), cp = m_cos(phi), sp = m_sin(phi);
+  T dx = c * hx + s * (cp * ax + sp * bx);
+  T dy = c * hy + s * (cp * ay + sp * by);
+  T dz = c * hz + s * (cp * az + sp * bz);
+  const T dn = um / m_sqrt(dx * dx + dy * dy + dz * dz);
+  ux = dx * dn; uy = dy * dn; uz = dz * dn;
+}
+
+// ---- bremsstrahlung table lookups ------------------------------------------
+template <typename T>
+struct TableView {
+  const T* X; const T* SIG; const T* SUB;
+  int nT, nr;
+  T ln_kcut, s_scale, kcut;
+  __device__ __forceinline__ void row(T lneps, int& j, T& f) const {
+    T s = s_scale * (lneps - ln_kcut);
+    s = s > (T)0 ? s : (T)0;                    // also maps NaN to row 0
+    s = s < (T)(nT - 1) ? s : (T)(nT - 1);
+    int jj = (int)m_floor(s);
+    jj = jj > nT - 2 ? nT - 2 : jj;
+    j = jj; f = s - (T)jj;
+  }
+  // sigma / C_Z ; 0 at or below k_cut
+  __device__ __forceinline__ T sigma(T eps, T lneps) const {
+    if (!(eps > kcut)) return (T)0;
+    int j; T f; row(lneps, j, f);
+    return SIG[j] + f * (SIG[j + 1] - SIG[j]);
+  }
+  // sub-cut stopping / C_Z [m c^2]; eps itself at or below k_cut
+  __device__ __forceinline__ T sub(T eps, T lneps) const {
+    if (!(eps > kcut)) return eps;
+    int j; T f; row(lneps, j, f);
+    return SUB[j] + f * (SUB[j + 1] - SUB[j]);
+  }
+  // photon energy for an electron of kinetic energy eps > k_cut and variate r
+  __device__ __forceinline__ T sample_k(T eps, T lneps, T r) const {
+    int j; T f; row(lneps, j, f);
+    const T q = r * (T)(nr - 1);
+    int i = (int)m_floor(q);
+    i = i > nr - 2 ? nr - 2 : i;
+    const T g = q - (T)i;
+    const T* r0 = X + (long long)j * nr;
+    const T* r1 = r0 + nr;
+    const T x0 = r0[i] + g * (r0[i + 1] - r0[i]);
+    const T x1 = r1[i] + g * (r1[i + 1] - r1[i]);
+    const T x = x0 + f * (x1 - x0);
+    return kcut * m_exp(x * (lneps - ln_kcut));
+  }
+};
+
+}  // namespace hyb

@@ -1,0 +1,31 @@
+// Launch interface between the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hyb_internal.h"
+
+namespace hyb {
+
+// One entry per workgroup of a batched launch: which run it serves, its
+// block index inside that run and how many blocks the run has.
+struct BlockMap { int run, lb, nb, pad; };
+
+struct Plan {
+  BlockMap* map = nullptr;   // device array [nb]
+  int nb = 0;
+};
+
+// Everything one step needs: the run descriptors and one plan per phase.
+struct LaunchSet {
+  const RunDesc* runs = nullptr;   // device array [nruns]
+  int nruns = 0;
+  Plan zero, inject, particle, grid, cells, fin, adv;
+  Plan sort_cnt, sort_scan, sort_scatter;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
+};
+
+void launch_step(const LaunchSet& L, hipStream_t s, int precision, int max_sub);
+void launch_kinetic(const RunDesc* runs, int run, int nblocks, hipStream_t s, int precision);
+
+}  // namespace hyb

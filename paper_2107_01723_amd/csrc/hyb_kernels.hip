@@ -1,0 +1,714 @@
+// HIP kernels of the hybrid-PIC step for gfx950 (CDNA4, 64-wide waves).
+//
+// Every kernel is "batched": it receives the device array of run
+// descriptors and a block map that assigns each workgroup to one run and a
+// block index inside that run, so one launch serves a single run or many
+// resident runs of the serving engine.  All loops are grid-stride over
+// counts read from device memory, so a step can be captured once as a HIP
+// graph and replayed while particles are injected and removed.
+#include <hip/hip_runtime.h>
+
+#include "hyb_internal.h"
+#include "hyb_kernels.h"
+#include "hyb_solid.h"
+
+namespace hyb {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// Number of electrons sources inject at `step`, and per-source first id.
+__device__ __forceinline__ long long inject_count(const RunDesc& R, long long step,
+                                                  long long* cnt = nullptr, long long* first = nullptr) {
+  long long tot = 0;
+  for (int s = 0; s < R.nsrc; ++s) {
+    const SourceDesc& S = R.src[s];
+    const long long i = step - S.s0;
+    long long c = 0;
+    if (i >= 0 && i < S.ns) c = S.base + (i < S.rem ? 1 : 0);
+    if (cnt) cnt[s] = c;
+    if (first) first[s] = S.id0 + i * S.base + (i < S.rem ? i : S.rem);
+    tot += c;
+  }
+  return tot;
+}
+
+// Block-wide sum of per-thread integer accumulators, then one atomic per
+// non-zero term: ledger terms to `led`, event counts to `evt`.
+template <int NL, int NC>
+__device__ __forceinline__ void block_flush(const long long (&v)[NL + NC], long long* __restrict__ led,
+                                            long long* __restrict__ evt) {
+  __shared__ long long sm[kWaves][NL + NC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NL + NC; ++i) {
+    long long x = v[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sm[wave][i] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NL + NC) {
+    long long s = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += sm[w][threadIdx.x];
+    if (s != 0) {
+      long long* dst = threadIdx.x < NL ? &led[threadIdx.x] : &evt[threadIdx.x - NL];
+      atomicAdd((unsigned long long*)dst, (unsigned long long)s);
+    }
+  }
+}
+
+__device__ __forceinline__ void atomic_add_i64(long long* p, long long v) {
+  atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+
+// Cell index and offset of a coordinate (cell units), kept inside [0, n).
+template <typename T>
+__device__ __forceinline__ void to_cell(T x, int n, int& c, T& o) {
+  T f = m_floor(x);
+  if (!(f >= (T)0)) { c = 0; o = (T)0; return; }
+  if (f > (T)(n - 1)) { c = n - 1; o = (T)1 - (T)(sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16); return; }
+  c = (int)f;
+  o = x - f;
+}
+
+// ---------------------------------------------------------------------------
+// injection (App. B exponential spectrum; Sec. II.B spot and cone)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ runs,
+                                                   const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  const Counters* ctr = R.ctr;
+  if (!ctr->active) return;
+  const long long step = ctr->step;
+  const long long n0 = ctr->n_total;
+  const PartPtrs P = R.p[ctr->cur];
+  long long cnt[kMaxSources], first[kMaxSources];
+  const long long tot = inject_count(R, step, cnt, first);
+  long long acc[L_N + C_N];
+#pragma unroll
+  for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
+  const T twopi = (T)(2.0 * kPi);
+  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
+    int s = 0;
+    long long off = 0;
+    while (s < R.nsrc - 1 && t >= off + cnt[s]) { off += cnt[s]; ++s; }
+    const SourceDesc& S = R.src[s];
+    const uint32_t id = (uint32_t)(first[s] + (t - off));
+    const Uni4<T> a = draws<T>(id, R.seed, step, SLOT_INJ_A);
+    const Uni4<T> b = draws<T>(id, R.seed, step, SLOT_INJ_B);
+    const T r = m_sqrt((T)-2 * (T)S.sig2 * m_log((T)1 - (T)0.5 * a.a));
+    const T ps = twopi * a.b;
+    const T y = (T)S.y0 + r * m_cos(ps);
+    const T z = (T)S.z0 + r * m_sin(ps);
+    const T eps = -(T)S.t_hot * m_log((T)1 - a.c);
+    const T ct = (T)1 - a.d * (T)S.one_minus_cos;
+    T st2 = (T)1 - ct * ct;
+    const T st = m_sqrt(st2 > (T)0 ? st2 : (T)0);
+    const T pc = twopi * b.a;
+    const T um = umag_of(eps);
+    const T ux = um * ct, uy = um * st * m_cos(pc), uz = um * st * m_sin(pc);
+    const T tau = -m_log((T)1 - b.b);
+    const long long slot = n0 + t;
+    if (slot >= R.capacity) break;   // never write past the particle arrays
+    int cy, cz;
+    T oy, oz;
+    to_cell(y, R.ny, cy, oy);
+    to_cell(z, R.nz, cz, oz);
+    P.cell[slot] = pack_cell(R.ix_lo, cy, cz);
+    ((T*)P.ox)[slot] = (T)0;
+    ((T*)P.oy)[slot] = oy;
+    ((T*)P.oz)[slot] = oz;
+    ((T*)P.ux)[slot] = ux;
+    ((T*)P.uy)[slot] = uy;
+    ((T*)P.uz)[slot] = uz;
+    ((T*)P.wn)[slot] = (T)S.wn;
+    ((T*)P.tau)[slot] = tau;
+    P.id[slot] = id;
+    const T u2 = ux * ux + uy * uy + uz * uz;
+    acc[L_INJECTED] += to_fixed(kinetic(u2, m_sqrt((T)1 + u2)) * (T)S.wn * (T)kLedScale);
+    acc[L_N + C_INJECTED] += 1;
+  }
+  block_flush<L_N, C_N>(acc, R.acc_led, R.events);
+}
+
+// ---------------------------------------------------------------------------
+// Yee stencil helpers.  Along an axis a node quantity uses indices (c, c+1)
+// with weights (1-o, o); a staggered quantity sits at half-integers and uses
+// (c-1, c) or (c, c+1).  A staggered index one past either end is the mirror
+// ghost of the nearest index, with the opposite sign.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Axis { int i0, i1; T w0, w1; };
+
+template <typename T>
+__device__ __forceinline__ Axis<T> node_axis(int c, T o) { return Axis<T>{c, c + 1, (T)1 - o, o}; }
+
+template <typename T>
+__device__ __forceinline__ Axis<T> stag_axis(int c, T o, int n) {
+  Axis<T> a;
+  T f;
+  if (o >= (T)0.5) { a.i0 = c; f = o - (T)0.5; }
+  else { a.i0 = c - 1; f = o + (T)0.5; }
+  a.i1 = a.i0 + 1;
+  a.w0 = (T)1 - f;
+  a.w1 = f;
+  if (a.i0 < 0) { a.i0 = 0; a.w0 = -a.w0; }
+  if (a.i1 > n - 1) { a.i1 = n - 1; a.w1 = -a.w1; }
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T gather8(const T* __restrict__ F, int sx, int sxy, const Axis<T>& ax,
+                                     const Axis<T>& ay, const Axis<T>& az) {
+  const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
+  const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
+  const T v00 = ax.w0 * F[r00 + ax.i0] + ax.w1 * F[r00 + ax.i1];
+  const T v10 = ax.w0 * F[r10 + ax.i0] + ax.w1 * F[r10 + ax.i1];
+  const T v01 = ax.w0 * F[r01 + ax.i0] + ax.w1 * F[r01 + ax.i1];
+  const T v11 = ax.w0 * F[r11 + ax.i0] + ax.w1 * F[r11 + ax.i1];
+  return az.w0 * (ay.w0 * v00 + ay.w1 * v10) + az.w1 * (ay.w0 * v01 + ay.w1 * v11);
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit8(long long* __restrict__ J, int sx, int sxy, const Axis<T>& ax,
+                                         const Axis<T>& ay, const Axis<T>& az, T amp) {
+  const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
+  const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
+  const T a00 = amp * az.w0 * ay.w0, a10 = amp * az.w0 * ay.w1;
+  const T a01 = amp * az.w1 * ay.w0, a11 = amp * az.w1 * ay.w1;
+  atomic_add_i64(&J[r00 + ax.i0], to_fixed(a00 * ax.w0));
+  atomic_add_i64(&J[r00 + ax.i1], to_fixed(a00 * ax.w1));
+  atomic_add_i64(&J[r10 + ax.i0], to_fixed(a10 * ax.w0));
+  atomic_add_i64(&J[r10 + ax.i1], to_fixed(a10 * ax.w1));
+  atomic_add_i64(&J[r01 + ax.i0], to_fixed(a01 * ax.w0));
+  atomic_add_i64(&J[r01 + ax.i1], to_fixed(a01 * ax.w1));
+  atomic_add_i64(&J[r11 + ax.i0], to_fixed(a11 * ax.w0));
+  atomic_add_i64(&J[r11 + ax.i1], to_fixed(a11 * ax.w1));
+}
+
+// ---------------------------------------------------------------------------
+// reflux / escape on one axis (Sec. II.A).  Returns false if the electron
+// leaves the simulation.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c, T& o, int lo, int hi,
+                                              T& ux, T& uy, T& uz, T& eps, T wn, uint32_t id,
+                                              long long step, long long (&acc)[L_N + C_N]) {
+  const bool below = c < lo;
+  const bool above = c >= hi;
+  if (!(below || above)) return true;
+  if (eps > (T)R.eps_esc) {
+    acc[L_ESCAPED] += to_fixed(eps * wn * (T)kLedScale);
+    acc[L_N + C_ESCAPED] += 1;
+    return false;
+  }
+  acc[L_N + C_REFLUX] += 1;
+  // mirror about the face, then clamp into [lo, hi)
+  int c2 = (below ? 2 * lo : 2 * hi) - c - 1;
+  T o2 = (T)1 - o;
+  if (o2 >= (T)1) { c2 += 1; o2 = (T)0; }
+  if (c2 < lo) { c2 = lo; o2 = (T)0; }
+  if (c2 >= hi) { c2 = hi - 1; o2 = (T)1 - (T)(sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16); }
+  c = c2;
+  o = o2;
+  T& un = axis == 0 ? ux : (axis == 1 ? uy : uz);
+  un = -un;
+  // energy or momentum loss
+  const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
+  T scale;
+  if (R.reflux_ke_mode) {
+    // an electron already stopped by the collisions (u = 0) stays at rest
+    scale = um > (T)0 ? umag_of(eps * (T)R.keep_frac) / um : (T)0;
+  } else {
+    const T um2 = um - (T)R.du_tnsa;
+    if (!(um2 > (T)0)) {
+      acc[L_REFLUX] += to_fixed(eps * wn * (T)kLedScale);
+      return false;
+    }
+    scale = um2 / um;
+  }
+  ux *= scale; uy *= scale; uz *= scale;
+  const T u2 = ux * ux + uy * uy + uz * uz;
+  const T eps_a = kinetic(u2, m_sqrt((T)1 + u2));
+  acc[L_REFLUX] += to_fixed((eps - eps_a) * wn * (T)kLedScale);
+  eps = eps_a;
+  if (u2 > (T)0) {
+    const Uni4<T> rd = draws<T>(id, R.seed, step, SLOT_REFLUX0 + (uint32_t)axis);
+    rotate(ux, uy, uz, (rd.a - (T)0.5) * (T)R.sigma_dth, (T)(2.0 * kPi) * rd.b);
+    const T v2 = ux * ux + uy * uy + uz * uz;
+    const T eps_r = kinetic(v2, m_sqrt((T)1 + v2));
+    acc[L_RESIDUAL] += to_fixed((eps - eps_r) * wn * (T)kLedScale);
+    eps = eps_r;
+  }
+  T& un2 = axis == 0 ? ux : (axis == 1 ? uy : uz);
+  un2 = below ? fabs(un2) : -fabs(un2);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// the particle step: gather, Boris, deposit, move, ionisation,
+// bremsstrahlung, Davies scatter, boundaries, low-energy removal
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__ runs,
+                                                     const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  if (bm.nb < 8) return;   // alignment padding between runs
+  const RunDesc& R = runs[bm.run];
+  const Counters* ctr = R.ctr;
+  if (!ctr->active) return;
+  const long long step = ctr->step;
+  long long n = ctr->n_total + inject_count(R, step);
+  n = n < R.capacity ? n : R.capacity;
+  const PartPtrs P = R.p[ctr->cur];
+  long long acc[L_N + C_N];
+#pragma unroll
+  for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
+
+  const int nx = R.nx, ny = R.ny, nz = R.nz;
+  const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
+  const uint32_t phys = R.physics;
+  const T* E0 = (const T*)R.E[0]; const T* E1 = (const T*)R.E[1]; const T* E2 = (const T*)R.E[2];
+  const T* B0 = (const T*)R.B[0]; const T* B1 = (const T*)R.B[1]; const T* B2 = (const T*)R.B[2];
+  TableView<T> tab{(const T*)R.tab_X, (const T*)R.tab_SIG, (const T*)R.tab_SUB, R.tab_nT, R.tab_nr,
+                   (T)R.tab_ln_kcut, (T)R.tab_s_scale, (T)R.tab_kcut};
+  const T e_kick = (T)R.e_kick, b_rot = (T)R.b_rot, cdt = (T)R.cdt_dx;
+  const T ledS = (T)kLedScale;
+  const T twopi = (T)(2.0 * kPi);
+
+  // XCD-aware split: workgroup b runs on XCD b % 8, so give each XCD one
+  // contiguous eighth of the (cell-sorted) particle array.
+  const int xcd = bm.lb & 7, kk = bm.lb >> 3, nb8 = bm.nb >> 3;
+  const long long seg = (((n + 7) >> 3) + kBlock - 1) / kBlock * kBlock;
+  const long long beg = (long long)xcd * seg;
+  const long long end = beg + seg < n ? beg + seg : n;
+  for (long long i = beg + (long long)kk * kBlock + threadIdx.x; i < end; i += (long long)nb8 * kBlock) {
+    const uint32_t cell = P.cell[i];
+    if (cell == kDead) continue;
+    int ci = cell_i(cell), cj = cell_j(cell), ck = cell_k(cell);
+    const int heat_cell = ci + nx * (cj + ny * ck);
+    T ox = ((const T*)P.ox)[i], oy = ((const T*)P.oy)[i], oz = ((const T*)P.oz)[i];
+    T ux = ((const T*)P.ux)[i], uy = ((const T*)P.uy)[i], uz = ((const T*)P.uz)[i];
+    const T wn = ((const T*)P.wn)[i];
+    T tau = ((const T*)P.tau)[i];
+    const uint32_t id = P.id[i];
+
+    T u2 = ux * ux + uy * uy + uz * uz;
+    const T eps0 = kinetic(u2, m_sqrt((T)1 + u2));
+
+    // stencils at x^n (shared by gather and deposit)
+    const Axis<T> nxa = node_axis(ci, ox), nya = node_axis(cj, oy), nza = node_axis(ck, oz);
+    const Axis<T> sxa = stag_axis(ci, ox, nx), sya = stag_axis(cj, oy, ny), sza = stag_axis(ck, oz, nz);
+
+    // --- gather + Boris push (q = -e) ---
+    if (phys & PHYS_FIELDS) {
+      const T Ex = gather8(E0, sx, sxy, sxa, nya, nza);
+      const T Ey = gather8(E1, sx, sxy, nxa, sya, nza);
+      const T Ez = gather8(E2, sx, sxy, nxa, nya, sza);
+      const T Bx = gather8(B0, sx, sxy, nxa, sya, sza);
+      const T By = gather8(B1, sx, sxy, sxa, nya, sza);
+      const T Bz = gather8(B2, sx, sxy, sxa, sya, nza);
+      const T ex = e_kick * Ex, ey = e_kick * Ey, ez = e_kick * Ez;
+      const T mx = ux + ex, my = uy + ey, mz = uz + ez;
+      const T gi = b_rot / m_sqrt((T)1 + mx * mx + my * my + mz * mz);
+      const T tx = gi * Bx, ty = gi * By, tz = gi * Bz;
+      const T sf = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
+      const T sxv = sf * tx, syv = sf * ty, szv = sf * tz;
+      const T px = mx + (my * tz - mz * ty), py = my + (mz * tx - mx * tz), pz = mz + (mx * ty - my * tx);
+      ux = mx + (py * szv - pz * syv) + ex;
+      uy = my + (pz * sxv - px * szv) + ey;
+      uz = mz + (px * syv - py * sxv) + ez;
+    }
+    u2 = ux * ux + uy * uy + uz * uz;
+    T g = m_sqrt((T)1 + u2);
+    const T eps1 = kinetic(u2, g);
+    {
+      const T dW = eps1 - eps0;
+      if (dW > (T)0) acc[L_FIELD_GAIN] += to_fixed(dW * wn * ledS);
+      else acc[L_FIELD_LOSS] += to_fixed(-dW * wn * ledS);
+    }
+    const T ig = (T)1 / g;
+    const T vx = ux * ig, vy = uy * ig, vz = uz * ig;
+
+    // --- hot-current deposit at x^n with the pushed velocity ---
+    {
+      const T amp = -wn * (T)kJScale;
+      deposit8(R.J[0], sx, sxy, sxa, nya, nza, amp * vx);
+      deposit8(R.J[1], sx, sxy, nxa, sya, nza, amp * vy);
+      deposit8(R.J[2], sx, sxy, nxa, nya, sza, amp * vz);
+    }
+
+    // --- move ---
+    ox += vx * cdt; oy += vy * cdt; oz += vz * cdt;
+    {
+      const T fx = m_floor(ox), fy = m_floor(oy), fz = m_floor(oz);
+      ci += (int)fx; cj += (int)fy; ck += (int)fz;
+      ox -= fx; oy -= fy; oz -= fz;
+    }
+
+    // --- ionisation, eq. (stop_ion) ---
+    T eps2 = eps1;
+    if ((phys & PHYS_ION) && u2 > (T)0) {
+      const T beta = m_sqrt(u2) * ig;
+      T L = m_log(eps1) - (T)R.ln_iex + (T)0.5 * m_log(g + (T)1) + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
+      L = L > (T)0 ? L : (T)0;
+      T dE = (T)R.c_ion * L / beta;
+      dE = dE < eps1 ? dE : eps1;
+      const T sc = umag_of(eps1 - dE) / m_sqrt(u2);
+      ux *= sc; uy *= sc; uz *= sc;
+      u2 = ux * ux + uy * uy + uz * uz;
+      g = m_sqrt((T)1 + u2);
+      eps2 = kinetic(u2, g);
+      const T ion = (eps1 - eps2) * wn;
+      acc[L_ION] += to_fixed(ion * ledS);
+      atomic_add_i64(&R.ion_heat[heat_cell], to_fixed(ion * (T)kHeatScale));
+    }
+
+    // --- bremsstrahlung: optical depth, one emission per step at most ---
+    Uni4<T> cd{};
+    if (phys & (PHYS_BREM | PHYS_SCATTER)) cd = draws<T>(id, R.seed, step, SLOT_COLLIDE);
+    T eps3 = eps2;
+    if ((phys & PHYS_BREM) && u2 > (T)0) {
+      const T lne = m_log(eps2);
+      const T um = m_sqrt(u2);
+      const T beta = um / g;
+      tau -= (T)R.k_brem * tab.sigma(eps2, lne) * beta;
+      const T sub = (T)R.k_sub * tab.sub(eps2, lne) * beta;
+      T kph = (T)0;
+      if (tau < (T)0) {
+        kph = tab.sample_k(eps2, lne, cd.d);
+        const Uni4<T> pd = draws<T>(id, R.seed, step, SLOT_PHOTON);
+        tau = -m_log((T)1 - pd.c);
+        // photon direction about the electron direction
+        T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
+        th = th < (T)kPi ? th : (T)kPi;
+        T dxp = ux, dyp = uy, dzp = uz;
+        rotate(dxp, dyp, dzp, th, twopi * pd.b);
+        T cx = dxp / um;
+        cx = cx > (T)1 ? (T)1 : (cx < (T)-1 ? (T)-1 : cx);
+        const T tq = m_acos(cx) * (T)R.nth * (T)(1.0 / kPi);
+        const int it = tq >= (T)0 ? (tq < (T)(R.nth - 1) ? (int)tq : R.nth - 1) : 0;
+        const T eq = (m_log(kph) - (T)R.ln_Elo) * (T)R.e_bin_scale;
+        const int ie = !(eq >= (T)0) ? -1 : (eq >= (T)R.nE ? R.nE : (int)eq);
+        const T wph = wn * (T)R.inv_boost;
+        const long long vE = to_fixed(kph * wph * ledS);
+        const long long vN = to_fixed(wph * ledS);
+        const int nbin = R.nE * R.nth;
+        if (ie < 0) {
+          atomic_add_i64(&R.acc_hist[2 * nbin + 0], vE);
+          atomic_add_i64(&R.acc_hist[2 * nbin + 1], vN);
+        } else if (ie >= R.nE) {
+          atomic_add_i64(&R.acc_hist[2 * nbin + 2], vE);
+          atomic_add_i64(&R.acc_hist[2 * nbin + 3], vN);
+        } else {
+          atomic_add_i64(&R.acc_hist[ie * R.nth + it], vE);
+          atomic_add_i64(&R.acc_hist[nbin + ie * R.nth + it], vN);
+        }
+        if (kph >= (T)R.Ethr) acc[L_PHOTON_THR] += vE;
+        acc[L_RAD_D] += vE;
+        acc[L_N + C_EMITTED] += 1;
+      }
+      const T kb = kph * (T)R.inv_boost;
+      const T room = eps2 - kb;                   // >= 0: k <= eps2, boost >= 1
+      const T sub_a = sub < room ? sub : room;    // sub-cut loss actually applied
+      const T sc = umag_of(room - sub_a) / um;
+      ux *= sc; uy *= sc; uz *= sc;
+      u2 = ux * ux + uy * uy + uz * uz;
+      g = m_sqrt((T)1 + u2);
+      eps3 = kinetic(u2, g);
+      acc[L_RAD_S] += to_fixed(sub_a * wn * ledS);
+      acc[L_RESIDUAL] += to_fixed((eps2 - eps3 - kb - sub_a) * wn * ledS);
+    }
+
+    // --- Davies elastic scatter ---
+    if ((phys & PHYS_SCATTER) && u2 > (T)0) {
+      const T um = m_sqrt(u2);
+      T lg = m_log((T)R.l_dav * um);
+      lg = lg > (T)0 ? lg : (T)0;
+      const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
+      const T gam = m_sqrt((T)-2 * m_log(cd.a)) * m_cos(twopi * cd.b);
+      rotate(ux, uy, uz, gam * m_sqrt(s2), twopi * cd.c);
+      // elastic: any change of the stored energy is rounding, booked apart
+      u2 = ux * ux + uy * uy + uz * uz;
+      g = m_sqrt((T)1 + u2);
+      const T eps_r = kinetic(u2, g);
+      acc[L_RESIDUAL] += to_fixed((eps3 - eps_r) * wn * ledS);
+      eps3 = eps_r;
+    }
+
+    // --- boundaries: x (slab faces), y, z (domain walls) ---
+    T eps = eps3;
+    bool alive = boundary_axis(R, 0, ci, ox, R.ix_lo, R.ix_hi, ux, uy, uz, eps, wn, id, step, acc);
+    if (alive) alive = boundary_axis(R, 1, cj, oy, 0, ny, ux, uy, uz, eps, wn, id, step, acc);
+    if (alive) alive = boundary_axis(R, 2, ck, oz, 0, nz, ux, uy, uz, eps, wn, id, step, acc);
+
+    // --- removal below e_min, energy to the cell's heat ---
+    if (alive && eps < (T)R.e_min) {
+      acc[L_STOPPED] += to_fixed(eps * wn * ledS);
+      acc[L_N + C_STOPPED] += 1;
+      atomic_add_i64(&R.ion_heat[heat_cell], to_fixed(eps * wn * (T)kHeatScale));
+      alive = false;
+    }
+    if (!alive) {
+      P.cell[i] = kDead;
+      continue;
+    }
+    P.cell[i] = pack_cell(ci, cj, ck);
+    ((T*)P.ox)[i] = ox; ((T*)P.oy)[i] = oy; ((T*)P.oz)[i] = oz;
+    ((T*)P.ux)[i] = ux; ((T*)P.uy)[i] = uy; ((T*)P.uz)[i] = uz;
+    ((T*)P.tau)[i] = tau;
+  }
+  block_flush<L_N, C_N>(acc, R.acc_led, R.events);
+}
+
+// ---------------------------------------------------------------------------
+// grid kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_zero_step(const RunDesc* __restrict__ runs,
+                                                      const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active) return;
+  const long long nn = R.nodes, tot = 3 * nn + R.cells;
+  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
+    if (t < 3 * nn) R.J[t / nn][t % nn] = 0;
+    else R.ion_heat[t - 3 * nn] = 0;
+  }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// E = eta_edge (curl B / mu0 - j_h) on the three edge families
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs,
+                                                const BlockMap* __restrict__ bmap, int sub) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active || sub >= R.n_sub || !(R.physics & PHYS_EVOLVE_E)) return;
+  const int nx = R.nx, ny = R.ny, nz = R.nz;
+  const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
+  const T* Bx = (const T*)R.B[0]; const T* By = (const T*)R.B[1]; const T* Bz = (const T*)R.B[2];
+  T* Ex = (T*)R.E[0]; T* Ey = (T*)R.E[1]; T* Ez = (T*)R.E[2];
+  const double* eta = R.eta;
+  const double inv_dx = 1.0 / R.dx, inv_mu0 = 1.0 / kMu0, ju = R.j_unit;
+  const long long nn = R.nodes;
+  auto ce = [&](int i, int j, int k) { return eta[i + nx * (j + ny * k)]; };
+  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < nn; t += (long long)bm.nb * kBlock) {
+    const int i = (int)(t % sx);
+    const long long q = t / sx;
+    const int j = (int)(q % (ny + 1));
+    const int k = (int)(q / (ny + 1));
+    const int idx = (int)t;
+    const int jm = clampi(j - 1, 0, ny - 1), jc = clampi(j, 0, ny - 1);
+    const int km = clampi(k - 1, 0, nz - 1), kc = clampi(k, 0, nz - 1);
+    const int im = clampi(i - 1, 0, nx - 1), ic = clampi(i, 0, nx - 1);
+    if (i < nx) {   // Ex at (i+1/2, j, k): dBz/dy - dBy/dz
+      const T bzp = j < ny ? Bz[idx] : -Bz[idx - sx];
+      const T bzm = j > 0 ? Bz[idx - sx] : -Bz[idx];
+      const T byp = k < nz ? By[idx] : -By[idx - sxy];
+      const T bym = k > 0 ? By[idx - sxy] : -By[idx];
+      const double curl = (double)((bzp - bzm) - (byp - bym)) * inv_dx;
+      const double ee = 0.25 * (ce(i, jm, km) + ce(i, jc, km) + ce(i, jm, kc) + ce(i, jc, kc));
+      Ex[idx] = (T)(ee * (curl * inv_mu0 - (double)R.J[0][idx] * ju));
+    }
+    if (j < ny) {   // Ey at (i, j+1/2, k): dBx/dz - dBz/dx
+      const T bxp = k < nz ? Bx[idx] : -Bx[idx - sxy];
+      const T bxm = k > 0 ? Bx[idx - sxy] : -Bx[idx];
+      const T bzp = i < nx ? Bz[idx] : -Bz[idx - 1];
+      const T bzm = i > 0 ? Bz[idx - 1] : -Bz[idx];
+      const double curl = (double)((bxp - bxm) - (bzp - bzm)) * inv_dx;
+      const double ee = 0.25 * (ce(im, j, km) + ce(ic, j, km) + ce(im, j, kc) + ce(ic, j, kc));
+      Ey[idx] = (T)(ee * (curl * inv_mu0 - (double)R.J[1][idx] * ju));
+    }
+    if (k < nz) {   // Ez at (i, j, k+1/2): dBy/dx - dBx/dy
+      const T byp = i < nx ? By[idx] : -By[idx - 1];
+      const T bym = i > 0 ? By[idx - 1] : -By[idx];
+      const T bxp = j < ny ? Bx[idx] : -Bx[idx - sx];
+      const T bxm = j > 0 ? Bx[idx - sx] : -Bx[idx];
+      const double curl = (double)((byp - bym) - (bxp - bxm)) * inv_dx;
+      const double ee = 0.25 * (ce(im, jm, k) + ce(ic, jm, k) + ce(im, jc, k) + ce(ic, jc, k));
+      Ez[idx] = (T)(ee * (curl * inv_mu0 - (double)R.J[2][idx] * ju));
+    }
+  }
+}
+
+// B -= (dt / n_sub) curl E on the three face families
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_faraday(const RunDesc* __restrict__ runs,
+                                                    const BlockMap* __restrict__ bmap, int sub) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active || sub >= R.n_sub || !(R.physics & PHYS_EVOLVE_B)) return;
+  const int nx = R.nx, ny = R.ny, nz = R.nz;
+  const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
+  const T* Ex = (const T*)R.E[0]; const T* Ey = (const T*)R.E[1]; const T* Ez = (const T*)R.E[2];
+  T* Bx = (T*)R.B[0]; T* By = (T*)R.B[1]; T* Bz = (T*)R.B[2];
+  const T h = (T)(R.dt / R.n_sub / R.dx);
+  const long long nn = R.nodes;
+  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < nn; t += (long long)bm.nb * kBlock) {
+    const int i = (int)(t % sx);
+    const long long q = t / sx;
+    const int j = (int)(q % (ny + 1));
+    const int k = (int)(q / (ny + 1));
+    const int idx = (int)t;
+    if (j < ny && k < nz)   // Bx: dEz/dy - dEy/dz
+      Bx[idx] -= h * ((Ez[idx + sx] - Ez[idx]) - (Ey[idx + sxy] - Ey[idx]));
+    if (i < nx && k < nz)   // By: dEx/dz - dEz/dx
+      By[idx] -= h * ((Ex[idx + sxy] - Ex[idx]) - (Ez[idx + 1] - Ez[idx]));
+    if (i < nx && j < ny)   // Bz: dEy/dx - dEx/dy
+      Bz[idx] -= h * ((Ey[idx + 1] - Ey[idx]) - (Ex[idx + sx] - Ex[idx]));
+  }
+}
+
+// Ohmic + collisional heating, exchange and resistivity of the solid cells (FP64)
+__global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ runs,
+                                                 const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active || !(R.physics & PHYS_HEAT)) return;
+  const int nx = R.nx, ny = R.ny;
+  const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
+  const int w = R.ix_hi - R.ix_lo;
+  const long long ns = (long long)w * ny * R.nz;
+  const double ju = 0.25 * R.j_unit, dV = R.dx * R.dx * R.dx;
+  const bool fixed = R.eta_fixed > 0.0;
+  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < ns; t += (long long)bm.nb * kBlock) {
+    const int i = R.ix_lo + (int)(t % w);
+    const long long q = t / w;
+    const int j = (int)(q % ny);
+    const int k = (int)(q / ny);
+    const int c = i + nx * (j + ny * k);
+    const int n = i + sx * j + sxy * k;
+    const long long* Jx = R.J[0]; const long long* Jy = R.J[1]; const long long* Jz = R.J[2];
+    const double jx = (double)(Jx[n] + Jx[n + sx] + Jx[n + sxy] + Jx[n + sx + sxy]) * ju;
+    const double jy = (double)(Jy[n] + Jy[n + 1] + Jy[n + sxy] + Jy[n + 1 + sxy]) * ju;
+    const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
+    double Te = R.Te[c], Ti = R.Ti[c], eta = R.eta[c];
+    heat_cell(Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)R.ion_heat[c] * R.heat_unit, R.dt, dV,
+              R.Z, R.A, R.rho, R.n_i, R.m_i, R.lambda1, R.lambda2, fixed);
+    R.Te[c] = Te;
+    R.Ti[c] = Ti;
+    R.eta[c] = eta;
+  }
+}
+
+__device__ __forceinline__ void kahan(double* s, double* c, double v) {
+  const double y = v - *c;
+  const double t = *s + y;
+  *c = (t - *s) - y;
+  *s = t;
+}
+
+// Per-step integer accumulators -> FP64 Kahan totals (fixed order), reset.
+__global__ __launch_bounds__(kBlock) void k_finalize(const RunDesc* __restrict__ runs,
+                                                     const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active) return;
+  const int nbin = R.nE * R.nth;
+  const long long nh = 2LL * nbin + 4;
+  for (long long b = (long long)bm.lb * kBlock + threadIdx.x; b < nh; b += (long long)bm.nb * kBlock) {
+    const long long x = R.acc_hist[b];
+    if (x == 0) continue;
+    bool is_energy;
+    if (b < nbin) is_energy = true;
+    else if (b < 2 * nbin) is_energy = false;
+    else is_energy = ((b - 2 * nbin) & 1) == 0;
+    kahan(&R.tot_hist[b], &R.tot_hist_c[b], (double)x * (is_energy ? R.led_unit : R.cnt_unit));
+    R.acc_hist[b] = 0;
+  }
+  if (bm.lb == 0 && threadIdx.x < L_N) {
+    const int l = threadIdx.x;
+    const long long x = R.acc_led[l];
+    const double v = (double)x * R.led_unit;
+    if (x != 0) kahan(&R.tot_led[l], &R.tot_led_c[l], v);
+    R.acc_led[l] = 0;
+    if (l == L_PHOTON_THR) {
+      const long long step = R.ctr->step;
+      if (step < R.series_len) R.series[step] = v;
+    }
+  }
+}
+
+// End of step: particle count, step counter, engine bookkeeping (one
+// single-thread block per run).
+__global__ void k_advance(const RunDesc* __restrict__ runs, const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const RunDesc& R = runs[bm.run];
+  Counters* c = R.ctr;
+  if (!c->active) return;
+  const long long n = c->n_total + inject_count(R, c->step);
+  c->n_total = n < R.capacity ? n : R.capacity;
+  c->step += 1;
+  if (c->steps_left > 0) {
+    c->steps_left -= 1;
+    if (c->steps_left == 0) c->active = 0;
+  }
+}
+
+// Kinetic energy and alive count: per-block partial sums (fixed tree order).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kinetic(const RunDesc* __restrict__ runs, int run) {
+  const RunDesc& R = runs[run];
+  const long long n = R.ctr->n_total;
+  const PartPtrs P = R.p[R.ctr->cur];
+  double s = 0.0, cnt = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    if (P.cell[i] == kDead) continue;
+    const T ux = ((const T*)P.ux)[i], uy = ((const T*)P.uy)[i], uz = ((const T*)P.uz)[i];
+    const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+    s += (double)((const T*)P.wn)[i] * (u2 / (1.0 + sqrt(1.0 + u2)));
+    cnt += 1.0;
+  }
+  __shared__ double sm[2][kBlock];
+  sm[0][threadIdx.x] = s;
+  sm[1][threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    R.red[2 * blockIdx.x] = sm[0][0];
+    R.red[2 * blockIdx.x + 1] = sm[1][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+template <typename T>
+static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
+  hipLaunchKernelGGL(k_zero_step, dim3(L.zero.nb), dim3(kBlock), 0, s, L.runs, L.zero.map);
+  hipLaunchKernelGGL(k_inject<T>, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
+  if (L.ev_start) (void)hipEventRecord(L.ev_start, s);
+  hipLaunchKernelGGL(k_particle<T>, dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+  if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
+  for (int k = 0; k < max_sub; ++k) {
+    hipLaunchKernelGGL(k_ohm<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);
+    hipLaunchKernelGGL(k_faraday<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);
+  }
+  hipLaunchKernelGGL(k_heat, dim3(L.cells.nb), dim3(kBlock), 0, s, L.runs, L.cells.map);
+  hipLaunchKernelGGL(k_finalize, dim3(L.fin.nb), dim3(kBlock), 0, s, L.runs, L.fin.map);
+  hipLaunchKernelGGL(k_advance, dim3(L.adv.nb), dim3(64), 0, s, L.runs, L.adv.map);
+}
+
+void launch_step(const LaunchSet& L, hipStream_t s, int precision, int max_sub) {
+  if (precision == 0) launch_step_t<double>(L, s, max_sub);
+  else launch_step_t<float>(L, s, max_sub);
+}
+
+void launch_kinetic(const RunDesc* runs, int run, int nblocks, hipStream_t s, int precision) {
+  if (precision == 0) hipLaunchKernelGGL(k_kinetic<double>, dim3(nblocks), dim3(kBlock), 0, s, runs, run);
+  else hipLaunchKernelGGL(k_kinetic<float>, dim3(nblocks), dim3(kBlock), 0, s, runs, run);
+}
+
+}  // namespace hyb

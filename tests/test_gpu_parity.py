@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Per-particle bars: FP64 1e-10, FP32-mixed 1e-5 (positions as |dx|/dx,
+momenta norm-relative, optical depth relative).  The coupled particle-field
+system is chaotic (a 1e-13 perturbation reaches O(1) within ~35 steps at the
+small-config density), so per-particle parity is checked one step at a time
+from an identical state, over short free runs, and over whole runs with the
+field feedback switched off; aggregates of one step are checked at 1e-4 (FP32)
+and tighter in FP64.  FP32 particles whose discrete decision flips (emission,
+removal, reflux) are excluded and counted.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import OracleRun
+from oracle import run as OR
+
+from parity_util import (field_rel, gpu_from_oracle, oracle_at, particle_errors, rel,
+                         small_config)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2107_01723_amd as P
+    P.check_abi()
+    return P
+
+
+# --------------------------------------------------------------------------
+def _compare_step(P, cfg, srcs, n_pre, tol_p, tol_grid, max_flip_frac=0.0, brem_boost=None):
+    """Oracle to step n_pre; same state into the GPU; one step on both;
+    compare particles, current, heat, fields, temperatures, ledger and tallies."""
+    if brem_boost:
+        cfg = dict(cfg, brem_boost=brem_boost)
+    ora = oracle_at(cfg, srcs, n_pre)
+    run = gpu_from_oracle(P, cfg, srcs, ora)
+    led0 = dict(ora.ledger)
+    h0 = ora.hist_E.copy()
+    hn0 = ora.hist_N.copy()
+    ora.step()
+    run.step(1)
+    got, ref = run.get_state(), ora.state()
+    err, only = particle_errors(got, ref, cfg["dx"])
+    n = len(err["ids"])
+    assert n > 100
+    # particles whose discrete path differs
+    bad = (err["p"] > tol_p) | (err["pos"] > tol_p) | (err["tau"] > tol_p)
+    nflip = int(np.sum(bad)) + len(only)
+    print(f"  n={n} max|dp|={err['p'].max():.2e} max|dx|/dx={err['pos'].max():.2e} "
+          f"max|dtau|={err['tau'].max():.2e} flips={nflip}", flush=True)
+    assert nflip <= max_flip_frac * n, (nflip, only[:10])
+    good = ~bad
+    assert err["p"][good].max() <= tol_p and err["pos"][good].max() <= tol_p
+    assert err["w"].max() <= tol_p
+    # grid quantities of this step
+    assert field_rel(got["j"], ref["j"]) <= tol_grid, field_rel(got["j"], ref["j"])
+    assert rel(got["ion_heat"], ref["ion_heat"]) <= tol_grid
+    assert field_rel(got["E"], ref["E"]) <= tol_grid
+    assert field_rel(got["B"], ref["B"]) <= tol_grid
+    s = ora.solid
+    assert rel(got["Te"][s], ref["Te"][s]) <= tol_grid
+    assert rel(got["Ti"][s], ref["Ti"][s]) <= tol_grid
+    assert rel(got["eta"][s], ref["eta"][s]) <= tol_grid
+    # aggregates of the step.  Ledger sums are 64-bit fixed point with one
+    # unit (LSB) = w_ref m c^2 / 2^32 per contribution, so each term may differ
+    # by the rounding of its contributions; in FP32 also by the rounding of the
+    # particle energies, bounded against the step's energy throughput.
+    t = run.tally()
+    lsb = run.info()["w_ref"] * 8.1871057769e-14 / 2.0 ** 32
+    dled = {k: ora.ledger[k] - led0[k] for k in led0}
+    through = sum(abs(v) for k, v in dled.items() if k != "residual")
+    fp32 = cfg["precision"] == W.FP32_MIXED
+    for k, v in dled.items():
+        if k == "residual":
+            assert abs(t["ledger"][k]) <= (1e-5 if fp32 else 1e-12) * through + 4 * n * lsb, (k, t["ledger"][k])
+            continue
+        tol = (1e-4 * abs(v) + 1e-6 * through) if fp32 else 1e-8 * abs(v)
+        assert abs(t["ledger"][k] - v) <= tol + 4 * n * lsb, (k, t["ledger"][k], v)
+    dh = ora.hist_E - h0
+    if np.sum(dh) > 0:
+        l1 = np.sum(np.abs(t["hist_E"] - dh)) / np.sum(np.abs(dh))
+        assert l1 <= max(tol_grid, 1e-8), l1
+        l1n = np.sum(np.abs(t["hist_N"] - (ora.hist_N - hn0))) / np.sum(np.abs(ora.hist_N - hn0))
+        assert l1n <= max(tol_grid, 1e-8), l1n
+    run.close()
+    return n, nflip
+
+
+@pytest.mark.parametrize("n_pre", [1, 37, 120])
+def test_step_fp64_small(P, n_pre):
+    """FP64, all physics: one step from identical state (during and after injection)."""
+    cfg, srcs, _ = small_config(10000, brem_boost=10.0)
+    _compare_step(P, cfg, srcs, n_pre, 1e-10, 1e-10)
+
+
+def test_step_fp64_paper_reflux_ragged(P):
+    """Paper reflux mode (momentum loss), escape energy inside the spectrum,
+    odd grid dimensions (ragged tails of every launch) and two sources."""
+    cfg, srcs, _ = small_config(3001, nx=27, ny=13, nz=11, x_lo=3e-6, x_hi=24e-6,
+                                reflux_ke_frac=0.0, I0=W.intensity_wcm2(1e19), brem_boost=10.0)
+    srcs[0].update(y0=6.5e-6, z0=5.5e-6, r_fwhm=4e-6, T_hot=2.0 * W.MEV)
+    s2 = dict(srcs[0], n_macro=777, t_start=3e-13, t_end=6e-13, T_hot=0.5 * W.MEV)
+    cfg["max_particles"] = 4000
+    _compare_step(P, cfg, [srcs[0], s2], 45, 1e-10, 1e-10)
+
+
+def test_step_fp32_mixed(P):
+    """FP32-mixed from the oracle's FP64 state: per particle 1e-5 with the flips
+    counted, step aggregates 1e-4."""
+    cfg, srcs, _ = small_config(10000, precision=W.FP32_MIXED, brem_boost=10.0)
+    n, nflip = _compare_step(P, cfg, srcs, 60, 1e-5, 1e-4, max_flip_frac=1e-3)
+
+
+@pytest.mark.parametrize("nsteps,wscale", [(2, 1.0), (10, 0.01)])
+def test_free_run_fp64(P, nsteps, wscale):
+    """FP64 free-running from an identical state with every field feedback on:
+    every particle within 1e-10.  At full density the coupling is chaotic and
+    amplifies the 2^-41 rounding of the fixed-point current (~1e-12 of E) to
+    ~2e-10 within 3 steps, so that run takes 2 steps; at 1/100 of the weight
+    (fields 100x weaker) it takes 10."""
+    cfg, srcs, _ = small_config(10000, brem_boost=10.0)
+    if wscale != 1.0:
+        from oracle import particles as PT
+        srcs[0]["weight"] = PT.default_weight(srcs[0], cfg["I0"]) * wscale
+    ora = oracle_at(cfg, srcs, 50)
+    run = gpu_from_oracle(P, cfg, srcs, ora)
+    ora.run(nsteps)
+    run.step(nsteps)
+    err, only = particle_errors(run.get_state(), ora.state(), cfg["dx"])
+    print(f"  max|dp|={err['p'].max():.2e} max|dx|/dx={err['pos'].max():.2e}", flush=True)
+    assert not only
+    assert err["p"].max() < 1e-10 and err["pos"].max() < 1e-10 and err["tau"].max() < 1e-10
+    run.close()
+
+
+def test_whole_run_fp64_no_field_feedback(P):
+    """The whole small workload (1e4 electrons, 200 steps) with the push in
+    fields switched off, so particles are independent: every particle, the
+    current, heat, temperatures, ledger and tallies match."""
+    cfg, srcs, steps = small_config(10000, brem_boost=10.0, physics=W.PHYS_ALL & ~W.PHYS_FIELDS)
+    ora = oracle_at(cfg, srcs, steps)
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(steps)
+    got, ref = run.get_state(), ora.state()
+    err, only = particle_errors(got, ref, cfg["dx"])
+    print(f"  alive={len(err['ids'])} max|dp|={err['p'].max():.2e} "
+          f"max|dx|/dx={err['pos'].max():.2e}", flush=True)
+    assert not only
+    assert err["p"].max() < 1e-10 and err["pos"].max() < 1e-10 and err["tau"].max() < 1e-10
+    s = ora.solid
+    assert rel(got["Te"][s], ref["Te"][s]) < 1e-10
+    assert rel(got["eta"][s], ref["eta"][s]) < 1e-10
+    t = run.tally()
+    for k in ("injected", "ionisation", "rad_discrete", "reflux", "stopped", "escaped", "photon_thr"):
+        assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-8, abs=1e-12 * ora.ledger["injected"]), k
+    assert np.sum(np.abs(t["hist_E"] - ora.hist_E)) / np.sum(ora.hist_E) < 1e-8
+    assert rel(t["series"], ora.series) < 1e-8
+    assert t["conversion"] == pytest.approx(ora.conversion_efficiency(), rel=1e-8)
+    assert t["counters"]["n_emitted"] == ora.counters["n_emitted"]
+    assert t["counters"]["n_reflux"] == ora.counters["n_reflux"]
+    run.close()
+
+
+def test_whole_run_fp32_no_field_feedback(P):
+    """FP32-mixed whole run (200 steps) without field feedback against the FP64
+    oracle.  FP32 rounding accumulates along each trajectory, so per-particle
+    errors are reported, not bounded; the conversion efficiency must agree within
+    1e-4, the histograms within 1e-3 in L1 (a handful of photons change bin),
+    and every physical ledger term within 1e-3."""
+    cfg, srcs, steps = small_config(10000, precision=W.FP32_MIXED, brem_boost=10.0,
+                                    physics=W.PHYS_ALL & ~W.PHYS_FIELDS)
+    ora = oracle_at(cfg, srcs, steps)
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(steps)
+    got, ref = run.get_state(), ora.state()
+    err, only = particle_errors(got, ref, cfg["dx"])
+    t = run.tally()
+    eff_rel = abs(t["conversion"] - ora.conversion_efficiency()) / ora.conversion_efficiency()
+    h_l1 = np.sum(np.abs(t["hist_E"] - ora.hist_E)) / np.sum(ora.hist_E)
+    pct = np.percentile(err["p"], [50, 90, 99])
+    print(f"  alive={len(err['ids'])} only-one-side={len(only)} |dp| p50/p90/p99={pct} "
+          f"eff rel={eff_rel:.2e} hist L1={h_l1:.2e}", flush=True)
+    assert len(only) < 0.01 * len(err["ids"])
+    assert eff_rel < 1e-4
+    assert h_l1 < 1e-3
+    for k in ("injected", "ionisation", "rad_discrete", "reflux", "photon_thr"):
+        assert abs(t["ledger"][k] - ora.ledger[k]) <= 1e-3 * abs(ora.ledger[k]), k
+    run.close()
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_ledger_closes_on_gpu(P, precision):
+    """injected = kinetic + losses - gains within 1e-6 after the full small
+    workload with every physics process and field feedback on."""
+    cfg, srcs, steps = small_config(10000, precision=precision, brem_boost=10.0)
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(steps)
+    t = run.tally()
+    L = t["ledger"]
+    out = (t["kinetic"] + L["field_loss"] - L["field_gain"] + L["ionisation"] + L["stopped"]
+           + L["rad_discrete"] + L["rad_subcut"] + L["escaped"] + L["reflux"] + L["residual"])
+    clo = abs(L["injected"] - out) / L["injected"]
+    res = abs(L["residual"]) / L["injected"]
+    print(f"  closure={clo:.2e} rounding residual={res:.2e} conversion={t['conversion']:.4f} "
+          f"alive={t['n_alive']}", flush=True)
+    assert clo < 1e-6
+    assert res < (1e-5 if precision == W.FP32_MIXED else 1e-12)
+    run.close()
+
+
+def test_table_matches_oracle(P):
+    cfg, srcs, _ = small_config(100)
+    run = P.Run(cfg)
+    X, S, U = run.table()
+    ora = OracleRun(cfg)
+    assert np.max(np.abs(X - ora.table.X)) < 1e-14
+    assert np.max(np.abs(S - ora.table.SIG)) <= 1e-14 * np.max(ora.table.SIG)
+    assert np.max(np.abs(U - ora.table.SUB)) <= 1e-14 * np.max(ora.table.SUB)
+    info = run.info()
+    assert info["n_sub"] == ora.n_sub
+    assert info["eps_esc"] == pytest.approx(ora.eps_esc, rel=1e-14)
+    run.close()
+
+
+def test_resistive_mode_decay_gpu(P):
+    """No particles, uniform eta: B_z = sin(kx x) sin(ky y) decays by the exact
+    discrete factor per step (same closed form the oracle is pinned to)."""
+    cfg = W.base_config(nx=24, ny=20, nz=9, x_lo=0.0, x_hi=24e-6, eta_fixed=2e-7, n_sub=1,
+                        physics=W.PHYS_EVOLVE_E | W.PHYS_EVOLVE_B, max_particles=16, series_len=4)
+    run = P.Run(cfg)
+    nx, ny, nz, dx, dt = 24, 20, 9, 1e-6, cfg["dt"]
+    kx, ky = 2 * math.pi / (nx * dx), math.pi / (ny * dx)
+    xi = (np.arange(nx + 1) + 0.5) * dx
+    yj = (np.arange(ny + 1) + 0.5) * dx
+    mode = np.sin(kx * xi)[:, None, None] * np.sin(ky * yj)[None, :, None] * np.ones(nz + 1)
+    mode[nx] = 0
+    mode[:, ny] = 0
+    z = np.zeros_like(mode)
+    run.set_state(dict(pos=np.zeros((0, 3)), p=np.zeros((0, 3)), w=np.zeros(0), tau=np.zeros(0),
+                       ids=np.zeros(0, np.uint32), E=(z, z, z), B=(z, z, 50.0 * mode)))
+    g = 1 - 2e-7 * dt / 1.25663706212e-6 * 4 / dx ** 2 * (math.sin(kx * dx / 2) ** 2 + math.sin(ky * dx / 2) ** 2)
+    run.step(9)
+    B = run.get_state()["B"]
+    assert np.max(np.abs(B[2] - 50.0 * mode * g ** 9)) < 1e-10 * 50
+    assert np.max(np.abs(B[0])) < 1e-10 and np.max(np.abs(B[1])) < 1e-10
+    run.close()
+
+
+def test_bitwise_reproducible_and_graph_replay(P):
+    """Two runs give bit-identical results; a run replayed as a HIP graph gives
+    the same bits as direct launches (several replays, host syncs between)."""
+    cfg, srcs, _ = small_config(3000, precision=W.FP32_MIXED, brem_boost=10.0)
+    outs = []
+    for graph in (False, False, True):
+        run = P.Run(cfg)
+        run.inject(srcs[0])
+        if graph:
+            run.use_graph(True)
+        for _ in range(4):
+            run.step(15)
+            run.tally()
+        t = run.tally()
+        st = run.get_state()
+        o = np.argsort(st["ids"])
+        outs.append((t, st["p"][o], st["pos"][o]))
+        run.close()
+    for t, p, x in outs[1:]:
+        assert np.array_equal(p, outs[0][1]) and np.array_equal(x, outs[0][2])
+        assert np.array_equal(t["hist_E"], outs[0][0]["hist_E"])
+        assert t["ledger"] == outs[0][0]["ledger"]

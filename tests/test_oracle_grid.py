@@ -84,14 +84,14 @@ def test_deposit_gather_adjoint_and_sum_rule():
     shape = (nx + 1, ny + 1, nz + 1)
     E = tuple(rng.normal(size=shape) for _ in range(3))
     j = tuple(np.zeros(shape) for _ in range(3))
-    PT.deposit(j, pos, vel, w, dx, dims)
-    Ep, _ = PT.gather(pos, E, E, dx, dims)
+    PT.deposit(j, pos / dx, vel, w, dx, dims)
+    Ep, _ = PT.gather(pos / dx, E, E, dims)
     lhs = np.sum(PT.Q_E * w[:, None] * vel * Ep)
     rhs = sum(np.sum(j[c] * E[c]) for c in range(3)) * dx ** 3
     assert lhs == pytest.approx(rhs, rel=1e-12)
     inner = np.all((pos / dx > 0.5) & (pos / dx < np.array(dims) - 0.5), axis=1)
     j2 = tuple(np.zeros(shape) for _ in range(3))
-    PT.deposit(j2, pos[inner], vel[inner], w[inner], dx, dims)
+    PT.deposit(j2, pos[inner] / dx, vel[inner], w[inner], dx, dims)
     for c in range(3):
         assert np.sum(j2[c]) * dx ** 3 == pytest.approx(np.sum(PT.Q_E * w[inner] * vel[inner, c]), rel=1e-12)
 

@@ -156,8 +156,8 @@ def test_davies_scatter_statistics():
     d = rng.normal(size=(n, 3))
     d /= np.linalg.norm(d, axis=1)[:, None]
     r = _one_particle_run(pos, d * pm, R.PHYS_SCATTER, dt=1e-15)
-    r.box_lo[:] = -1.0
-    r.box_hi[:] = 1.0
+    r.box_lo[:] = -1e12
+    r.box_hi[:] = 1e12
     p_before = r.p.copy()
     r.step()
     cosang = np.sum(p_before * r.p, axis=1) / (pm * np.linalg.norm(r.p, axis=1))
@@ -262,7 +262,8 @@ def test_low_energy_removal_heats_cell():
 # --------------------------------------------------------------------------
 def test_injection_samplers():
     src = W.source(n_macro=200000, r_fwhm=5e-6, T_hot=2.0 * MEV, half_angle=math.radians(30))
-    pos, p, w, tau, ids = PT.inject(src, 0, 200000, 0, 11, 2e-6, 1e24)
+    X, p, w, tau, ids = PT.inject(src, 0, 200000, 0, 11, 2, 1e-6, 1e24)
+    pos = X * 1e-6
     eps = PT.kinetic(p)
     assert np.mean(eps) == pytest.approx(2.0 * MEV, rel=0.01)
     r = np.hypot(pos[:, 1] - src["y0"], pos[:, 2] - src["z0"])
@@ -277,7 +278,7 @@ def test_injection_samplers():
     cm = math.cos(math.radians(30))
     assert stats.kstest((1 - ct) / (1 - cm), "uniform").pvalue > 1e-3
     assert stats.kstest(tau, "expon").pvalue > 1e-3
-    assert np.all(pos[:, 0] == 2e-6)
+    assert np.all(X[:, 0] == 2.0)
 
 
 def test_injection_schedule_counts():
