@@ -35,7 +35,7 @@ struct Layout {
   size_t off_part[2][10];
   size_t off_tabX, off_tabSIG, off_tabSUB;
   size_t off_acc_led, off_acc_hist, off_events, off_tot_led, off_tot_led_c, off_tot_hist, off_tot_hist_c;
-  size_t off_series, off_ctr, off_src, off_sort_cnt, off_sort_blk, off_red, off_desc;
+  size_t off_series, off_ctr, off_src, off_tile_cnt, off_tile_start, off_tile_cursor, off_scan_blk, off_red, off_desc;
   size_t total;
 };
 
@@ -74,8 +74,12 @@ Layout make_layout(const hyb_config& c) {
   L.off_series = take((size_t)std::max(1, c.series_len) * 8);
   L.off_ctr = take(sizeof(Counters));
   L.off_src = take(sizeof(SourceDesc) * kMaxSources);
-  L.off_sort_cnt = take((cells + 1) * 4);
-  L.off_sort_blk = take(65536 * 4);
+  const size_t ntiles = (size_t)((c.nx + kTile - 1) / kTile) * ((c.ny + kTile - 1) / kTile) *
+                        ((c.nz + kTile - 1) / kTile);
+  L.off_tile_cnt = take(ntiles * 4);
+  L.off_tile_start = take(ntiles * 4);
+  L.off_tile_cursor = take(ntiles * 4);
+  L.off_scan_blk = take(((ntiles + kScanTile - 1) / kScanTile) * 4);
   L.off_red = take(2 * kRedBlocks * 8);
   L.off_desc = take(sizeof(RunDesc));
   L.total = o;
@@ -245,6 +249,11 @@ static void fill_desc(hyb_run* r) {
   h.Z = c.Z; h.A = c.A; h.rho = c.rho; h.n_i = n_i; h.m_i = c.A * kAmu;
   h.lambda1 = c.lambda1; h.lambda2 = c.lambda2; h.eta_fixed = c.eta_fixed;
   h.sort_every = c.sort_every;
+  h.ntx = (c.nx + kTile - 1) / kTile;
+  h.nty = (c.ny + kTile - 1) / kTile;
+  h.ntz = (c.nz + kTile - 1) / kTile;
+  h.ntiles = h.ntx * h.nty * h.ntz;
+  h.scan_nblk = (h.ntiles + kScanTile - 1) / kScanTile;
   set_units(h, r->w_ref > 0 ? r->w_ref : 1.0);
   r->solid_cells = (int64_t)(h.ix_hi - h.ix_lo) * c.ny * c.nz;
 }
@@ -283,8 +292,10 @@ static void point_desc(hyb_run* r) {
   h.series = (double*)(b + L.off_series);
   h.ctr = (Counters*)(b + L.off_ctr);
   h.src = (const SourceDesc*)(b + L.off_src);
-  h.sort_cnt = (unsigned*)(b + L.off_sort_cnt);
-  h.sort_blk = (unsigned*)(b + L.off_sort_blk);
+  h.tile_cnt = (unsigned*)(b + L.off_tile_cnt);
+  h.tile_start = (unsigned*)(b + L.off_tile_start);
+  h.tile_cursor = (unsigned*)(b + L.off_tile_cursor);
+  h.scan_blk = (unsigned*)(b + L.off_scan_blk);
   h.red = (double*)(b + L.off_red);
 }
 
@@ -309,7 +320,7 @@ static void dev_free(const hyb_device& d, void* p) {
 
 // Launch plans of a batch.  Particle plans get a multiple of 8 blocks per run
 // so the XCD split inside the particle kernel stays aligned.
-struct PlanSpec { std::vector<BlockMap> zero, inject, particle, grid, cells, fin, adv; };
+struct PlanSpec { std::vector<BlockMap> zero, inject, particle, grid, cells, fin, adv, scan, scan1; };
 
 static void add_run_plans(PlanSpec& ps, int run, const RunDesc& h) {
   auto add = [&](std::vector<BlockMap>& v, int nb) {
@@ -328,6 +339,8 @@ static void add_run_plans(PlanSpec& ps, int run, const RunDesc& h) {
   add(ps.cells, clampi((sc + 255) / 256, 1, 4096));
   add(ps.fin, clampi((2LL * h.nE * h.nth + 4 + 255) / 256, 1, 256));
   add(ps.adv, 1);
+  add(ps.scan, h.scan_nblk);
+  add(ps.scan1, 1);
 }
 
 static hyb_status upload_plans(hyb_run* owner, hipStream_t s, const PlanSpec& ps, LaunchSet& L,
@@ -335,7 +348,8 @@ static hyb_status upload_plans(hyb_run* owner, hipStream_t s, const PlanSpec& ps
   std::vector<BlockMap> all;
   std::vector<std::pair<Plan*, const std::vector<BlockMap>*>> parts = {
       {&L.zero, &ps.zero}, {&L.inject, &ps.inject}, {&L.particle, &ps.particle}, {&L.grid, &ps.grid},
-      {&L.cells, &ps.cells}, {&L.fin, &ps.fin}, {&L.adv, &ps.adv}};
+      {&L.cells, &ps.cells}, {&L.fin, &ps.fin}, {&L.adv, &ps.adv}, {&L.scan, &ps.scan},
+      {&L.scan1, &ps.scan1}};
   std::vector<size_t> offs;
   for (auto& p : parts) {
     offs.push_back(all.size());
@@ -497,6 +511,7 @@ static hyb_status ensure_single_plans(hyb_run* r) {
   add_run_plans(ps, 0, r->h);
   r->L.runs = r->d_desc;
   r->L.nruns = 1;
+  r->L.sort = r->h.sort_every > 0;
   return upload_plans(r, r->stream, ps, r->L, &r->d_maps, &r->maps_bytes, r->dev);
 }
 
@@ -931,6 +946,8 @@ static hyb_status eng_rebuild(hyb_engine* e, int p) {
   if (nres == 0) return HYB_OK;
   e->L[p].runs = e->d_descs[p];
   e->L[p].nruns = e->max_runs;
+  for (int s = 0; s < e->max_runs; ++s)
+    if (e->slots[p][s] && e->slots[p][s]->h.sort_every > 0) e->L[p].sort = true;
   hyb_run tmp;
   hyb_status st = upload_plans(&tmp, e->stream, ps, e->L[p], &e->d_maps[p], &e->maps_bytes[p], e->dev);
   if (st != HYB_OK) return eng_fail(e, st, tmp.err);

@@ -131,13 +131,24 @@ struct RunDesc {
   double* tot_led; double* tot_led_c;     // Kahan sum and compensation
   double* tot_hist; double* tot_hist_c;
   double* series;
-  // cell sort
-  int sort_every;
-  unsigned* sort_cnt;       // [cells + 1]
-  unsigned* sort_blk;       // block sums of the scan
-  int sort_nblk;
+  // counting sort of the particles by tile of 4x4x4 cells
+  int sort_every;           // 0: never; S: after the particle kernel of every S-th step
+  int ntx, nty, ntz, ntiles;
+  int scan_nblk;            // scan blocks of kScanTile tiles
+  unsigned* tile_cnt;       // [ntiles] electrons per destination tile
+  unsigned* tile_start;     // [ntiles] exclusive scan of tile_cnt
+  unsigned* tile_cursor;    // [ntiles] scatter cursors
+  unsigned* scan_blk;       // [scan_nblk] block sums
   double* red;              // per-block partial sums for host-side reductions
 };
+
+constexpr int kTile = 4;           // tile edge in cells
+constexpr int kScanTile = 1024;    // tiles per scan block
+
+// Does the step `step` end with a tile sort?
+__host__ __device__ __forceinline__ bool sort_step(int sort_every, long long step) {
+  return sort_every > 0 && (step + 1) % sort_every == 0;
+}
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
 struct U4 { uint32_t x, y, z, w; };

@@ -21,7 +21,8 @@ struct LaunchSet {
   const RunDesc* runs = nullptr;   // device array [nruns]
   int nruns = 0;
   Plan zero, inject, particle, grid, cells, fin, adv;
-  Plan sort_cnt, sort_scan, sort_scatter;
+  Plan scan, scan1;   // tile-count scan: one block per kScanTile tiles; one block per run
+  bool sort = false;                                  // some run sorts its particles
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
 };
 

@@ -173,23 +173,6 @@ __device__ __forceinline__ T gather8(const T* __restrict__ F, int sx, int sxy, c
   return az.w0 * (ay.w0 * v00 + ay.w1 * v10) + az.w1 * (ay.w0 * v01 + ay.w1 * v11);
 }
 
-template <typename T>
-__device__ __forceinline__ void deposit8(long long* __restrict__ J, int sx, int sxy, const Axis<T>& ax,
-                                         const Axis<T>& ay, const Axis<T>& az, T amp) {
-  const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
-  const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
-  const T a00 = amp * az.w0 * ay.w0, a10 = amp * az.w0 * ay.w1;
-  const T a01 = amp * az.w1 * ay.w0, a11 = amp * az.w1 * ay.w1;
-  atomic_add_i64(&J[r00 + ax.i0], to_fixed(a00 * ax.w0));
-  atomic_add_i64(&J[r00 + ax.i1], to_fixed(a00 * ax.w1));
-  atomic_add_i64(&J[r10 + ax.i0], to_fixed(a10 * ax.w0));
-  atomic_add_i64(&J[r10 + ax.i1], to_fixed(a10 * ax.w1));
-  atomic_add_i64(&J[r01 + ax.i0], to_fixed(a01 * ax.w0));
-  atomic_add_i64(&J[r01 + ax.i1], to_fixed(a01 * ax.w1));
-  atomic_add_i64(&J[r11 + ax.i0], to_fixed(a11 * ax.w0));
-  atomic_add_i64(&J[r11 + ax.i1], to_fixed(a11 * ax.w1));
-}
-
 // ---------------------------------------------------------------------------
 // reflux / escape on one axis (Sec. II.A).  Returns false if the electron
 // leaves the simulation.
@@ -250,6 +233,142 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 }
 
 // ---------------------------------------------------------------------------
+// LDS staging of one chunk of particles.  Particles sorted by tile arrive in
+// chunks of kBlock; the chunk's home tile is the smallest tile among its
+// electrons.  Deposits of electrons inside the home tile go to LDS integer
+// accumulators covering the 6x6x6 nodes that tile's stencils can reach, its
+// 4x4x4 cells of collisional heat, and the 5x5x5 tiles around it that its
+// electrons can move to in one step; everything else falls back to global
+// atomics.  The LDS sums are flushed with one atomic per non-zero entry.
+// ---------------------------------------------------------------------------
+constexpr int kHalo = kTile + 2;              // node span of a tile's stencils
+constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
+constexpr int kNb = 5;                        // destination tiles: home +-2 per axis
+constexpr int kNbN = kNb * kNb * kNb;         // 125
+
+struct ChunkLds {
+  long long J[3][kHaloN];
+  long long heat[kTile * kTile * kTile];
+  unsigned cnt[kNbN];
+  int home;
+};
+
+struct Home {
+  int ok;                 // chunk has an alive electron
+  int tx, ty, tz;         // home tile
+  int bx, by, bz;         // first node of the home tile's halo
+};
+
+__device__ __forceinline__ int tile_of(const RunDesc& R, int i, int j, int k) {
+  return (i >> 2) + R.ntx * ((j >> 2) + R.nty * (k >> 2));
+}
+
+__device__ __forceinline__ Home make_home(const RunDesc& R, int t) {
+  Home h;
+  h.ok = t != 0x7FFFFFFF;
+  if (!h.ok) t = 0;
+  h.tx = t % R.ntx;
+  const int q = t / R.ntx;
+  h.ty = q % R.nty;
+  h.tz = q / R.nty;
+  h.bx = kTile * h.tx - 1;
+  h.by = kTile * h.ty - 1;
+  h.bz = kTile * h.tz - 1;
+  return h;
+}
+
+// bin of tile (tx,ty,tz) in the 5x5x5 neighbourhood of home, or -1
+__device__ __forceinline__ int nb_bin(const Home& h, int tx, int ty, int tz) {
+  const int dx = tx - h.tx + 2, dy = ty - h.ty + 2, dz = tz - h.tz + 2;
+  if ((unsigned)dx >= (unsigned)kNb || (unsigned)dy >= (unsigned)kNb || (unsigned)dz >= (unsigned)kNb) return -1;
+  return dx + kNb * (dy + kNb * dz);
+}
+
+__device__ __forceinline__ void lds_clear(ChunkLds& L) {
+  long long* J = &L.J[0][0];
+  for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) J[t] = 0;
+  if (threadIdx.x < kTile * kTile * kTile) L.heat[threadIdx.x] = 0;
+  if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) L.home = 0x7FFFFFFF;
+}
+
+__device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds& L, const Home& h, bool count) {
+  if (!h.ok) return;
+  const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
+  for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
+    const long long v = (&L.J[0][0])[t];
+    if (v == 0) continue;
+    const int c = t / kHaloN, l = t % kHaloN;
+    const int i = h.bx + l % kHalo, j = h.by + (l / kHalo) % kHalo, k = h.bz + l / (kHalo * kHalo);
+    if (i < 0 || j < 0 || k < 0 || i > R.nx || j > R.ny || k > R.nz) continue;
+    atomic_add_i64(&R.J[c][i + sx * j + sxy * k], v);
+  }
+  if (threadIdx.x < kTile * kTile * kTile) {
+    const long long v = L.heat[threadIdx.x];
+    const int l = threadIdx.x;
+    const int i = kTile * h.tx + (l & 3), j = kTile * h.ty + ((l >> 2) & 3), k = kTile * h.tz + (l >> 4);
+    if (v != 0 && i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.ion_heat[i + R.nx * (j + R.ny * k)], v);
+  }
+  if (count && threadIdx.x < kNbN) {
+    const unsigned v = L.cnt[threadIdx.x];
+    const int l = threadIdx.x;
+    const int tx = h.tx + l % kNb - 2, ty = h.ty + (l / kNb) % kNb - 2, tz = h.tz + l / (kNb * kNb) - 2;
+    if (v != 0 && tx >= 0 && ty >= 0 && tz >= 0 && tx < R.ntx && ty < R.nty && tz < R.ntz)
+      atomicAdd(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], v);
+  }
+}
+
+// deposit of one current component: 8 corners to LDS (home tile) or HBM
+template <typename T>
+__device__ __forceinline__ void deposit8(long long* __restrict__ J, long long* __restrict__ Js, bool local,
+                                         const Home& h, int sx, int sxy, const Axis<T>& ax,
+                                         const Axis<T>& ay, const Axis<T>& az, T amp) {
+  const T a00 = amp * az.w0 * ay.w0, a10 = amp * az.w0 * ay.w1;
+  const T a01 = amp * az.w1 * ay.w0, a11 = amp * az.w1 * ay.w1;
+  const long long v[8] = {to_fixed(a00 * ax.w0), to_fixed(a00 * ax.w1), to_fixed(a10 * ax.w0), to_fixed(a10 * ax.w1),
+                          to_fixed(a01 * ax.w0), to_fixed(a01 * ax.w1), to_fixed(a11 * ax.w0), to_fixed(a11 * ax.w1)};
+  if (local) {
+    const int i0 = ax.i0 - h.bx, i1 = ax.i1 - h.bx;
+    const int j0 = (ay.i0 - h.by) * kHalo, j1 = (ay.i1 - h.by) * kHalo;
+    const int k0 = (az.i0 - h.bz) * kHalo * kHalo, k1 = (az.i1 - h.bz) * kHalo * kHalo;
+    atomicAdd((unsigned long long*)&Js[i0 + j0 + k0], (unsigned long long)v[0]);
+    atomicAdd((unsigned long long*)&Js[i1 + j0 + k0], (unsigned long long)v[1]);
+    atomicAdd((unsigned long long*)&Js[i0 + j1 + k0], (unsigned long long)v[2]);
+    atomicAdd((unsigned long long*)&Js[i1 + j1 + k0], (unsigned long long)v[3]);
+    atomicAdd((unsigned long long*)&Js[i0 + j0 + k1], (unsigned long long)v[4]);
+    atomicAdd((unsigned long long*)&Js[i1 + j0 + k1], (unsigned long long)v[5]);
+    atomicAdd((unsigned long long*)&Js[i0 + j1 + k1], (unsigned long long)v[6]);
+    atomicAdd((unsigned long long*)&Js[i1 + j1 + k1], (unsigned long long)v[7]);
+  } else {
+    const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
+    const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
+    atomic_add_i64(&J[r00 + ax.i0], v[0]);
+    atomic_add_i64(&J[r00 + ax.i1], v[1]);
+    atomic_add_i64(&J[r10 + ax.i0], v[2]);
+    atomic_add_i64(&J[r10 + ax.i1], v[3]);
+    atomic_add_i64(&J[r01 + ax.i0], v[4]);
+    atomic_add_i64(&J[r01 + ax.i1], v[5]);
+    atomic_add_i64(&J[r11 + ax.i0], v[6]);
+    atomic_add_i64(&J[r11 + ax.i1], v[7]);
+  }
+}
+
+// XCD-aware chunk range of a workgroup: workgroup b runs on XCD b % 8, so
+// each XCD gets one contiguous eighth of the (tile-sorted) chunks.
+struct ChunkRange { long long beg, end, stride; };
+
+__device__ __forceinline__ ChunkRange chunk_range(const BlockMap& bm, long long n) {
+  const long long nch = (n + kBlock - 1) / kBlock;
+  const long long per = (nch + 7) >> 3;
+  const int xcd = bm.lb & 7;
+  ChunkRange r;
+  r.beg = (long long)xcd * per + (bm.lb >> 3);
+  r.end = (long long)xcd * per + per < nch ? (long long)xcd * per + per : nch;
+  r.stride = bm.nb >> 3;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // the particle step: gather, Boris, deposit, move, ionisation,
 // bremsstrahlung, Davies scatter, boundaries, low-energy removal
 // ---------------------------------------------------------------------------
@@ -265,6 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
   long long n = ctr->n_total + inject_count(R, step);
   n = n < R.capacity ? n : R.capacity;
   const PartPtrs P = R.p[ctr->cur];
+  const bool count = sort_step(R.sort_every, step);
+  __shared__ ChunkLds S;
   long long acc[L_N + C_N];
 #pragma unroll
   for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
@@ -280,189 +401,359 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
   const T ledS = (T)kLedScale;
   const T twopi = (T)(2.0 * kPi);
 
-  // XCD-aware split: workgroup b runs on XCD b % 8, so give each XCD one
-  // contiguous eighth of the (cell-sorted) particle array.
-  const int xcd = bm.lb & 7, kk = bm.lb >> 3, nb8 = bm.nb >> 3;
-  const long long seg = (((n + 7) >> 3) + kBlock - 1) / kBlock * kBlock;
-  const long long beg = (long long)xcd * seg;
-  const long long end = beg + seg < n ? beg + seg : n;
-  for (long long i = beg + (long long)kk * kBlock + threadIdx.x; i < end; i += (long long)nb8 * kBlock) {
-    const uint32_t cell = P.cell[i];
-    if (cell == kDead) continue;
-    int ci = cell_i(cell), cj = cell_j(cell), ck = cell_k(cell);
-    const int heat_cell = ci + nx * (cj + ny * ck);
-    T ox = ((const T*)P.ox)[i], oy = ((const T*)P.oy)[i], oz = ((const T*)P.oz)[i];
-    T ux = ((const T*)P.ux)[i], uy = ((const T*)P.uy)[i], uz = ((const T*)P.uz)[i];
-    const T wn = ((const T*)P.wn)[i];
-    T tau = ((const T*)P.tau)[i];
-    const uint32_t id = P.id[i];
-
-    T u2 = ux * ux + uy * uy + uz * uz;
-    const T eps0 = kinetic(u2, m_sqrt((T)1 + u2));
-
-    // stencils at x^n (shared by gather and deposit)
-    const Axis<T> nxa = node_axis(ci, ox), nya = node_axis(cj, oy), nza = node_axis(ck, oz);
-    const Axis<T> sxa = stag_axis(ci, ox, nx), sya = stag_axis(cj, oy, ny), sza = stag_axis(ck, oz, nz);
-
-    // --- gather + Boris push (q = -e) ---
-    if (phys & PHYS_FIELDS) {
-      const T Ex = gather8(E0, sx, sxy, sxa, nya, nza);
-      const T Ey = gather8(E1, sx, sxy, nxa, sya, nza);
-      const T Ez = gather8(E2, sx, sxy, nxa, nya, sza);
-      const T Bx = gather8(B0, sx, sxy, nxa, sya, sza);
-      const T By = gather8(B1, sx, sxy, sxa, nya, sza);
-      const T Bz = gather8(B2, sx, sxy, sxa, sya, nza);
-      const T ex = e_kick * Ex, ey = e_kick * Ey, ez = e_kick * Ez;
-      const T mx = ux + ex, my = uy + ey, mz = uz + ez;
-      const T gi = b_rot / m_sqrt((T)1 + mx * mx + my * my + mz * mz);
-      const T tx = gi * Bx, ty = gi * By, tz = gi * Bz;
-      const T sf = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
-      const T sxv = sf * tx, syv = sf * ty, szv = sf * tz;
-      const T px = mx + (my * tz - mz * ty), py = my + (mz * tx - mx * tz), pz = mz + (mx * ty - my * tx);
-      ux = mx + (py * szv - pz * syv) + ex;
-      uy = my + (pz * sxv - px * szv) + ey;
-      uz = mz + (px * syv - py * sxv) + ez;
+  const ChunkRange cr = chunk_range(bm, n);
+  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride) {
+    lds_clear(S);
+    __syncthreads();
+    const long long i = ch * kBlock + threadIdx.x;
+    const uint32_t cell = i < n ? P.cell[i] : kDead;
+    int ci = 0, cj = 0, ck = 0, my_tile = -1;
+    if (cell != kDead) {
+      ci = cell_i(cell); cj = cell_j(cell); ck = cell_k(cell);
+      my_tile = tile_of(R, ci, cj, ck);
+      atomicMin(&S.home, my_tile);
     }
-    u2 = ux * ux + uy * uy + uz * uz;
-    T g = m_sqrt((T)1 + u2);
-    const T eps1 = kinetic(u2, g);
-    {
-      const T dW = eps1 - eps0;
-      if (dW > (T)0) acc[L_FIELD_GAIN] += to_fixed(dW * wn * ledS);
-      else acc[L_FIELD_LOSS] += to_fixed(-dW * wn * ledS);
-    }
-    const T ig = (T)1 / g;
-    const T vx = ux * ig, vy = uy * ig, vz = uz * ig;
+    __syncthreads();
+    const Home hm = make_home(R, S.home);
+    if (cell != kDead) {
+      const bool local = my_tile == S.home;
+      const int heat_cell = ci + nx * (cj + ny * ck);
+      const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
+      T ox = ((const T*)P.ox)[i], oy = ((const T*)P.oy)[i], oz = ((const T*)P.oz)[i];
+      T ux = ((const T*)P.ux)[i], uy = ((const T*)P.uy)[i], uz = ((const T*)P.uz)[i];
+      const T wn = ((const T*)P.wn)[i];
+      T tau = ((const T*)P.tau)[i];
+      const uint32_t id = P.id[i];
 
-    // --- hot-current deposit at x^n with the pushed velocity ---
-    {
-      const T amp = -wn * (T)kJScale;
-      deposit8(R.J[0], sx, sxy, sxa, nya, nza, amp * vx);
-      deposit8(R.J[1], sx, sxy, nxa, sya, nza, amp * vy);
-      deposit8(R.J[2], sx, sxy, nxa, nya, sza, amp * vz);
-    }
+      T u2 = ux * ux + uy * uy + uz * uz;
+      const T eps0 = kinetic(u2, m_sqrt((T)1 + u2));
 
-    // --- move ---
-    ox += vx * cdt; oy += vy * cdt; oz += vz * cdt;
-    {
-      const T fx = m_floor(ox), fy = m_floor(oy), fz = m_floor(oz);
-      ci += (int)fx; cj += (int)fy; ck += (int)fz;
-      ox -= fx; oy -= fy; oz -= fz;
-    }
+      // stencils at x^n (shared by gather and deposit)
+      const Axis<T> nxa = node_axis(ci, ox), nya = node_axis(cj, oy), nza = node_axis(ck, oz);
+      const Axis<T> sxa = stag_axis(ci, ox, nx), sya = stag_axis(cj, oy, ny), sza = stag_axis(ck, oz, nz);
 
-    // --- ionisation, eq. (stop_ion) ---
-    T eps2 = eps1;
-    if ((phys & PHYS_ION) && u2 > (T)0) {
-      const T beta = m_sqrt(u2) * ig;
-      T L = m_log(eps1) - (T)R.ln_iex + (T)0.5 * m_log(g + (T)1) + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
-      L = L > (T)0 ? L : (T)0;
-      T dE = (T)R.c_ion * L / beta;
-      dE = dE < eps1 ? dE : eps1;
-      const T sc = umag_of(eps1 - dE) / m_sqrt(u2);
-      ux *= sc; uy *= sc; uz *= sc;
-      u2 = ux * ux + uy * uy + uz * uz;
-      g = m_sqrt((T)1 + u2);
-      eps2 = kinetic(u2, g);
-      const T ion = (eps1 - eps2) * wn;
-      acc[L_ION] += to_fixed(ion * ledS);
-      atomic_add_i64(&R.ion_heat[heat_cell], to_fixed(ion * (T)kHeatScale));
-    }
-
-    // --- bremsstrahlung: optical depth, one emission per step at most ---
-    Uni4<T> cd{};
-    if (phys & (PHYS_BREM | PHYS_SCATTER)) cd = draws<T>(id, R.seed, step, SLOT_COLLIDE);
-    T eps3 = eps2;
-    if ((phys & PHYS_BREM) && u2 > (T)0) {
-      const T lne = m_log(eps2);
-      const T um = m_sqrt(u2);
-      const T beta = um / g;
-      tau -= (T)R.k_brem * tab.sigma(eps2, lne) * beta;
-      const T sub = (T)R.k_sub * tab.sub(eps2, lne) * beta;
-      T kph = (T)0;
-      if (tau < (T)0) {
-        kph = tab.sample_k(eps2, lne, cd.d);
-        const Uni4<T> pd = draws<T>(id, R.seed, step, SLOT_PHOTON);
-        tau = -m_log((T)1 - pd.c);
-        // photon direction about the electron direction
-        T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
-        th = th < (T)kPi ? th : (T)kPi;
-        T dxp = ux, dyp = uy, dzp = uz;
-        rotate(dxp, dyp, dzp, th, twopi * pd.b);
-        T cx = dxp / um;
-        cx = cx > (T)1 ? (T)1 : (cx < (T)-1 ? (T)-1 : cx);
-        const T tq = m_acos(cx) * (T)R.nth * (T)(1.0 / kPi);
-        const int it = tq >= (T)0 ? (tq < (T)(R.nth - 1) ? (int)tq : R.nth - 1) : 0;
-        const T eq = (m_log(kph) - (T)R.ln_Elo) * (T)R.e_bin_scale;
-        const int ie = !(eq >= (T)0) ? -1 : (eq >= (T)R.nE ? R.nE : (int)eq);
-        const T wph = wn * (T)R.inv_boost;
-        const long long vE = to_fixed(kph * wph * ledS);
-        const long long vN = to_fixed(wph * ledS);
-        const int nbin = R.nE * R.nth;
-        if (ie < 0) {
-          atomic_add_i64(&R.acc_hist[2 * nbin + 0], vE);
-          atomic_add_i64(&R.acc_hist[2 * nbin + 1], vN);
-        } else if (ie >= R.nE) {
-          atomic_add_i64(&R.acc_hist[2 * nbin + 2], vE);
-          atomic_add_i64(&R.acc_hist[2 * nbin + 3], vN);
-        } else {
-          atomic_add_i64(&R.acc_hist[ie * R.nth + it], vE);
-          atomic_add_i64(&R.acc_hist[nbin + ie * R.nth + it], vN);
-        }
-        if (kph >= (T)R.Ethr) acc[L_PHOTON_THR] += vE;
-        acc[L_RAD_D] += vE;
-        acc[L_N + C_EMITTED] += 1;
+      // --- gather + Boris push (q = -e) ---
+      if (phys & PHYS_FIELDS) {
+        const T Ex = gather8(E0, sx, sxy, sxa, nya, nza);
+        const T Ey = gather8(E1, sx, sxy, nxa, sya, nza);
+        const T Ez = gather8(E2, sx, sxy, nxa, nya, sza);
+        const T Bx = gather8(B0, sx, sxy, nxa, sya, sza);
+        const T By = gather8(B1, sx, sxy, sxa, nya, sza);
+        const T Bz = gather8(B2, sx, sxy, sxa, sya, nza);
+        const T ex = e_kick * Ex, ey = e_kick * Ey, ez = e_kick * Ez;
+        const T mx = ux + ex, my = uy + ey, mz = uz + ez;
+        const T gi = b_rot / m_sqrt((T)1 + mx * mx + my * my + mz * mz);
+        const T tx = gi * Bx, ty = gi * By, tz = gi * Bz;
+        const T sf = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
+        const T sxv = sf * tx, syv = sf * ty, szv = sf * tz;
+        const T px = mx + (my * tz - mz * ty), py = my + (mz * tx - mx * tz), pz = mz + (mx * ty - my * tx);
+        ux = mx + (py * szv - pz * syv) + ex;
+        uy = my + (pz * sxv - px * szv) + ey;
+        uz = mz + (px * syv - py * sxv) + ez;
       }
-      const T kb = kph * (T)R.inv_boost;
-      const T room = eps2 - kb;                   // >= 0: k <= eps2, boost >= 1
-      const T sub_a = sub < room ? sub : room;    // sub-cut loss actually applied
-      const T sc = umag_of(room - sub_a) / um;
-      ux *= sc; uy *= sc; uz *= sc;
       u2 = ux * ux + uy * uy + uz * uz;
-      g = m_sqrt((T)1 + u2);
-      eps3 = kinetic(u2, g);
-      acc[L_RAD_S] += to_fixed(sub_a * wn * ledS);
-      acc[L_RESIDUAL] += to_fixed((eps2 - eps3 - kb - sub_a) * wn * ledS);
-    }
+      T g = m_sqrt((T)1 + u2);
+      const T eps1 = kinetic(u2, g);
+      {
+        const T dW = eps1 - eps0;
+        if (dW > (T)0) acc[L_FIELD_GAIN] += to_fixed(dW * wn * ledS);
+        else acc[L_FIELD_LOSS] += to_fixed(-dW * wn * ledS);
+      }
+      const T ig = (T)1 / g;
+      const T vx = ux * ig, vy = uy * ig, vz = uz * ig;
 
-    // --- Davies elastic scatter ---
-    if ((phys & PHYS_SCATTER) && u2 > (T)0) {
-      const T um = m_sqrt(u2);
-      T lg = m_log((T)R.l_dav * um);
-      lg = lg > (T)0 ? lg : (T)0;
-      const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
-      const T gam = m_sqrt((T)-2 * m_log(cd.a)) * m_cos(twopi * cd.b);
-      rotate(ux, uy, uz, gam * m_sqrt(s2), twopi * cd.c);
-      // elastic: any change of the stored energy is rounding, booked apart
-      u2 = ux * ux + uy * uy + uz * uz;
-      g = m_sqrt((T)1 + u2);
-      const T eps_r = kinetic(u2, g);
-      acc[L_RESIDUAL] += to_fixed((eps3 - eps_r) * wn * ledS);
-      eps3 = eps_r;
-    }
+      // --- hot-current deposit at x^n with the pushed velocity ---
+      {
+        const T amp = -wn * (T)kJScale;
+        deposit8(R.J[0], S.J[0], local, hm, sx, sxy, sxa, nya, nza, amp * vx);
+        deposit8(R.J[1], S.J[1], local, hm, sx, sxy, nxa, sya, nza, amp * vy);
+        deposit8(R.J[2], S.J[2], local, hm, sx, sxy, nxa, nya, sza, amp * vz);
+      }
 
-    // --- boundaries: x (slab faces), y, z (domain walls) ---
-    T eps = eps3;
-    bool alive = boundary_axis(R, 0, ci, ox, R.ix_lo, R.ix_hi, ux, uy, uz, eps, wn, id, step, acc);
-    if (alive) alive = boundary_axis(R, 1, cj, oy, 0, ny, ux, uy, uz, eps, wn, id, step, acc);
-    if (alive) alive = boundary_axis(R, 2, ck, oz, 0, nz, ux, uy, uz, eps, wn, id, step, acc);
+      // --- move ---
+      ox += vx * cdt; oy += vy * cdt; oz += vz * cdt;
+      {
+        const T fx = m_floor(ox), fy = m_floor(oy), fz = m_floor(oz);
+        ci += (int)fx; cj += (int)fy; ck += (int)fz;
+        ox -= fx; oy -= fy; oz -= fz;
+      }
 
-    // --- removal below e_min, energy to the cell's heat ---
-    if (alive && eps < (T)R.e_min) {
-      acc[L_STOPPED] += to_fixed(eps * wn * ledS);
-      acc[L_N + C_STOPPED] += 1;
-      atomic_add_i64(&R.ion_heat[heat_cell], to_fixed(eps * wn * (T)kHeatScale));
-      alive = false;
+      // --- ionisation, eq. (stop_ion) ---
+      T eps2 = eps1;
+      long long heat = 0;
+      if ((phys & PHYS_ION) && u2 > (T)0) {
+        const T beta = m_sqrt(u2) * ig;
+        T L = m_log(eps1) - (T)R.ln_iex + (T)0.5 * m_log(g + (T)1) + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
+        L = L > (T)0 ? L : (T)0;
+        T dE = (T)R.c_ion * L / beta;
+        dE = dE < eps1 ? dE : eps1;
+        const T sc = umag_of(eps1 - dE) / m_sqrt(u2);
+        ux *= sc; uy *= sc; uz *= sc;
+        u2 = ux * ux + uy * uy + uz * uz;
+        g = m_sqrt((T)1 + u2);
+        eps2 = kinetic(u2, g);
+        const T ion = (eps1 - eps2) * wn;
+        acc[L_ION] += to_fixed(ion * ledS);
+        heat += to_fixed(ion * (T)kHeatScale);
+      }
+
+      // --- bremsstrahlung: optical depth, one emission per step at most ---
+      Uni4<T> cd{};
+      if (phys & (PHYS_BREM | PHYS_SCATTER)) cd = draws<T>(id, R.seed, step, SLOT_COLLIDE);
+      T eps3 = eps2;
+      if ((phys & PHYS_BREM) && u2 > (T)0) {
+        const T lne = m_log(eps2);
+        const T um = m_sqrt(u2);
+        const T beta = um / g;
+        tau -= (T)R.k_brem * tab.sigma(eps2, lne) * beta;
+        const T sub = (T)R.k_sub * tab.sub(eps2, lne) * beta;
+        T kph = (T)0;
+        if (tau < (T)0) {
+          kph = tab.sample_k(eps2, lne, cd.d);
+          const Uni4<T> pd = draws<T>(id, R.seed, step, SLOT_PHOTON);
+          tau = -m_log((T)1 - pd.c);
+          // photon direction about the electron direction
+          T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
+          th = th < (T)kPi ? th : (T)kPi;
+          T dxp = ux, dyp = uy, dzp = uz;
+          rotate(dxp, dyp, dzp, th, twopi * pd.b);
+          T cx = dxp / um;
+          cx = cx > (T)1 ? (T)1 : (cx < (T)-1 ? (T)-1 : cx);
+          const T tq = m_acos(cx) * (T)R.nth * (T)(1.0 / kPi);
+          const int it = tq >= (T)0 ? (tq < (T)(R.nth - 1) ? (int)tq : R.nth - 1) : 0;
+          const T eq = (m_log(kph) - (T)R.ln_Elo) * (T)R.e_bin_scale;
+          const int ie = !(eq >= (T)0) ? -1 : (eq >= (T)R.nE ? R.nE : (int)eq);
+          const T wph = wn * (T)R.inv_boost;
+          const long long vE = to_fixed(kph * wph * ledS);
+          const long long vN = to_fixed(wph * ledS);
+          const int nbin = R.nE * R.nth;
+          if (ie < 0) {
+            atomic_add_i64(&R.acc_hist[2 * nbin + 0], vE);
+            atomic_add_i64(&R.acc_hist[2 * nbin + 1], vN);
+          } else if (ie >= R.nE) {
+            atomic_add_i64(&R.acc_hist[2 * nbin + 2], vE);
+            atomic_add_i64(&R.acc_hist[2 * nbin + 3], vN);
+          } else {
+            atomic_add_i64(&R.acc_hist[ie * R.nth + it], vE);
+            atomic_add_i64(&R.acc_hist[nbin + ie * R.nth + it], vN);
+          }
+          if (kph >= (T)R.Ethr) acc[L_PHOTON_THR] += vE;
+          acc[L_RAD_D] += vE;
+          acc[L_N + C_EMITTED] += 1;
+        }
+        const T kb = kph * (T)R.inv_boost;
+        const T room = eps2 - kb;                   // >= 0: k <= eps2, boost >= 1
+        const T sub_a = sub < room ? sub : room;    // sub-cut loss actually applied
+        const T sc = umag_of(room - sub_a) / um;
+        ux *= sc; uy *= sc; uz *= sc;
+        u2 = ux * ux + uy * uy + uz * uz;
+        g = m_sqrt((T)1 + u2);
+        eps3 = kinetic(u2, g);
+        acc[L_RAD_S] += to_fixed(sub_a * wn * ledS);
+        acc[L_RESIDUAL] += to_fixed((eps2 - eps3 - kb - sub_a) * wn * ledS);
+      }
+
+      // --- Davies elastic scatter ---
+      if ((phys & PHYS_SCATTER) && u2 > (T)0) {
+        const T um = m_sqrt(u2);
+        T lg = m_log((T)R.l_dav * um);
+        lg = lg > (T)0 ? lg : (T)0;
+        const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
+        const T gam = m_sqrt((T)-2 * m_log(cd.a)) * m_cos(twopi * cd.b);
+        rotate(ux, uy, uz, gam * m_sqrt(s2), twopi * cd.c);
+        // elastic: any change of the stored energy is rounding, booked apart
+        u2 = ux * ux + uy * uy + uz * uz;
+        g = m_sqrt((T)1 + u2);
+        const T eps_r = kinetic(u2, g);
+        acc[L_RESIDUAL] += to_fixed((eps3 - eps_r) * wn * ledS);
+        eps3 = eps_r;
+      }
+
+      // --- boundaries: x (slab faces), y, z (domain walls) ---
+      T eps = eps3;
+      bool alive = boundary_axis(R, 0, ci, ox, R.ix_lo, R.ix_hi, ux, uy, uz, eps, wn, id, step, acc);
+      if (alive) alive = boundary_axis(R, 1, cj, oy, 0, ny, ux, uy, uz, eps, wn, id, step, acc);
+      if (alive) alive = boundary_axis(R, 2, ck, oz, 0, nz, ux, uy, uz, eps, wn, id, step, acc);
+
+      // --- removal below e_min, energy to the cell's heat ---
+      if (alive && eps < (T)R.e_min) {
+        acc[L_STOPPED] += to_fixed(eps * wn * ledS);
+        acc[L_N + C_STOPPED] += 1;
+        heat += to_fixed(eps * wn * (T)kHeatScale);
+        alive = false;
+      }
+      if (heat != 0) {
+        if (local) atomicAdd((unsigned long long*)&S.heat[heat_local], (unsigned long long)heat);
+        else atomic_add_i64(&R.ion_heat[heat_cell], heat);
+      }
+      if (!alive) {
+        P.cell[i] = kDead;
+      } else {
+        P.cell[i] = pack_cell(ci, cj, ck);
+        ((T*)P.ox)[i] = ox; ((T*)P.oy)[i] = oy; ((T*)P.oz)[i] = oz;
+        ((T*)P.ux)[i] = ux; ((T*)P.uy)[i] = uy; ((T*)P.uz)[i] = uz;
+        ((T*)P.tau)[i] = tau;
+        if (count) {   // destination tile for the sort that ends this step
+          const int tx = ci >> 2, ty = cj >> 2, tz = ck >> 2;
+          const int b = nb_bin(hm, tx, ty, tz);
+          if (b >= 0) atomicAdd(&S.cnt[b], 1u);
+          else atomicAdd(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
+        }
+      }
     }
-    if (!alive) {
-      P.cell[i] = kDead;
-      continue;
-    }
-    P.cell[i] = pack_cell(ci, cj, ck);
-    ((T*)P.ox)[i] = ox; ((T*)P.oy)[i] = oy; ((T*)P.oz)[i] = oz;
-    ((T*)P.ux)[i] = ux; ((T*)P.uy)[i] = uy; ((T*)P.uz)[i] = uz;
-    ((T*)P.tau)[i] = tau;
+    __syncthreads();
+    lds_flush(R, S, hm, count);
+    __syncthreads();
   }
   block_flush<L_N, C_N>(acc, R.acc_led, R.events);
+}
+
+// ---------------------------------------------------------------------------
+// tile sort: scan of the destination counts, then scatter of the electrons
+// into the other particle buffer in tile order (dead electrons dropped)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const RunDesc* __restrict__ runs,
+                                                        const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active || !sort_step(R.sort_every, R.ctr->step)) return;
+  __shared__ unsigned sm[kBlock];
+  const int t0 = bm.lb * kScanTile;
+  unsigned s = 0;
+  for (int t = t0 + threadIdx.x; t < t0 + kScanTile && t < R.ntiles; t += kBlock) s += R.tile_cnt[t];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) R.scan_blk[bm.lb] = sm[0];
+}
+
+// exclusive scan of the block sums (one workgroup per run)
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(const RunDesc* __restrict__ runs,
+                                                        const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active || !sort_step(R.sort_every, R.ctr->step)) return;
+  __shared__ unsigned sm[kBlock];
+  __shared__ unsigned carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < R.scan_nblk; base += kBlock) {
+    const int t = base + threadIdx.x;
+    const unsigned v = t < R.scan_nblk ? R.scan_blk[t] : 0u;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {   // inclusive Hillis-Steele scan
+      const unsigned a = threadIdx.x >= o ? sm[threadIdx.x - o] : 0u;
+      __syncthreads();
+      sm[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (t < R.scan_nblk) R.scan_blk[t] = carry + sm[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == kBlock - 1) carry += sm[kBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) R.ctr->n_sorted = carry;
+}
+
+// tile starts and scatter cursors
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict__ runs,
+                                                       const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  if (!R.ctr->active || !sort_step(R.sort_every, R.ctr->step)) return;
+  __shared__ unsigned sm[kBlock];
+  constexpr int per = kScanTile / kBlock;   // tiles per thread
+  const int t0 = bm.lb * kScanTile + threadIdx.x * per;
+  unsigned v[per];
+  unsigned s = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    v[q] = t0 + q < R.ntiles ? R.tile_cnt[t0 + q] : 0u;
+    s += v[q];
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    const unsigned a = threadIdx.x >= o ? sm[threadIdx.x - o] : 0u;
+    __syncthreads();
+    sm[threadIdx.x] += a;
+    __syncthreads();
+  }
+  unsigned run = R.scan_blk[bm.lb] + sm[threadIdx.x] - s;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    if (t0 + q < R.ntiles) {
+      R.tile_start[t0 + q] = run;
+      R.tile_cursor[t0 + q] = run;
+    }
+    run += v[q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ runs,
+                                                    const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  if (bm.nb < 8) return;
+  const RunDesc& R = runs[bm.run];
+  const Counters* ctr = R.ctr;
+  if (!ctr->active || !sort_step(R.sort_every, ctr->step)) return;
+  long long n = ctr->n_total + inject_count(R, ctr->step);
+  n = n < R.capacity ? n : R.capacity;
+  const PartPtrs A = R.p[ctr->cur];
+  const PartPtrs B = R.p[ctr->cur ^ 1];
+  __shared__ unsigned cnt[kNbN];
+  __shared__ unsigned base[kNbN];
+  __shared__ int home;
+  const ChunkRange cr = chunk_range(bm, n);
+  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride) {
+    if (threadIdx.x < kNbN) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) home = 0x7FFFFFFF;
+    __syncthreads();
+    const long long i = ch * kBlock + threadIdx.x;
+    const uint32_t cell = i < n ? A.cell[i] : kDead;
+    int t = -1, tx = 0, ty = 0, tz = 0;
+    if (cell != kDead) {
+      tx = cell_i(cell) >> 2; ty = cell_j(cell) >> 2; tz = cell_k(cell) >> 2;
+      t = tx + R.ntx * (ty + R.nty * tz);
+      atomicMin(&home, t);
+    }
+    __syncthreads();
+    const Home hm = make_home(R, home);
+    int b = -1;
+    unsigned rank = 0;
+    long long slot = -1;
+    if (t >= 0) {
+      b = nb_bin(hm, tx, ty, tz);
+      if (b >= 0) rank = atomicAdd(&cnt[b], 1u);
+      else slot = atomicAdd(&R.tile_cursor[t], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNbN && cnt[threadIdx.x] != 0) {
+      const int l = threadIdx.x;
+      const int bx = hm.tx + l % kNb - 2, by = hm.ty + (l / kNb) % kNb - 2, bz = hm.tz + l / (kNb * kNb) - 2;
+      base[l] = atomicAdd(&R.tile_cursor[bx + R.ntx * (by + R.nty * bz)], cnt[l]);
+    }
+    __syncthreads();
+    if (b >= 0) slot = (long long)base[b] + rank;
+    if (t >= 0 && slot >= 0 && slot < R.capacity) {   // counts and scatter agree; the bound is a guard
+      B.cell[slot] = cell;
+      ((T*)B.ox)[slot] = ((const T*)A.ox)[i];
+      ((T*)B.oy)[slot] = ((const T*)A.oy)[i];
+      ((T*)B.oz)[slot] = ((const T*)A.oz)[i];
+      ((T*)B.ux)[slot] = ((const T*)A.ux)[i];
+      ((T*)B.uy)[slot] = ((const T*)A.uy)[i];
+      ((T*)B.uz)[slot] = ((const T*)A.uz)[i];
+      ((T*)B.wn)[slot] = ((const T*)A.wn)[i];
+      ((T*)B.tau)[slot] = ((const T*)A.tau)[i];
+      B.id[slot] = A.id[i];
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -473,10 +764,13 @@ __global__ __launch_bounds__(kBlock) void k_zero_step(const RunDesc* __restrict_
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
   if (!R.ctr->active) return;
-  const long long nn = R.nodes, tot = 3 * nn + R.cells;
+  const long long nn = R.nodes;
+  const long long nt = sort_step(R.sort_every, R.ctr->step) ? R.ntiles : 0;
+  const long long tot = 3 * nn + R.cells + nt;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
     if (t < 3 * nn) R.J[t / nn][t % nn] = 0;
-    else R.ion_heat[t - 3 * nn] = 0;
+    else if (t < 3 * nn + R.cells) R.ion_heat[t - 3 * nn] = 0;
+    else R.tile_cnt[t - 3 * nn - R.cells] = 0;
   }
 }
 
@@ -642,8 +936,13 @@ __global__ void k_advance(const RunDesc* __restrict__ runs, const BlockMap* __re
   const RunDesc& R = runs[bm.run];
   Counters* c = R.ctr;
   if (!c->active) return;
-  const long long n = c->n_total + inject_count(R, c->step);
-  c->n_total = n < R.capacity ? n : R.capacity;
+  if (sort_step(R.sort_every, c->step)) {
+    c->n_total = c->n_sorted;   // the scatter kept the alive electrons only
+    c->cur ^= 1;
+  } else {
+    const long long n = c->n_total + inject_count(R, c->step);
+    c->n_total = n < R.capacity ? n : R.capacity;
+  }
   c->step += 1;
   if (c->steps_left > 0) {
     c->steps_left -= 1;
@@ -692,6 +991,12 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
   if (L.ev_start) (void)hipEventRecord(L.ev_start, s);
   hipLaunchKernelGGL(k_particle<T>, dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
   if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
+  if (L.sort) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+  }
   for (int k = 0; k < max_sub; ++k) {
     hipLaunchKernelGGL(k_ohm<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);
     hipLaunchKernelGGL(k_faraday<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);

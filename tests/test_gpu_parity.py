@@ -278,3 +278,28 @@ def test_bitwise_reproducible_and_graph_replay(P):
         assert np.array_equal(p, outs[0][1]) and np.array_equal(x, outs[0][2])
         assert np.array_equal(t["hist_E"], outs[0][0]["hist_E"])
         assert t["ledger"] == outs[0][0]["ledger"]
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_tile_sort_changes_nothing(P, precision):
+    """Sorting the electrons by tile every step (or every 3rd) only reorders
+    them: every electron, the ledger and the tallies are bitwise the same as
+    without sorting (all sums are integer, all draws keyed by id)."""
+    outs = []
+    for every in (0, 1, 3):
+        cfg, srcs, _ = small_config(6000, precision=precision, brem_boost=10.0, sort_every=every)
+        run = P.Run(cfg)
+        run.inject(srcs[0])
+        run.step(70)
+        t = run.tally()
+        st = run.get_state()
+        o = np.argsort(st["ids"])
+        outs.append((t, st["ids"][o], st["p"][o], st["pos"][o], st["tau"][o], st["Te"], st["B"][2]))
+        run.close()
+    for t, ids, p, x, tau, Te, Bz in outs[1:]:
+        assert np.array_equal(ids, outs[0][1])
+        assert np.array_equal(p, outs[0][2]) and np.array_equal(x, outs[0][3]) and np.array_equal(tau, outs[0][4])
+        assert np.array_equal(Te, outs[0][5]) and np.array_equal(Bz, outs[0][6])
+        assert np.array_equal(t["hist_E"], outs[0][0]["hist_E"])
+        assert t["ledger"] == outs[0][0]["ledger"]
+        assert t["n_alive"] == outs[0][0]["n_alive"]

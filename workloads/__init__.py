@@ -129,7 +129,7 @@ def config_fp64_large() -> tuple[dict, list[dict], int]:
         material="Au", x_lo=2e-6, x_hi=202e-6,
         I0=intensity_wcm2(1e21), reflux_ke_frac=0.0,
         tally_nE=64, tally_ntheta=90, series_len=2048,
-        max_particles=20_000_000, seed=0, sort_every=0)
+        max_particles=20_000_000, seed=0, sort_every=1)
     src = source(n_macro=20_000_000, t_start=0.0, t_end=1e-12, y0=64e-6,
                  z0=64e-6, r_fwhm=3e-6, T_hot=3.4 * MEV,
                  half_angle=math.radians(40.0))
@@ -145,7 +145,7 @@ def config_mixed_large() -> tuple[dict, list[dict], int]:
         material="Au", x_lo=2e-6, x_hi=254e-6,
         I0=intensity_wcm2(1e22), reflux_ke_frac=0.01,
         tally_nE=64, tally_ntheta=90, series_len=5000,
-        max_particles=100_000_000, seed=0)
+        max_particles=100_000_000, seed=0, sort_every=1)
     src = source(n_macro=100_000_000, t_start=0.0, t_end=1e-12, y0=128e-6,
                  z0=128e-6, r_fwhm=5e-6, T_hot=10.8 * MEV,
                  half_angle=math.radians(30.0))
@@ -160,7 +160,7 @@ def config_huge() -> tuple[dict, list[dict], int]:
         material="Au", x_lo=2e-6, x_hi=252e-6,
         I0=intensity_wcm2(1e22), reflux_ke_frac=0.0,
         tally_nE=128, tally_ntheta=180, series_len=10000,
-        max_particles=200_000_000, seed=0)
+        max_particles=200_000_000, seed=0, sort_every=1)
     src = source(n_macro=200_000_000, t_start=0.0, t_end=1e-12, y0=128e-6,
                  z0=128e-6, r_fwhm=2e-6, T_hot=10.8 * MEV,
                  half_angle=math.radians(30.0))
@@ -234,7 +234,7 @@ def scan_runs(n_runs: int = 64, seed: int = 0, rate_hz: float = 2.0,
             x_lo=ix_lo * dx_um * 1e-6, x_hi=ix_hi * dx_um * 1e-6,
             I0=intensity_wcm2(i_wcm2), reflux_ke_frac=0.0,
             tally_nE=64, tally_ntheta=90, series_len=max(steps, 1),
-            max_particles=n_macro, seed=r)
+            max_particles=n_macro, seed=r, sort_every=1)
         half = ny * dx_um * 1e-6 / 2
         src = source(n_macro=n_macro, t_start=0.0, t_end=1e-12, y0=half,
                      z0=half, r_fwhm=min(5e-6, 0.8 * half),
