@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", action="store_true", help="also run the 64-run serving scan")
     ap.add_argument("--particles", type=int, default=0, help="override the macro-electron count")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 512 MiB with torch (reference kernel for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
@@ -110,6 +112,16 @@ def main():
 
     import workloads as W
     import paper_2107_01723_amd as P
+
+    if a.copy_probe:
+        import torch
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# copy probe: 3 x 512 MiB read + 512 MiB written", file=sys.stderr, flush=True)
+        del src, dst
 
     cfg, srcs, total_steps = W.config_fp64_large()
     if a.particles:

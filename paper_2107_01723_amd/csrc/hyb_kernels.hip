@@ -245,10 +245,14 @@ constexpr int kHalo = kTile + 2;              // node span of a tile's stencils
 constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
 constexpr int kNb = 5;                        // destination tiles: home +-2 per axis
 constexpr int kNbN = kNb * kNb * kNb;         // 125
+// Electrons of a dense tile hit the same few LDS words; each accumulator
+// has kCopies interleaved copies (lane l adds into copy l % kCopies), which
+// divides the same-address serialisation of the LDS atomics by kCopies.
+constexpr int kCopies = 8;
 
 struct ChunkLds {
-  long long J[3][kHaloN];
-  long long heat[kTile * kTile * kTile];
+  long long J[3 * kHaloN * kCopies];
+  long long heat[kTile * kTile * kTile * kCopies];
   unsigned cnt[kNbN];
   int home;
 };
@@ -285,9 +289,8 @@ __device__ __forceinline__ int nb_bin(const Home& h, int tx, int ty, int tz) {
 }
 
 __device__ __forceinline__ void lds_clear(ChunkLds& L) {
-  long long* J = &L.J[0][0];
-  for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) J[t] = 0;
-  if (threadIdx.x < kTile * kTile * kTile) L.heat[threadIdx.x] = 0;
+  for (int t = threadIdx.x; t < 3 * kHaloN * kCopies; t += kBlock) L.J[t] = 0;
+  for (int t = threadIdx.x; t < kTile * kTile * kTile * kCopies; t += kBlock) L.heat[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) L.home = 0x7FFFFFFF;
 }
@@ -296,7 +299,9 @@ __device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds& L, const H
   if (!h.ok) return;
   const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
   for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
-    const long long v = (&L.J[0][0])[t];
+    long long v = 0;
+#pragma unroll
+    for (int q = 0; q < kCopies; ++q) v += L.J[t * kCopies + q];
     if (v == 0) continue;
     const int c = t / kHaloN, l = t % kHaloN;
     const int i = h.bx + l % kHalo, j = h.by + (l / kHalo) % kHalo, k = h.bz + l / (kHalo * kHalo);
@@ -304,7 +309,9 @@ __device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds& L, const H
     atomic_add_i64(&R.J[c][i + sx * j + sxy * k], v);
   }
   if (threadIdx.x < kTile * kTile * kTile) {
-    const long long v = L.heat[threadIdx.x];
+    long long v = 0;
+#pragma unroll
+    for (int q = 0; q < kCopies; ++q) v += L.heat[threadIdx.x * kCopies + q];
     const int l = threadIdx.x;
     const int i = kTile * h.tx + (l & 3), j = kTile * h.ty + ((l >> 2) & 3), k = kTile * h.tz + (l >> 4);
     if (v != 0 && i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.ion_heat[i + R.nx * (j + R.ny * k)], v);
@@ -328,17 +335,19 @@ __device__ __forceinline__ void deposit8(long long* __restrict__ J, long long* _
   const long long v[8] = {to_fixed(a00 * ax.w0), to_fixed(a00 * ax.w1), to_fixed(a10 * ax.w0), to_fixed(a10 * ax.w1),
                           to_fixed(a01 * ax.w0), to_fixed(a01 * ax.w1), to_fixed(a11 * ax.w0), to_fixed(a11 * ax.w1)};
   if (local) {
+    const int q = threadIdx.x & (kCopies - 1);
     const int i0 = ax.i0 - h.bx, i1 = ax.i1 - h.bx;
     const int j0 = (ay.i0 - h.by) * kHalo, j1 = (ay.i1 - h.by) * kHalo;
     const int k0 = (az.i0 - h.bz) * kHalo * kHalo, k1 = (az.i1 - h.bz) * kHalo * kHalo;
-    atomicAdd((unsigned long long*)&Js[i0 + j0 + k0], (unsigned long long)v[0]);
-    atomicAdd((unsigned long long*)&Js[i1 + j0 + k0], (unsigned long long)v[1]);
-    atomicAdd((unsigned long long*)&Js[i0 + j1 + k0], (unsigned long long)v[2]);
-    atomicAdd((unsigned long long*)&Js[i1 + j1 + k0], (unsigned long long)v[3]);
-    atomicAdd((unsigned long long*)&Js[i0 + j0 + k1], (unsigned long long)v[4]);
-    atomicAdd((unsigned long long*)&Js[i1 + j0 + k1], (unsigned long long)v[5]);
-    atomicAdd((unsigned long long*)&Js[i0 + j1 + k1], (unsigned long long)v[6]);
-    atomicAdd((unsigned long long*)&Js[i1 + j1 + k1], (unsigned long long)v[7]);
+    unsigned long long* J8 = (unsigned long long*)Js;
+    atomicAdd(&J8[(i0 + j0 + k0) * kCopies + q], (unsigned long long)v[0]);
+    atomicAdd(&J8[(i1 + j0 + k0) * kCopies + q], (unsigned long long)v[1]);
+    atomicAdd(&J8[(i0 + j1 + k0) * kCopies + q], (unsigned long long)v[2]);
+    atomicAdd(&J8[(i1 + j1 + k0) * kCopies + q], (unsigned long long)v[3]);
+    atomicAdd(&J8[(i0 + j0 + k1) * kCopies + q], (unsigned long long)v[4]);
+    atomicAdd(&J8[(i1 + j0 + k1) * kCopies + q], (unsigned long long)v[5]);
+    atomicAdd(&J8[(i0 + j1 + k1) * kCopies + q], (unsigned long long)v[6]);
+    atomicAdd(&J8[(i1 + j1 + k1) * kCopies + q], (unsigned long long)v[7]);
   } else {
     const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
     const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
@@ -411,10 +420,16 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
     if (cell != kDead) {
       ci = cell_i(cell); cj = cell_j(cell); ck = cell_k(cell);
       my_tile = tile_of(R, ci, cj, ck);
-      atomicMin(&S.home, my_tile);
+    }
+    {
+      int m = cell != kDead ? my_tile : 0x7FFFFFFF;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+      if ((threadIdx.x & 63) == 0 && m != 0x7FFFFFFF) atomicMin(&S.home, m);
     }
     __syncthreads();
     const Home hm = make_home(R, S.home);
+    int dest_bin = -1;
     if (cell != kDead) {
       const bool local = my_tile == S.home;
       const int heat_cell = ci + nx * (cj + ny * ck);
@@ -465,9 +480,9 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
       // --- hot-current deposit at x^n with the pushed velocity ---
       {
         const T amp = -wn * (T)kJScale;
-        deposit8(R.J[0], S.J[0], local, hm, sx, sxy, sxa, nya, nza, amp * vx);
-        deposit8(R.J[1], S.J[1], local, hm, sx, sxy, nxa, sya, nza, amp * vy);
-        deposit8(R.J[2], S.J[2], local, hm, sx, sxy, nxa, nya, sza, amp * vz);
+        deposit8(R.J[0], S.J, local, hm, sx, sxy, sxa, nya, nza, amp * vx);
+        deposit8(R.J[1], S.J + kHaloN * kCopies, local, hm, sx, sxy, nxa, sya, nza, amp * vy);
+        deposit8(R.J[2], S.J + 2 * kHaloN * kCopies, local, hm, sx, sxy, nxa, nya, sza, amp * vz);
       }
 
       // --- move ---
@@ -583,7 +598,9 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
         alive = false;
       }
       if (heat != 0) {
-        if (local) atomicAdd((unsigned long long*)&S.heat[heat_local], (unsigned long long)heat);
+        if (local)
+          atomicAdd((unsigned long long*)&S.heat[heat_local * kCopies + (threadIdx.x & (kCopies - 1))],
+                    (unsigned long long)heat);
         else atomic_add_i64(&R.ion_heat[heat_cell], heat);
       }
       if (!alive) {
@@ -595,11 +612,18 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
         ((T*)P.tau)[i] = tau;
         if (count) {   // destination tile for the sort that ends this step
           const int tx = ci >> 2, ty = cj >> 2, tz = ck >> 2;
-          const int b = nb_bin(hm, tx, ty, tz);
-          if (b >= 0) atomicAdd(&S.cnt[b], 1u);
-          else atomicAdd(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
+          dest_bin = nb_bin(hm, tx, ty, tz);
+          if (dest_bin < 0) atomicAdd(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
         }
       }
+    }
+    if (count) {
+      // most electrons of a chunk land in one tile: count it with one atomic
+      // per wave, the rest one by one
+      const int lead = __shfl(dest_bin, 0, 64);
+      const unsigned long long same = __ballot(dest_bin == lead && dest_bin >= 0);
+      if ((threadIdx.x & 63) == 0 && same) atomicAdd(&S.cnt[lead], (unsigned)__popcll(same));
+      if (dest_bin >= 0 && dest_bin != lead) atomicAdd(&S.cnt[dest_bin], 1u);
     }
     __syncthreads();
     lds_flush(R, S, hm, count);
