@@ -471,7 +471,10 @@ static hyb_status add_source(hyb_run* r, const hyb_source* s) {
     r->w_ref = std::max(r->w_ref, w);
   }
   const double wref = r->w_ref > 0 ? r->w_ref : w;
-  if (w / wref > 64.0) return fail(r, HYB_EINVAL, "source weight too large for the accumulator scale");
+  // the accumulator units are per w_ref; FP32-mixed runs stage the current in
+  // 32-bit LDS words, which bounds w / w_ref at 2
+  const double wmax = c.precision == HYB_FP64 ? 64.0 : 2.0;
+  if (w / wref > wmax) return fail(r, HYB_EINVAL, "source weight too large for the accumulator scale");
   SourceDesc d{};
   d.s0 = s0;
   d.ns = ns;
@@ -828,6 +831,11 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
     else if (wm > 0) r->w_ref = std::max(r->w_ref, wm);
     if (r->w_ref <= 0) r->w_ref = 1.0;
     set_units(r->h, r->w_ref);
+  }
+  {
+    const double wmax = (c.precision == HYB_FP64 ? 64.0 : 2.0) * r->w_ref;
+    for (size_t i = 0; i < n; ++i)
+      if (!(st->w[i] > 0) || st->w[i] > wmax) return fail(r, HYB_EINVAL, "particle weight outside (0, w_max]");
   }
   const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
   std::vector<uint32_t> cell(n);

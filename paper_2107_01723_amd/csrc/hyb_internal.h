@@ -191,6 +191,33 @@ __host__ __device__ __forceinline__ Uni4<T> draws(uint32_t id, uint32_t seed, lo
 enum : uint32_t { SLOT_COLLIDE = 0, SLOT_PHOTON = 1, SLOT_REFLUX0 = 2, SLOT_INJ_A = 8, SLOT_INJ_B = 9 };
 
 // ---- math in the run's precision ------------------------------------------
+// Descriptor pointers are generic.  Kernels cast them to the global address
+// space so that the compiler emits global rather than flat memory
+// instructions: a flat access also counts against the LDS / scalar-load wait
+// counter, so every wait for an LDS result would drain the HBM loads in
+// flight as well.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> G(T* p) { return (gptr<T>)p; }
+
+__device__ __forceinline__ void atomic_add_i64(long long* p, long long v) {
+  __hip_atomic_fetch_add(G(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned atomic_add_u32(unsigned* p, unsigned v) {
+  return __hip_atomic_fetch_add(G(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Particle arrays of one buffer, typed for the run's precision.
+template <typename T>
+struct PartG {
+  gptr<uint32_t> cell, id;
+  gptr<T> ox, oy, oz, ux, uy, uz, wn, tau;
+};
+template <typename T>
+__device__ __forceinline__ PartG<T> part_g(const PartPtrs& P) {
+  return PartG<T>{G(P.cell), G(P.id), G((T*)P.ox), G((T*)P.oy), G((T*)P.oz),
+                  G((T*)P.ux), G((T*)P.uy), G((T*)P.uz), G((T*)P.wn), G((T*)P.tau)};
+}
+
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_log(float x) { return logf(x); }
@@ -243,7 +270,7 @@ __device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T phi) {
 // ---- bremsstrahlung table lookups ------------------------------------------
 template <typename T>
 struct TableView {
-  const T* X; const T* SIG; const T* SUB;
+  gptr<const T> X; gptr<const T> SIG; gptr<const T> SUB;
   int nT, nr;
   T ln_kcut, s_scale, kcut;
   __device__ __forceinline__ void row(T lneps, int& j, T& f) const {
@@ -273,8 +300,8 @@ struct TableView {
     int i = (int)m_floor(q);
     i = i > nr - 2 ? nr - 2 : i;
     const T g = q - (T)i;
-    const T* r0 = X + (long long)j * nr;
-    const T* r1 = r0 + nr;
+    const gptr<const T> r0 = X + (long long)j * nr;
+    const gptr<const T> r1 = r0 + nr;
     const T x0 = r0[i] + g * (r0[i + 1] - r0[i]);
     const T x1 = r1[i] + g * (r1[i + 1] - r1[i]);
     const T x = x0 + f * (x1 - x0);

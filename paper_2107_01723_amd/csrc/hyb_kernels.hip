@@ -22,12 +22,12 @@ __device__ __forceinline__ long long inject_count(const RunDesc& R, long long st
                                                   long long* cnt = nullptr, long long* first = nullptr) {
   long long tot = 0;
   for (int s = 0; s < R.nsrc; ++s) {
-    const SourceDesc& S = R.src[s];
-    const long long i = step - S.s0;
+    const gptr<const SourceDesc> S = G(R.src) + s;
+    const long long i = step - S->s0;
     long long c = 0;
-    if (i >= 0 && i < S.ns) c = S.base + (i < S.rem ? 1 : 0);
+    if (i >= 0 && i < S->ns) c = S->base + (i < S->rem ? 1 : 0);
     if (cnt) cnt[s] = c;
-    if (first) first[s] = S.id0 + i * S.base + (i < S.rem ? i : S.rem);
+    if (first) first[s] = S->id0 + i * S->base + (i < S->rem ? i : S->rem);
     tot += c;
   }
   return tot;
@@ -54,13 +54,9 @@ __device__ __forceinline__ void block_flush(const long long (&v)[NL + NC], long 
     for (int w = 0; w < kWaves; ++w) s += sm[w][threadIdx.x];
     if (s != 0) {
       long long* dst = threadIdx.x < NL ? &led[threadIdx.x] : &evt[threadIdx.x - NL];
-      atomicAdd((unsigned long long*)dst, (unsigned long long)s);
+      atomic_add_i64(dst, s);
     }
   }
-}
-
-__device__ __forceinline__ void atomic_add_i64(long long* p, long long v) {
-  atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
 
 // Cell index and offset of a coordinate (cell units), kept inside [0, n).
@@ -81,11 +77,11 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
                                                    const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  const Counters* ctr = R.ctr;
+  const auto ctr = G(R.ctr);
   if (!ctr->active) return;
   const long long step = ctr->step;
   const long long n0 = ctr->n_total;
-  const PartPtrs P = R.p[ctr->cur];
+  const PartG<T> P = part_g<T>(R.p[ctr->cur]);
   long long cnt[kMaxSources], first[kMaxSources];
   const long long tot = inject_count(R, step, cnt, first);
   long long acc[L_N + C_N];
@@ -96,16 +92,16 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     int s = 0;
     long long off = 0;
     while (s < R.nsrc - 1 && t >= off + cnt[s]) { off += cnt[s]; ++s; }
-    const SourceDesc& S = R.src[s];
+    const gptr<const SourceDesc> S = G(R.src) + s;
     const uint32_t id = (uint32_t)(first[s] + (t - off));
     const Uni4<T> a = draws<T>(id, R.seed, step, SLOT_INJ_A);
     const Uni4<T> b = draws<T>(id, R.seed, step, SLOT_INJ_B);
-    const T r = m_sqrt((T)-2 * (T)S.sig2 * m_log((T)1 - (T)0.5 * a.a));
+    const T r = m_sqrt((T)-2 * (T)S->sig2 * m_log((T)1 - (T)0.5 * a.a));
     const T ps = twopi * a.b;
-    const T y = (T)S.y0 + r * m_cos(ps);
-    const T z = (T)S.z0 + r * m_sin(ps);
-    const T eps = -(T)S.t_hot * m_log((T)1 - a.c);
-    const T ct = (T)1 - a.d * (T)S.one_minus_cos;
+    const T y = (T)S->y0 + r * m_cos(ps);
+    const T z = (T)S->z0 + r * m_sin(ps);
+    const T eps = -(T)S->t_hot * m_log((T)1 - a.c);
+    const T ct = (T)1 - a.d * (T)S->one_minus_cos;
     T st2 = (T)1 - ct * ct;
     const T st = m_sqrt(st2 > (T)0 ? st2 : (T)0);
     const T pc = twopi * b.a;
@@ -119,17 +115,17 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     to_cell(y, R.ny, cy, oy);
     to_cell(z, R.nz, cz, oz);
     P.cell[slot] = pack_cell(R.ix_lo, cy, cz);
-    ((T*)P.ox)[slot] = (T)0;
-    ((T*)P.oy)[slot] = oy;
-    ((T*)P.oz)[slot] = oz;
-    ((T*)P.ux)[slot] = ux;
-    ((T*)P.uy)[slot] = uy;
-    ((T*)P.uz)[slot] = uz;
-    ((T*)P.wn)[slot] = (T)S.wn;
-    ((T*)P.tau)[slot] = tau;
+    P.ox[slot] = (T)0;
+    P.oy[slot] = oy;
+    P.oz[slot] = oz;
+    P.ux[slot] = ux;
+    P.uy[slot] = uy;
+    P.uz[slot] = uz;
+    P.wn[slot] = (T)S->wn;
+    P.tau[slot] = tau;
     P.id[slot] = id;
     const T u2 = ux * ux + uy * uy + uz * uz;
-    acc[L_INJECTED] += to_fixed(kinetic(u2, m_sqrt((T)1 + u2)) * (T)S.wn * (T)kLedScale);
+    acc[L_INJECTED] += to_fixed(kinetic(u2, m_sqrt((T)1 + u2)) * (T)S->wn * (T)kLedScale);
     acc[L_N + C_INJECTED] += 1;
   }
   block_flush<L_N, C_N>(acc, R.acc_led, R.events);
@@ -162,7 +158,7 @@ __device__ __forceinline__ Axis<T> stag_axis(int c, T o, int n) {
 }
 
 template <typename T>
-__device__ __forceinline__ T gather8(const T* __restrict__ F, int sx, int sxy, const Axis<T>& ax,
+__device__ __forceinline__ T gather8(gptr<const T> F, int sx, int sxy, const Axis<T>& ax,
                                      const Axis<T>& ay, const Axis<T>& az) {
   const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
   const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
@@ -250,8 +246,20 @@ constexpr int kNbN = kNb * kNb * kNb;         // 125
 // divides the same-address serialisation of the LDS atomics by kCopies.
 constexpr int kCopies = 8;
 
+// Current contributions are fixed point.  FP64 runs use 2^40 units per
+// (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
+// contribution to 2^24 units -- already finer than the FP32 state -- so the
+// LDS sums fit 32-bit words (one copy takes at most kBlock / kCopies = 32
+// contributions of magnitude < 2^25 for w / w_ref <= 2), which are widened to
+// the 2^40 HBM accumulators at the flush.  Every contribution is rounded the
+// same way whether it goes through LDS or straight to HBM, so the sums stay
+// independent of the electron order.
+template <typename T> struct JAcc { using type = long long; static constexpr int shift = 0; };
+template <> struct JAcc<float> { using type = int; static constexpr int shift = 16; };
+
+template <typename T>
 struct ChunkLds {
-  long long J[3 * kHaloN * kCopies];
+  typename JAcc<T>::type J[3 * kHaloN * kCopies];
   long long heat[kTile * kTile * kTile * kCopies];
   unsigned cnt[kNbN];
   int home;
@@ -288,21 +296,24 @@ __device__ __forceinline__ int nb_bin(const Home& h, int tx, int ty, int tz) {
   return dx + kNb * (dy + kNb * dz);
 }
 
-__device__ __forceinline__ void lds_clear(ChunkLds& L) {
+template <typename T>
+__device__ __forceinline__ void lds_clear(ChunkLds<T>& L) {
   for (int t = threadIdx.x; t < 3 * kHaloN * kCopies; t += kBlock) L.J[t] = 0;
   for (int t = threadIdx.x; t < kTile * kTile * kTile * kCopies; t += kBlock) L.heat[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) L.home = 0x7FFFFFFF;
 }
 
-__device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds& L, const Home& h, bool count) {
+template <typename T>
+__device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds<T>& L, const Home& h, bool count) {
   if (!h.ok) return;
   const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
   for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
     long long v = 0;
 #pragma unroll
-    for (int q = 0; q < kCopies; ++q) v += L.J[t * kCopies + q];
+    for (int q = 0; q < kCopies; ++q) v += (long long)L.J[t * kCopies + q];
     if (v == 0) continue;
+    v *= (1LL << JAcc<T>::shift);
     const int c = t / kHaloN, l = t % kHaloN;
     const int i = h.bx + l % kHalo, j = h.by + (l / kHalo) % kHalo, k = h.bz + l / (kHalo * kHalo);
     if (i < 0 || j < 0 || k < 0 || i > R.nx || j > R.ny || k > R.nz) continue;
@@ -321,44 +332,52 @@ __device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds& L, const H
     const int l = threadIdx.x;
     const int tx = h.tx + l % kNb - 2, ty = h.ty + (l / kNb) % kNb - 2, tz = h.tz + l / (kNb * kNb) - 2;
     if (v != 0 && tx >= 0 && ty >= 0 && tz >= 0 && tx < R.ntx && ty < R.nty && tz < R.ntz)
-      atomicAdd(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], v);
+      atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], v);
   }
 }
 
 // deposit of one current component: 8 corners to LDS (home tile) or HBM
+__device__ __forceinline__ void lds_add(long long* p, long long v) {
+  atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void lds_add(int* p, int v) { atomicAdd(p, v); }
+__device__ __forceinline__ long long jfix(double x) { return to_fixed(x); }
+__device__ __forceinline__ int jfix(float x) { return __float2int_rn(x); }
+
 template <typename T>
-__device__ __forceinline__ void deposit8(long long* __restrict__ J, long long* __restrict__ Js, bool local,
-                                         const Home& h, int sx, int sxy, const Axis<T>& ax,
+__device__ __forceinline__ void deposit8(long long* __restrict__ J, typename JAcc<T>::type* __restrict__ Js,
+                                         bool local, const Home& h, int sx, int sxy, const Axis<T>& ax,
                                          const Axis<T>& ay, const Axis<T>& az, T amp) {
+  using A = typename JAcc<T>::type;
   const T a00 = amp * az.w0 * ay.w0, a10 = amp * az.w0 * ay.w1;
   const T a01 = amp * az.w1 * ay.w0, a11 = amp * az.w1 * ay.w1;
-  const long long v[8] = {to_fixed(a00 * ax.w0), to_fixed(a00 * ax.w1), to_fixed(a10 * ax.w0), to_fixed(a10 * ax.w1),
-                          to_fixed(a01 * ax.w0), to_fixed(a01 * ax.w1), to_fixed(a11 * ax.w0), to_fixed(a11 * ax.w1)};
+  const A v[8] = {jfix(a00 * ax.w0), jfix(a00 * ax.w1), jfix(a10 * ax.w0), jfix(a10 * ax.w1),
+                  jfix(a01 * ax.w0), jfix(a01 * ax.w1), jfix(a11 * ax.w0), jfix(a11 * ax.w1)};
   if (local) {
     const int q = threadIdx.x & (kCopies - 1);
     const int i0 = ax.i0 - h.bx, i1 = ax.i1 - h.bx;
     const int j0 = (ay.i0 - h.by) * kHalo, j1 = (ay.i1 - h.by) * kHalo;
     const int k0 = (az.i0 - h.bz) * kHalo * kHalo, k1 = (az.i1 - h.bz) * kHalo * kHalo;
-    unsigned long long* J8 = (unsigned long long*)Js;
-    atomicAdd(&J8[(i0 + j0 + k0) * kCopies + q], (unsigned long long)v[0]);
-    atomicAdd(&J8[(i1 + j0 + k0) * kCopies + q], (unsigned long long)v[1]);
-    atomicAdd(&J8[(i0 + j1 + k0) * kCopies + q], (unsigned long long)v[2]);
-    atomicAdd(&J8[(i1 + j1 + k0) * kCopies + q], (unsigned long long)v[3]);
-    atomicAdd(&J8[(i0 + j0 + k1) * kCopies + q], (unsigned long long)v[4]);
-    atomicAdd(&J8[(i1 + j0 + k1) * kCopies + q], (unsigned long long)v[5]);
-    atomicAdd(&J8[(i0 + j1 + k1) * kCopies + q], (unsigned long long)v[6]);
-    atomicAdd(&J8[(i1 + j1 + k1) * kCopies + q], (unsigned long long)v[7]);
+    lds_add(&Js[(i0 + j0 + k0) * kCopies + q], v[0]);
+    lds_add(&Js[(i1 + j0 + k0) * kCopies + q], v[1]);
+    lds_add(&Js[(i0 + j1 + k0) * kCopies + q], v[2]);
+    lds_add(&Js[(i1 + j1 + k0) * kCopies + q], v[3]);
+    lds_add(&Js[(i0 + j0 + k1) * kCopies + q], v[4]);
+    lds_add(&Js[(i1 + j0 + k1) * kCopies + q], v[5]);
+    lds_add(&Js[(i0 + j1 + k1) * kCopies + q], v[6]);
+    lds_add(&Js[(i1 + j1 + k1) * kCopies + q], v[7]);
   } else {
+    constexpr long long up = 1LL << JAcc<T>::shift;
     const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
     const int r01 = ay.i0 * sx + az.i1 * sxy, r11 = ay.i1 * sx + az.i1 * sxy;
-    atomic_add_i64(&J[r00 + ax.i0], v[0]);
-    atomic_add_i64(&J[r00 + ax.i1], v[1]);
-    atomic_add_i64(&J[r10 + ax.i0], v[2]);
-    atomic_add_i64(&J[r10 + ax.i1], v[3]);
-    atomic_add_i64(&J[r01 + ax.i0], v[4]);
-    atomic_add_i64(&J[r01 + ax.i1], v[5]);
-    atomic_add_i64(&J[r11 + ax.i0], v[6]);
-    atomic_add_i64(&J[r11 + ax.i1], v[7]);
+    atomic_add_i64(&J[r00 + ax.i0], (long long)v[0] * up);
+    atomic_add_i64(&J[r00 + ax.i1], (long long)v[1] * up);
+    atomic_add_i64(&J[r10 + ax.i0], (long long)v[2] * up);
+    atomic_add_i64(&J[r10 + ax.i1], (long long)v[3] * up);
+    atomic_add_i64(&J[r01 + ax.i0], (long long)v[4] * up);
+    atomic_add_i64(&J[r01 + ax.i1], (long long)v[5] * up);
+    atomic_add_i64(&J[r11 + ax.i0], (long long)v[6] * up);
+    atomic_add_i64(&J[r11 + ax.i1], (long long)v[7] * up);
   }
 }
 
@@ -387,14 +406,14 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
   const BlockMap bm = bmap[blockIdx.x];
   if (bm.nb < 8) return;   // alignment padding between runs
   const RunDesc& R = runs[bm.run];
-  const Counters* ctr = R.ctr;
+  const auto ctr = G(R.ctr);
   if (!ctr->active) return;
   const long long step = ctr->step;
   long long n = ctr->n_total + inject_count(R, step);
   n = n < R.capacity ? n : R.capacity;
-  const PartPtrs P = R.p[ctr->cur];
+  const PartG<T> P = part_g<T>(R.p[ctr->cur]);
   const bool count = sort_step(R.sort_every, step);
-  __shared__ ChunkLds S;
+  __shared__ ChunkLds<T> S;
   long long acc[L_N + C_N];
 #pragma unroll
   for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
@@ -402,9 +421,9 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
   const int nx = R.nx, ny = R.ny, nz = R.nz;
   const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
   const uint32_t phys = R.physics;
-  const T* E0 = (const T*)R.E[0]; const T* E1 = (const T*)R.E[1]; const T* E2 = (const T*)R.E[2];
-  const T* B0 = (const T*)R.B[0]; const T* B1 = (const T*)R.B[1]; const T* B2 = (const T*)R.B[2];
-  TableView<T> tab{(const T*)R.tab_X, (const T*)R.tab_SIG, (const T*)R.tab_SUB, R.tab_nT, R.tab_nr,
+  const gptr<const T> E0 = G((const T*)R.E[0]), E1 = G((const T*)R.E[1]), E2 = G((const T*)R.E[2]);
+  const gptr<const T> B0 = G((const T*)R.B[0]), B1 = G((const T*)R.B[1]), B2 = G((const T*)R.B[2]);
+  TableView<T> tab{G((const T*)R.tab_X), G((const T*)R.tab_SIG), G((const T*)R.tab_SUB), R.tab_nT, R.tab_nr,
                    (T)R.tab_ln_kcut, (T)R.tab_s_scale, (T)R.tab_kcut};
   const T e_kick = (T)R.e_kick, b_rot = (T)R.b_rot, cdt = (T)R.cdt_dx;
   const T ledS = (T)kLedScale;
@@ -434,10 +453,10 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
       const bool local = my_tile == S.home;
       const int heat_cell = ci + nx * (cj + ny * ck);
       const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
-      T ox = ((const T*)P.ox)[i], oy = ((const T*)P.oy)[i], oz = ((const T*)P.oz)[i];
-      T ux = ((const T*)P.ux)[i], uy = ((const T*)P.uy)[i], uz = ((const T*)P.uz)[i];
-      const T wn = ((const T*)P.wn)[i];
-      T tau = ((const T*)P.tau)[i];
+      T ox = P.ox[i], oy = P.oy[i], oz = P.oz[i];
+      T ux = P.ux[i], uy = P.uy[i], uz = P.uz[i];
+      const T wn = P.wn[i];
+      T tau = P.tau[i];
       const uint32_t id = P.id[i];
 
       T u2 = ux * ux + uy * uy + uz * uz;
@@ -479,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
 
       // --- hot-current deposit at x^n with the pushed velocity ---
       {
-        const T amp = -wn * (T)kJScale;
+        const T amp = -wn * (T)(kJScale / (double)(1LL << JAcc<T>::shift));
         deposit8(R.J[0], S.J, local, hm, sx, sxy, sxa, nya, nza, amp * vx);
         deposit8(R.J[1], S.J + kHaloN * kCopies, local, hm, sx, sxy, nxa, sya, nza, amp * vy);
         deposit8(R.J[2], S.J + 2 * kHaloN * kCopies, local, hm, sx, sxy, nxa, nya, sza, amp * vz);
@@ -607,13 +626,13 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
         P.cell[i] = kDead;
       } else {
         P.cell[i] = pack_cell(ci, cj, ck);
-        ((T*)P.ox)[i] = ox; ((T*)P.oy)[i] = oy; ((T*)P.oz)[i] = oz;
-        ((T*)P.ux)[i] = ux; ((T*)P.uy)[i] = uy; ((T*)P.uz)[i] = uz;
-        ((T*)P.tau)[i] = tau;
+        P.ox[i] = ox; P.oy[i] = oy; P.oz[i] = oz;
+        P.ux[i] = ux; P.uy[i] = uy; P.uz[i] = uz;
+        P.tau[i] = tau;
         if (count) {   // destination tile for the sort that ends this step
           const int tx = ci >> 2, ty = cj >> 2, tz = ck >> 2;
           dest_bin = nb_bin(hm, tx, ty, tz);
-          if (dest_bin < 0) atomicAdd(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
+          if (dest_bin < 0) atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
         }
       }
     }
@@ -640,18 +659,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const RunDesc* __restric
                                                         const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active || !sort_step(R.sort_every, R.ctr->step)) return;
+  if (!G(R.ctr)->active || !sort_step(R.sort_every, G(R.ctr)->step)) return;
   __shared__ unsigned sm[kBlock];
   const int t0 = bm.lb * kScanTile;
   unsigned s = 0;
-  for (int t = t0 + threadIdx.x; t < t0 + kScanTile && t < R.ntiles; t += kBlock) s += R.tile_cnt[t];
+  for (int t = t0 + threadIdx.x; t < t0 + kScanTile && t < R.ntiles; t += kBlock) s += G(R.tile_cnt)[t];
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) R.scan_blk[bm.lb] = sm[0];
+  if (threadIdx.x == 0) G(R.scan_blk)[bm.lb] = sm[0];
 }
 
 // exclusive scan of the block sums (one workgroup per run)
@@ -659,14 +678,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_blocks(const RunDesc* __restric
                                                         const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active || !sort_step(R.sort_every, R.ctr->step)) return;
+  if (!G(R.ctr)->active || !sort_step(R.sort_every, G(R.ctr)->step)) return;
   __shared__ unsigned sm[kBlock];
   __shared__ unsigned carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int base = 0; base < R.scan_nblk; base += kBlock) {
     const int t = base + threadIdx.x;
-    const unsigned v = t < R.scan_nblk ? R.scan_blk[t] : 0u;
+    const unsigned v = t < R.scan_nblk ? G(R.scan_blk)[t] : 0u;
     sm[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < kBlock; o <<= 1) {   // inclusive Hillis-Steele scan
@@ -675,12 +694,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_blocks(const RunDesc* __restric
       sm[threadIdx.x] += a;
       __syncthreads();
     }
-    if (t < R.scan_nblk) R.scan_blk[t] = carry + sm[threadIdx.x] - v;
+    if (t < R.scan_nblk) G(R.scan_blk)[t] = carry + sm[threadIdx.x] - v;
     __syncthreads();
     if (threadIdx.x == kBlock - 1) carry += sm[kBlock - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0) R.ctr->n_sorted = carry;
+  if (threadIdx.x == 0) G(R.ctr)->n_sorted = carry;
 }
 
 // tile starts and scatter cursors
@@ -688,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
                                                        const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active || !sort_step(R.sort_every, R.ctr->step)) return;
+  if (!G(R.ctr)->active || !sort_step(R.sort_every, G(R.ctr)->step)) return;
   __shared__ unsigned sm[kBlock];
   constexpr int per = kScanTile / kBlock;   // tiles per thread
   const int t0 = bm.lb * kScanTile + threadIdx.x * per;
@@ -696,7 +715,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
   unsigned s = 0;
 #pragma unroll
   for (int q = 0; q < per; ++q) {
-    v[q] = t0 + q < R.ntiles ? R.tile_cnt[t0 + q] : 0u;
+    v[q] = t0 + q < R.ntiles ? G(R.tile_cnt)[t0 + q] : 0u;
     s += v[q];
   }
   sm[threadIdx.x] = s;
@@ -707,12 +726,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
     sm[threadIdx.x] += a;
     __syncthreads();
   }
-  unsigned run = R.scan_blk[bm.lb] + sm[threadIdx.x] - s;
+  unsigned run = G(R.scan_blk)[bm.lb] + sm[threadIdx.x] - s;
 #pragma unroll
   for (int q = 0; q < per; ++q) {
     if (t0 + q < R.ntiles) {
-      R.tile_start[t0 + q] = run;
-      R.tile_cursor[t0 + q] = run;
+      G(R.tile_start)[t0 + q] = run;
+      G(R.tile_cursor)[t0 + q] = run;
     }
     run += v[q];
   }
@@ -724,12 +743,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
   const BlockMap bm = bmap[blockIdx.x];
   if (bm.nb < 8) return;
   const RunDesc& R = runs[bm.run];
-  const Counters* ctr = R.ctr;
+  const auto ctr = G(R.ctr);
   if (!ctr->active || !sort_step(R.sort_every, ctr->step)) return;
   long long n = ctr->n_total + inject_count(R, ctr->step);
   n = n < R.capacity ? n : R.capacity;
-  const PartPtrs A = R.p[ctr->cur];
-  const PartPtrs B = R.p[ctr->cur ^ 1];
+  const PartG<T> A = part_g<T>(R.p[ctr->cur]);
+  const PartG<T> B = part_g<T>(R.p[ctr->cur ^ 1]);
   __shared__ unsigned cnt[kNbN];
   __shared__ unsigned base[kNbN];
   __shared__ int home;
@@ -754,26 +773,26 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
     if (t >= 0) {
       b = nb_bin(hm, tx, ty, tz);
       if (b >= 0) rank = atomicAdd(&cnt[b], 1u);
-      else slot = atomicAdd(&R.tile_cursor[t], 1u);
+      else slot = atomic_add_u32(&R.tile_cursor[t], 1u);
     }
     __syncthreads();
     if (threadIdx.x < kNbN && cnt[threadIdx.x] != 0) {
       const int l = threadIdx.x;
       const int bx = hm.tx + l % kNb - 2, by = hm.ty + (l / kNb) % kNb - 2, bz = hm.tz + l / (kNb * kNb) - 2;
-      base[l] = atomicAdd(&R.tile_cursor[bx + R.ntx * (by + R.nty * bz)], cnt[l]);
+      base[l] = atomic_add_u32(&R.tile_cursor[bx + R.ntx * (by + R.nty * bz)], cnt[l]);
     }
     __syncthreads();
     if (b >= 0) slot = (long long)base[b] + rank;
     if (t >= 0 && slot >= 0 && slot < R.capacity) {   // counts and scatter agree; the bound is a guard
       B.cell[slot] = cell;
-      ((T*)B.ox)[slot] = ((const T*)A.ox)[i];
-      ((T*)B.oy)[slot] = ((const T*)A.oy)[i];
-      ((T*)B.oz)[slot] = ((const T*)A.oz)[i];
-      ((T*)B.ux)[slot] = ((const T*)A.ux)[i];
-      ((T*)B.uy)[slot] = ((const T*)A.uy)[i];
-      ((T*)B.uz)[slot] = ((const T*)A.uz)[i];
-      ((T*)B.wn)[slot] = ((const T*)A.wn)[i];
-      ((T*)B.tau)[slot] = ((const T*)A.tau)[i];
+      B.ox[slot] = A.ox[i];
+      B.oy[slot] = A.oy[i];
+      B.oz[slot] = A.oz[i];
+      B.ux[slot] = A.ux[i];
+      B.uy[slot] = A.uy[i];
+      B.uz[slot] = A.uz[i];
+      B.wn[slot] = A.wn[i];
+      B.tau[slot] = A.tau[i];
       B.id[slot] = A.id[i];
     }
     __syncthreads();
@@ -787,14 +806,15 @@ __global__ __launch_bounds__(kBlock) void k_zero_step(const RunDesc* __restrict_
                                                       const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active) return;
+  const auto ctr = G(R.ctr);
+  if (!ctr->active) return;
   const long long nn = R.nodes;
-  const long long nt = sort_step(R.sort_every, R.ctr->step) ? R.ntiles : 0;
+  const long long nt = sort_step(R.sort_every, ctr->step) ? R.ntiles : 0;
   const long long tot = 3 * nn + R.cells + nt;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
-    if (t < 3 * nn) R.J[t / nn][t % nn] = 0;
-    else if (t < 3 * nn + R.cells) R.ion_heat[t - 3 * nn] = 0;
-    else R.tile_cnt[t - 3 * nn - R.cells] = 0;
+    if (t < 3 * nn) G(R.J[t / nn])[t % nn] = 0;
+    else if (t < 3 * nn + R.cells) G(R.ion_heat)[t - 3 * nn] = 0;
+    else G(R.tile_cnt)[t - 3 * nn - R.cells] = 0;
   }
 }
 
@@ -806,12 +826,14 @@ __global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs
                                                 const BlockMap* __restrict__ bmap, int sub) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active || sub >= R.n_sub || !(R.physics & PHYS_EVOLVE_E)) return;
+  if (!G(R.ctr)->active || sub >= R.n_sub || !(R.physics & PHYS_EVOLVE_E)) return;
   const int nx = R.nx, ny = R.ny, nz = R.nz;
   const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
-  const T* Bx = (const T*)R.B[0]; const T* By = (const T*)R.B[1]; const T* Bz = (const T*)R.B[2];
-  T* Ex = (T*)R.E[0]; T* Ey = (T*)R.E[1]; T* Ez = (T*)R.E[2];
-  const double* eta = R.eta;
+  const gptr<const T> Bx = G((const T*)R.B[0]), By = G((const T*)R.B[1]), Bz = G((const T*)R.B[2]);
+  const gptr<T> Ex = G((T*)R.E[0]), Ey = G((T*)R.E[1]), Ez = G((T*)R.E[2]);
+  const gptr<const long long> Jx = G((const long long*)R.J[0]), Jy = G((const long long*)R.J[1]),
+                              Jz = G((const long long*)R.J[2]);
+  const gptr<const double> eta = G((const double*)R.eta);
   const double inv_dx = 1.0 / R.dx, inv_mu0 = 1.0 / kMu0, ju = R.j_unit;
   const long long nn = R.nodes;
   auto ce = [&](int i, int j, int k) { return eta[i + nx * (j + ny * k)]; };
@@ -831,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs
       const T bym = k > 0 ? By[idx - sxy] : -By[idx];
       const double curl = (double)((bzp - bzm) - (byp - bym)) * inv_dx;
       const double ee = 0.25 * (ce(i, jm, km) + ce(i, jc, km) + ce(i, jm, kc) + ce(i, jc, kc));
-      Ex[idx] = (T)(ee * (curl * inv_mu0 - (double)R.J[0][idx] * ju));
+      Ex[idx] = (T)(ee * (curl * inv_mu0 - (double)Jx[idx] * ju));
     }
     if (j < ny) {   // Ey at (i, j+1/2, k): dBx/dz - dBz/dx
       const T bxp = k < nz ? Bx[idx] : -Bx[idx - sxy];
@@ -840,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs
       const T bzm = i > 0 ? Bz[idx - 1] : -Bz[idx];
       const double curl = (double)((bxp - bxm) - (bzp - bzm)) * inv_dx;
       const double ee = 0.25 * (ce(im, j, km) + ce(ic, j, km) + ce(im, j, kc) + ce(ic, j, kc));
-      Ey[idx] = (T)(ee * (curl * inv_mu0 - (double)R.J[1][idx] * ju));
+      Ey[idx] = (T)(ee * (curl * inv_mu0 - (double)Jy[idx] * ju));
     }
     if (k < nz) {   // Ez at (i, j, k+1/2): dBy/dx - dBx/dy
       const T byp = i < nx ? By[idx] : -By[idx - 1];
@@ -849,7 +871,7 @@ __global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs
       const T bxm = j > 0 ? Bx[idx - sx] : -Bx[idx];
       const double curl = (double)((byp - bym) - (bxp - bxm)) * inv_dx;
       const double ee = 0.25 * (ce(im, jm, k) + ce(ic, jm, k) + ce(im, jc, k) + ce(ic, jc, k));
-      Ez[idx] = (T)(ee * (curl * inv_mu0 - (double)R.J[2][idx] * ju));
+      Ez[idx] = (T)(ee * (curl * inv_mu0 - (double)Jz[idx] * ju));
     }
   }
 }
@@ -860,11 +882,11 @@ __global__ __launch_bounds__(kBlock) void k_faraday(const RunDesc* __restrict__ 
                                                     const BlockMap* __restrict__ bmap, int sub) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active || sub >= R.n_sub || !(R.physics & PHYS_EVOLVE_B)) return;
+  if (!G(R.ctr)->active || sub >= R.n_sub || !(R.physics & PHYS_EVOLVE_B)) return;
   const int nx = R.nx, ny = R.ny, nz = R.nz;
   const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
-  const T* Ex = (const T*)R.E[0]; const T* Ey = (const T*)R.E[1]; const T* Ez = (const T*)R.E[2];
-  T* Bx = (T*)R.B[0]; T* By = (T*)R.B[1]; T* Bz = (T*)R.B[2];
+  const gptr<const T> Ex = G((const T*)R.E[0]), Ey = G((const T*)R.E[1]), Ez = G((const T*)R.E[2]);
+  const gptr<T> Bx = G((T*)R.B[0]), By = G((T*)R.B[1]), Bz = G((T*)R.B[2]);
   const T h = (T)(R.dt / R.n_sub / R.dx);
   const long long nn = R.nodes;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < nn; t += (long long)bm.nb * kBlock) {
@@ -887,7 +909,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
                                                  const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active || !(R.physics & PHYS_HEAT)) return;
+  if (!G(R.ctr)->active || !(R.physics & PHYS_HEAT)) return;
   const int nx = R.nx, ny = R.ny;
   const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
   const int w = R.ix_hi - R.ix_lo;
@@ -901,20 +923,21 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const int k = (int)(q / ny);
     const int c = i + nx * (j + ny * k);
     const int n = i + sx * j + sxy * k;
-    const long long* Jx = R.J[0]; const long long* Jy = R.J[1]; const long long* Jz = R.J[2];
+    const gptr<const long long> Jx = G((const long long*)R.J[0]), Jy = G((const long long*)R.J[1]),
+                                Jz = G((const long long*)R.J[2]);
     const double jx = (double)(Jx[n] + Jx[n + sx] + Jx[n + sxy] + Jx[n + sx + sxy]) * ju;
     const double jy = (double)(Jy[n] + Jy[n + 1] + Jy[n + sxy] + Jy[n + 1 + sxy]) * ju;
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
-    double Te = R.Te[c], Ti = R.Ti[c], eta = R.eta[c];
-    heat_cell(Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)R.ion_heat[c] * R.heat_unit, R.dt, dV,
+    double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = G(R.eta)[c];
+    heat_cell(Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)G(R.ion_heat)[c] * R.heat_unit, R.dt, dV,
               R.Z, R.A, R.rho, R.n_i, R.m_i, R.lambda1, R.lambda2, fixed);
-    R.Te[c] = Te;
-    R.Ti[c] = Ti;
-    R.eta[c] = eta;
+    G(R.Te)[c] = Te;
+    G(R.Ti)[c] = Ti;
+    G(R.eta)[c] = eta;
   }
 }
 
-__device__ __forceinline__ void kahan(double* s, double* c, double v) {
+__device__ __forceinline__ void kahan(gptr<double> s, gptr<double> c, double v) {
   const double y = v - *c;
   const double t = *s + y;
   *c = (t - *s) - y;
@@ -926,28 +949,29 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDesc* __restrict__
                                                      const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!R.ctr->active) return;
+  const auto ctr = G(R.ctr);
+  if (!ctr->active) return;
   const int nbin = R.nE * R.nth;
   const long long nh = 2LL * nbin + 4;
   for (long long b = (long long)bm.lb * kBlock + threadIdx.x; b < nh; b += (long long)bm.nb * kBlock) {
-    const long long x = R.acc_hist[b];
+    const long long x = G(R.acc_hist)[b];
     if (x == 0) continue;
     bool is_energy;
     if (b < nbin) is_energy = true;
     else if (b < 2 * nbin) is_energy = false;
     else is_energy = ((b - 2 * nbin) & 1) == 0;
-    kahan(&R.tot_hist[b], &R.tot_hist_c[b], (double)x * (is_energy ? R.led_unit : R.cnt_unit));
-    R.acc_hist[b] = 0;
+    kahan(G(R.tot_hist) + b, G(R.tot_hist_c) + b, (double)x * (is_energy ? R.led_unit : R.cnt_unit));
+    G(R.acc_hist)[b] = 0;
   }
   if (bm.lb == 0 && threadIdx.x < L_N) {
     const int l = threadIdx.x;
-    const long long x = R.acc_led[l];
+    const long long x = G(R.acc_led)[l];
     const double v = (double)x * R.led_unit;
-    if (x != 0) kahan(&R.tot_led[l], &R.tot_led_c[l], v);
-    R.acc_led[l] = 0;
+    if (x != 0) kahan(G(R.tot_led) + l, G(R.tot_led_c) + l, v);
+    G(R.acc_led)[l] = 0;
     if (l == L_PHOTON_THR) {
-      const long long step = R.ctr->step;
-      if (step < R.series_len) R.series[step] = v;
+      const long long step = ctr->step;
+      if (step < R.series_len) G(R.series)[step] = v;
     }
   }
 }
@@ -958,7 +982,7 @@ __global__ void k_advance(const RunDesc* __restrict__ runs, const BlockMap* __re
   const BlockMap bm = bmap[blockIdx.x];
   if (threadIdx.x != 0) return;
   const RunDesc& R = runs[bm.run];
-  Counters* c = R.ctr;
+  const gptr<Counters> c = G(R.ctr);
   if (!c->active) return;
   if (sort_step(R.sort_every, c->step)) {
     c->n_total = c->n_sorted;   // the scatter kept the alive electrons only
@@ -978,14 +1002,15 @@ __global__ void k_advance(const RunDesc* __restrict__ runs, const BlockMap* __re
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kinetic(const RunDesc* __restrict__ runs, int run) {
   const RunDesc& R = runs[run];
-  const long long n = R.ctr->n_total;
-  const PartPtrs P = R.p[R.ctr->cur];
+  const auto ctr = G(R.ctr);
+  const long long n = ctr->n_total;
+  const PartG<T> P = part_g<T>(R.p[ctr->cur]);
   double s = 0.0, cnt = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     if (P.cell[i] == kDead) continue;
-    const T ux = ((const T*)P.ux)[i], uy = ((const T*)P.uy)[i], uz = ((const T*)P.uz)[i];
+    const T ux = P.ux[i], uy = P.uy[i], uz = P.uz[i];
     const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-    s += (double)((const T*)P.wn)[i] * (u2 / (1.0 + sqrt(1.0 + u2)));
+    s += (double)P.wn[i] * (u2 / (1.0 + sqrt(1.0 + u2)));
     cnt += 1.0;
   }
   __shared__ double sm[2][kBlock];
@@ -1000,8 +1025,8 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(const RunDesc* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    R.red[2 * blockIdx.x] = sm[0][0];
-    R.red[2 * blockIdx.x + 1] = sm[1][0];
+    G(R.red)[2 * blockIdx.x] = sm[0][0];
+    G(R.red)[2 * blockIdx.x + 1] = sm[1][0];
   }
 }
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -218,7 +219,12 @@ class _TorchMemory:
             return None
 
     def _free(self, ptr, user):
-        self._torch.cuda.caching_allocator_delete(ptr)
+        # a run still open at interpreter exit is freed after torch has
+        # begun tearing down; the process releases that memory anyway
+        cuda = getattr(self._torch, "cuda", None)
+        if cuda is None or sys.is_finalizing():
+            return
+        cuda.caching_allocator_delete(ptr)
 
 
 def _device(device: int, stream=None, torch_alloc=True):
