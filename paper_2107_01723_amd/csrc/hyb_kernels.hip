@@ -241,32 +241,45 @@ constexpr int kHalo = kTile + 2;              // node span of a tile's stencils
 constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
 constexpr int kNb = 5;                        // destination tiles: home +-2 per axis
 constexpr int kNbN = kNb * kNb * kNb;         // 125
-// Electrons of a dense tile hit the same few LDS words; each accumulator
-// has kCopies interleaved copies (lane l adds into copy l % kCopies), which
-// divides the same-address serialisation of the LDS atomics by kCopies.
-constexpr int kCopies = 8;
-
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
 // (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
 // contribution to 2^24 units -- already finer than the FP32 state -- so the
-// LDS sums fit 32-bit words (one copy takes at most kBlock / kCopies = 32
-// contributions of magnitude < 2^25 for w / w_ref <= 2), which are widened to
-// the 2^40 HBM accumulators at the flush.  Every contribution is rounded the
-// same way whether it goes through LDS or straight to HBM, so the sums stay
-// independent of the electron order.
-template <typename T> struct JAcc { using type = long long; static constexpr int shift = 0; };
-template <> struct JAcc<float> { using type = int; static constexpr int shift = 16; };
+// LDS sums fit 32-bit words, which are widened to the 2^40 HBM accumulators at
+// the flush.  Every contribution is rounded the same way whether it goes
+// through LDS or straight to HBM, so the sums stay independent of the
+// electron order.
+//
+// Electrons of a dense tile hit the same few LDS words; each accumulator has
+// `copies` interleaved copies (lane l adds into copy l % copies), which
+// divides the same-address serialisation of the LDS atomics.  With 8 copies
+// one 32-bit word takes at most kBlock / 8 = 32 contributions of magnitude
+// below 2^25 (w / w_ref <= 2), so it cannot overflow.
+template <typename T> struct JAcc {
+  using type = long long;
+  static constexpr int shift = 0, copies = 4;
+};
+template <> struct JAcc<float> {
+  using type = int;
+  static constexpr int shift = 16, copies = 8;
+};
+constexpr int kHeatCopies = 4;
+constexpr int kNoTile = 0x7FFFFFFF;
 
+// A chunk has two home tiles: the smallest and the largest tile among its
+// electrons.  The electrons of a tile-sorted chunk of kBlock rarely span
+// more than two tiles, so nearly all of them deposit into LDS; the homes'
+// tile indices are reduced into a pair of slots that alternate between
+// chunks, so that a chunk's reduction never races the previous chunk's reads.
 template <typename T>
 struct ChunkLds {
-  typename JAcc<T>::type J[3 * kHaloN * kCopies];
-  long long heat[kTile * kTile * kTile * kCopies];
+  typename JAcc<T>::type J[2][3 * kHaloN * JAcc<T>::copies];
+  long long heat[2][kTile * kTile * kTile * kHeatCopies];
   unsigned cnt[kNbN];
-  int home;
+  int lo[2], hi[2];
 };
 
 struct Home {
-  int ok;                 // chunk has an alive electron
+  int ok;                 // the tile exists (the chunk has an alive electron)
   int tx, ty, tz;         // home tile
   int bx, by, bz;         // first node of the home tile's halo
 };
@@ -277,7 +290,7 @@ __device__ __forceinline__ int tile_of(const RunDesc& R, int i, int j, int k) {
 
 __device__ __forceinline__ Home make_home(const RunDesc& R, int t) {
   Home h;
-  h.ok = t != 0x7FFFFFFF;
+  h.ok = t >= 0 && t != kNoTile;
   if (!h.ok) t = 0;
   h.tx = t % R.ntx;
   const int q = t / R.ntx;
@@ -297,21 +310,27 @@ __device__ __forceinline__ int nb_bin(const Home& h, int tx, int ty, int tz) {
 }
 
 template <typename T>
-__device__ __forceinline__ void lds_clear(ChunkLds<T>& L) {
-  for (int t = threadIdx.x; t < 3 * kHaloN * kCopies; t += kBlock) L.J[t] = 0;
-  for (int t = threadIdx.x; t < kTile * kTile * kTile * kCopies; t += kBlock) L.heat[t] = 0;
+__device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
+  for (int t = threadIdx.x; t < 2 * 3 * kHaloN * JAcc<T>::copies; t += kBlock) (&L.J[0][0])[t] = 0;
+  for (int t = threadIdx.x; t < 2 * kTile * kTile * kTile * kHeatCopies; t += kBlock) (&L.heat[0][0])[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
-  if (threadIdx.x == 0) L.home = 0x7FFFFFFF;
+  if (threadIdx.x < 2) { L.lo[threadIdx.x] = kNoTile; L.hi[threadIdx.x] = -1; }
 }
 
+// Adds the LDS sums of one home region to HBM (one atomic per non-zero
+// entry) and clears them for the next chunk.
 template <typename T>
-__device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds<T>& L, const Home& h, bool count) {
-  if (!h.ok) return;
+__device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& L, int r, const Home& h) {
+  constexpr int C = JAcc<T>::copies;
   const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
+  typename JAcc<T>::type* J = L.J[r];
   for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
     long long v = 0;
 #pragma unroll
-    for (int q = 0; q < kCopies; ++q) v += (long long)L.J[t * kCopies + q];
+    for (int q = 0; q < C; ++q) {
+      v += (long long)J[t * C + q];
+      J[t * C + q] = 0;
+    }
     if (v == 0) continue;
     v *= (1LL << JAcc<T>::shift);
     const int c = t / kHaloN, l = t % kHaloN;
@@ -322,13 +341,22 @@ __device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds<T>& L, cons
   if (threadIdx.x < kTile * kTile * kTile) {
     long long v = 0;
 #pragma unroll
-    for (int q = 0; q < kCopies; ++q) v += L.heat[threadIdx.x * kCopies + q];
+    for (int q = 0; q < kHeatCopies; ++q) {
+      v += L.heat[r][threadIdx.x * kHeatCopies + q];
+      L.heat[r][threadIdx.x * kHeatCopies + q] = 0;
+    }
     const int l = threadIdx.x;
     const int i = kTile * h.tx + (l & 3), j = kTile * h.ty + ((l >> 2) & 3), k = kTile * h.tz + (l >> 4);
     if (v != 0 && i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.ion_heat[i + R.nx * (j + R.ny * k)], v);
   }
-  if (count && threadIdx.x < kNbN) {
+}
+
+// destination counts of the chunk (bins around home tile h) to HBM, cleared
+template <typename T>
+__device__ __forceinline__ void lds_flush_counts(const RunDesc& R, ChunkLds<T>& L, const Home& h) {
+  if (threadIdx.x < kNbN) {
     const unsigned v = L.cnt[threadIdx.x];
+    L.cnt[threadIdx.x] = 0;
     const int l = threadIdx.x;
     const int tx = h.tx + l % kNb - 2, ty = h.ty + (l / kNb) % kNb - 2, tz = h.tz + l / (kNb * kNb) - 2;
     if (v != 0 && tx >= 0 && ty >= 0 && tz >= 0 && tx < R.ntx && ty < R.nty && tz < R.ntz)
@@ -336,7 +364,7 @@ __device__ __forceinline__ void lds_flush(const RunDesc& R, ChunkLds<T>& L, cons
   }
 }
 
-// deposit of one current component: 8 corners to LDS (home tile) or HBM
+// deposit of one current component: 8 corners to LDS (a home tile) or HBM
 __device__ __forceinline__ void lds_add(long long* p, long long v) {
   atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
@@ -344,28 +372,31 @@ __device__ __forceinline__ void lds_add(int* p, int v) { atomicAdd(p, v); }
 __device__ __forceinline__ long long jfix(double x) { return to_fixed(x); }
 __device__ __forceinline__ int jfix(float x) { return __float2int_rn(x); }
 
+// Js: the component's LDS block of the electron's home region (first halo
+// node bx, by, bz), or null for a deposit straight to HBM.
 template <typename T>
 __device__ __forceinline__ void deposit8(long long* __restrict__ J, typename JAcc<T>::type* __restrict__ Js,
-                                         bool local, const Home& h, int sx, int sxy, const Axis<T>& ax,
+                                         int bx, int by, int bz, int sx, int sxy, const Axis<T>& ax,
                                          const Axis<T>& ay, const Axis<T>& az, T amp) {
   using A = typename JAcc<T>::type;
+  constexpr int C = JAcc<T>::copies;
   const T a00 = amp * az.w0 * ay.w0, a10 = amp * az.w0 * ay.w1;
   const T a01 = amp * az.w1 * ay.w0, a11 = amp * az.w1 * ay.w1;
   const A v[8] = {jfix(a00 * ax.w0), jfix(a00 * ax.w1), jfix(a10 * ax.w0), jfix(a10 * ax.w1),
                   jfix(a01 * ax.w0), jfix(a01 * ax.w1), jfix(a11 * ax.w0), jfix(a11 * ax.w1)};
-  if (local) {
-    const int q = threadIdx.x & (kCopies - 1);
-    const int i0 = ax.i0 - h.bx, i1 = ax.i1 - h.bx;
-    const int j0 = (ay.i0 - h.by) * kHalo, j1 = (ay.i1 - h.by) * kHalo;
-    const int k0 = (az.i0 - h.bz) * kHalo * kHalo, k1 = (az.i1 - h.bz) * kHalo * kHalo;
-    lds_add(&Js[(i0 + j0 + k0) * kCopies + q], v[0]);
-    lds_add(&Js[(i1 + j0 + k0) * kCopies + q], v[1]);
-    lds_add(&Js[(i0 + j1 + k0) * kCopies + q], v[2]);
-    lds_add(&Js[(i1 + j1 + k0) * kCopies + q], v[3]);
-    lds_add(&Js[(i0 + j0 + k1) * kCopies + q], v[4]);
-    lds_add(&Js[(i1 + j0 + k1) * kCopies + q], v[5]);
-    lds_add(&Js[(i0 + j1 + k1) * kCopies + q], v[6]);
-    lds_add(&Js[(i1 + j1 + k1) * kCopies + q], v[7]);
+  if (Js) {
+    const int q = threadIdx.x & (C - 1);
+    const int i0 = ax.i0 - bx, i1 = ax.i1 - bx;
+    const int j0 = (ay.i0 - by) * kHalo, j1 = (ay.i1 - by) * kHalo;
+    const int k0 = (az.i0 - bz) * kHalo * kHalo, k1 = (az.i1 - bz) * kHalo * kHalo;
+    lds_add(&Js[(i0 + j0 + k0) * C + q], v[0]);
+    lds_add(&Js[(i1 + j0 + k0) * C + q], v[1]);
+    lds_add(&Js[(i0 + j1 + k0) * C + q], v[2]);
+    lds_add(&Js[(i1 + j1 + k0) * C + q], v[3]);
+    lds_add(&Js[(i0 + j0 + k1) * C + q], v[4]);
+    lds_add(&Js[(i1 + j0 + k1) * C + q], v[5]);
+    lds_add(&Js[(i0 + j1 + k1) * C + q], v[6]);
+    lds_add(&Js[(i1 + j1 + k1) * C + q], v[7]);
   } else {
     constexpr long long up = 1LL << JAcc<T>::shift;
     const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
@@ -430,9 +461,10 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
   const T twopi = (T)(2.0 * kPi);
 
   const ChunkRange cr = chunk_range(bm, n);
-  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride) {
-    lds_clear(S);
-    __syncthreads();
+  lds_init(S);
+  __syncthreads();
+  int slot = 0;
+  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
     const long long i = ch * kBlock + threadIdx.x;
     const uint32_t cell = i < n ? P.cell[i] : kDead;
     int ci = 0, cj = 0, ck = 0, my_tile = -1;
@@ -441,16 +473,29 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
       my_tile = tile_of(R, ci, cj, ck);
     }
     {
-      int m = cell != kDead ? my_tile : 0x7FFFFFFF;
+      int lo = cell != kDead ? my_tile : kNoTile, hi = my_tile;
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
-      if ((threadIdx.x & 63) == 0 && m != 0x7FFFFFFF) atomicMin(&S.home, m);
+      for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        if (lo != kNoTile) atomicMin(&S.lo[slot], lo);
+        if (hi >= 0) atomicMax(&S.hi[slot], hi);
+      }
     }
     __syncthreads();
-    const Home hm = make_home(R, S.home);
+    const int tlo = __builtin_amdgcn_readfirstlane(S.lo[slot]);
+    const int thi = __builtin_amdgcn_readfirstlane(S.hi[slot]);
+    // the other slot was last read before the previous chunk's flush
+    if (threadIdx.x == 0) { S.lo[slot ^ 1] = kNoTile; S.hi[slot ^ 1] = -1; }
+    const Home hm = make_home(R, tlo), hm2 = make_home(R, thi);
     int dest_bin = -1;
     if (cell != kDead) {
-      const bool local = my_tile == S.home;
+      // home region of the electron: 0 (smallest tile), 1 (largest), -1 none
+      const int reg = my_tile == tlo ? 0 : (my_tile == thi ? 1 : -1);
+      const int rbx = reg == 1 ? hm2.bx : hm.bx, rby = reg == 1 ? hm2.by : hm.by, rbz = reg == 1 ? hm2.bz : hm.bz;
+      typename JAcc<T>::type* Js = reg >= 0 ? S.J[reg] : nullptr;
       const int heat_cell = ci + nx * (cj + ny * ck);
       const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
       T ox = P.ox[i], oy = P.oy[i], oz = P.oz[i];
@@ -499,9 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
       // --- hot-current deposit at x^n with the pushed velocity ---
       {
         const T amp = -wn * (T)(kJScale / (double)(1LL << JAcc<T>::shift));
-        deposit8(R.J[0], S.J, local, hm, sx, sxy, sxa, nya, nza, amp * vx);
-        deposit8(R.J[1], S.J + kHaloN * kCopies, local, hm, sx, sxy, nxa, sya, nza, amp * vy);
-        deposit8(R.J[2], S.J + 2 * kHaloN * kCopies, local, hm, sx, sxy, nxa, nya, sza, amp * vz);
+        constexpr int CN = kHaloN * JAcc<T>::copies;
+        deposit8(R.J[0], Js, rbx, rby, rbz, sx, sxy, sxa, nya, nza, amp * vx);
+        deposit8(R.J[1], Js ? Js + CN : Js, rbx, rby, rbz, sx, sxy, nxa, sya, nza, amp * vy);
+        deposit8(R.J[2], Js ? Js + 2 * CN : Js, rbx, rby, rbz, sx, sxy, nxa, nya, sza, amp * vz);
       }
 
       // --- move ---
@@ -617,9 +663,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
         alive = false;
       }
       if (heat != 0) {
-        if (local)
-          atomicAdd((unsigned long long*)&S.heat[heat_local * kCopies + (threadIdx.x & (kCopies - 1))],
-                    (unsigned long long)heat);
+        if (reg >= 0)
+          lds_add(&S.heat[reg][heat_local * kHeatCopies + (threadIdx.x & (kHeatCopies - 1))], heat);
         else atomic_add_i64(&R.ion_heat[heat_cell], heat);
       }
       if (!alive) {
@@ -645,8 +690,11 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
       if (dest_bin >= 0 && dest_bin != lead) atomicAdd(&S.cnt[dest_bin], 1u);
     }
     __syncthreads();
-    lds_flush(R, S, hm, count);
-    __syncthreads();
+    // LDS sums to HBM; the flush also clears them, and the next chunk writes
+    // LDS only after its own barrier
+    if (hm.ok) lds_flush_region(R, S, 0, hm);
+    if (hm2.ok && thi != tlo) lds_flush_region(R, S, 1, hm2);
+    if (count) lds_flush_counts(R, S, hm);
   }
   block_flush<L_N, C_N>(acc, R.acc_led, R.events);
 }
