@@ -17,6 +17,12 @@ namespace hyb {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
+// integer adds into LDS words
+__device__ __forceinline__ void lds_add(long long* p, long long v) {
+  atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void lds_add(int* p, int v) { atomicAdd(p, v); }
+
 // Number of electrons sources inject at `step`, and per-source first id.
 __device__ __forceinline__ long long inject_count(const RunDesc& R, long long step,
                                                   long long* cnt = nullptr, long long* first = nullptr) {
@@ -35,9 +41,10 @@ __device__ __forceinline__ long long inject_count(const RunDesc& R, long long st
 
 // Block-wide sum of per-thread integer accumulators, then one atomic per
 // non-zero term: ledger terms to `led`, event counts to `evt`.
+// `extra`, if given, holds block-wide LDS sums of the same terms.
 template <int NL, int NC>
 __device__ __forceinline__ void block_flush(const long long (&v)[NL + NC], long long* __restrict__ led,
-                                            long long* __restrict__ evt) {
+                                            long long* __restrict__ evt, const long long* extra = nullptr) {
   __shared__ long long sm[kWaves][NL + NC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -52,6 +59,7 @@ __device__ __forceinline__ void block_flush(const long long (&v)[NL + NC], long 
     long long s = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += sm[w][threadIdx.x];
+    if (extra) s += extra[threadIdx.x];
     if (s != 0) {
       long long* dst = threadIdx.x < NL ? &led[threadIdx.x] : &evt[threadIdx.x - NL];
       atomic_add_i64(dst, s);
@@ -176,16 +184,16 @@ __device__ __forceinline__ T gather8(gptr<const T> F, int sx, int sxy, const Axi
 template <typename T>
 __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c, T& o, int lo, int hi,
                                               T& ux, T& uy, T& uz, T& eps, T wn, uint32_t id,
-                                              long long step, long long (&acc)[L_N + C_N]) {
+                                              long long step, long long* led) {
   const bool below = c < lo;
   const bool above = c >= hi;
   if (!(below || above)) return true;
   if (eps > (T)R.eps_esc) {
-    acc[L_ESCAPED] += to_fixed(eps * wn * (T)kLedScale);
-    acc[L_N + C_ESCAPED] += 1;
+    lds_add(&led[L_ESCAPED], to_fixed(eps * wn * (T)kLedScale));
+    lds_add(&led[L_N + C_ESCAPED], 1LL);
     return false;
   }
-  acc[L_N + C_REFLUX] += 1;
+  lds_add(&led[L_N + C_REFLUX], 1LL);
   // mirror about the face, then clamp into [lo, hi)
   int c2 = (below ? 2 * lo : 2 * hi) - c - 1;
   T o2 = (T)1 - o;
@@ -205,7 +213,7 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   } else {
     const T um2 = um - (T)R.du_tnsa;
     if (!(um2 > (T)0)) {
-      acc[L_REFLUX] += to_fixed(eps * wn * (T)kLedScale);
+      lds_add(&led[L_REFLUX], to_fixed(eps * wn * (T)kLedScale));
       return false;
     }
     scale = um2 / um;
@@ -213,14 +221,14 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   ux *= scale; uy *= scale; uz *= scale;
   const T u2 = ux * ux + uy * uy + uz * uz;
   const T eps_a = kinetic(u2, m_sqrt((T)1 + u2));
-  acc[L_REFLUX] += to_fixed((eps - eps_a) * wn * (T)kLedScale);
+  lds_add(&led[L_REFLUX], to_fixed((eps - eps_a) * wn * (T)kLedScale));
   eps = eps_a;
   if (u2 > (T)0) {
     const Uni4<T> rd = draws<T>(id, R.seed, step, SLOT_REFLUX0 + (uint32_t)axis);
     rotate(ux, uy, uz, (rd.a - (T)0.5) * (T)R.sigma_dth, (T)(2.0 * kPi) * rd.b);
     const T v2 = ux * ux + uy * uy + uz * uz;
     const T eps_r = kinetic(v2, m_sqrt((T)1 + v2));
-    acc[L_RESIDUAL] += to_fixed((eps - eps_r) * wn * (T)kLedScale);
+    lds_add(&led[L_RESIDUAL], to_fixed((eps - eps_r) * wn * (T)kLedScale));
     eps = eps_r;
   }
   T& un2 = axis == 0 ? ux : (axis == 1 ? uy : uz);
@@ -276,6 +284,8 @@ struct ChunkLds {
   long long heat[2][kTile * kTile * kTile * kHeatCopies];
   unsigned cnt[kNbN];
   int lo[2], hi[2];
+  long long led[L_N + C_N];   // rare ledger terms and event counts of the block
+  T ph[6][kBlock];            // emitted photon of each lane: k, u (3), |u|, gamma
 };
 
 struct Home {
@@ -315,6 +325,7 @@ __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
   for (int t = threadIdx.x; t < 2 * kTile * kTile * kTile * kHeatCopies; t += kBlock) (&L.heat[0][0])[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x < 2) { L.lo[threadIdx.x] = kNoTile; L.hi[threadIdx.x] = -1; }
+  if (threadIdx.x < L_N + C_N) L.led[threadIdx.x] = 0;
 }
 
 // Adds the LDS sums of one home region to HBM (one atomic per non-zero
@@ -365,10 +376,6 @@ __device__ __forceinline__ void lds_flush_counts(const RunDesc& R, ChunkLds<T>& 
 }
 
 // deposit of one current component: 8 corners to LDS (a home tile) or HBM
-__device__ __forceinline__ void lds_add(long long* p, long long v) {
-  atomicAdd((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ void lds_add(int* p, int v) { atomicAdd(p, v); }
 __device__ __forceinline__ long long jfix(double x) { return to_fixed(x); }
 __device__ __forceinline__ int jfix(float x) { return __float2int_rn(x); }
 
@@ -412,6 +419,43 @@ __device__ __forceinline__ void deposit8(long long* __restrict__ J, typename JAc
   }
 }
 
+// Tally of one photon (Sec. II.C, Table I bins): emitted at energy k about
+// the electron direction u (|u| = um, Lorentz factor g), weight wn / boost.
+template <typename T>
+__device__ __forceinline__ void photon_tally(const RunDesc& R, ChunkLds<T>& S, T wn, uint32_t id, long long step) {
+  const int t = threadIdx.x;
+  const T kph = S.ph[0][t], um = S.ph[4][t], g = S.ph[5][t];
+  T dxp = S.ph[1][t], dyp = S.ph[2][t], dzp = S.ph[3][t];
+  const Uni4<T> pd = draws<T>(id, R.seed, step, SLOT_PHOTON);
+  // photon direction about the electron direction
+  T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
+  th = th < (T)kPi ? th : (T)kPi;
+  rotate(dxp, dyp, dzp, th, (T)(2.0 * kPi) * pd.b);
+  T cx = dxp / um;
+  cx = cx > (T)1 ? (T)1 : (cx < (T)-1 ? (T)-1 : cx);
+  const T tq = m_acos(cx) * (T)R.nth * (T)(1.0 / kPi);
+  const int it = tq >= (T)0 ? (tq < (T)(R.nth - 1) ? (int)tq : R.nth - 1) : 0;
+  const T eq = (m_log(kph) - (T)R.ln_Elo) * (T)R.e_bin_scale;
+  const int ie = !(eq >= (T)0) ? -1 : (eq >= (T)R.nE ? R.nE : (int)eq);
+  const T wph = wn * (T)R.inv_boost;
+  const long long vE = to_fixed(kph * wph * (T)kLedScale);
+  const long long vN = to_fixed(wph * (T)kLedScale);
+  const int nbin = R.nE * R.nth;
+  if (ie < 0) {
+    atomic_add_i64(&R.acc_hist[2 * nbin + 0], vE);
+    atomic_add_i64(&R.acc_hist[2 * nbin + 1], vN);
+  } else if (ie >= R.nE) {
+    atomic_add_i64(&R.acc_hist[2 * nbin + 2], vE);
+    atomic_add_i64(&R.acc_hist[2 * nbin + 3], vN);
+  } else {
+    atomic_add_i64(&R.acc_hist[ie * R.nth + it], vE);
+    atomic_add_i64(&R.acc_hist[nbin + ie * R.nth + it], vN);
+  }
+  if (kph >= (T)R.Ethr) lds_add(&S.led[L_PHOTON_THR], vE);
+  lds_add(&S.led[L_RAD_D], vE);
+  lds_add(&S.led[L_N + C_EMITTED], 1LL);
+}
+
 // XCD-aware chunk range of a workgroup: workgroup b runs on XCD b % 8, so
 // each XCD gets one contiguous eighth of the (tile-sorted) chunks.
 struct ChunkRange { long long beg, end, stride; };
@@ -431,8 +475,10 @@ __device__ __forceinline__ ChunkRange chunk_range(const BlockMap& bm, long long 
 // the particle step: gather, Boris, deposit, move, ionisation,
 // bremsstrahlung, Davies scatter, boundaries, low-energy removal
 // ---------------------------------------------------------------------------
+template <typename T> struct PartOcc { static constexpr int waves = 2; };
+template <> struct PartOcc<float> { static constexpr int waves = 3; };
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__ runs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<T>::waves))) void k_particle(const RunDesc* __restrict__ runs,
                                                      const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   if (bm.nb < 8) return;   // alignment padding between runs
@@ -581,6 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
       Uni4<T> cd{};
       if (phys & (PHYS_BREM | PHYS_SCATTER)) cd = draws<T>(id, R.seed, step, SLOT_COLLIDE);
       T eps3 = eps2;
+      bool emitted = false;
       if ((phys & PHYS_BREM) && u2 > (T)0) {
         const T lne = m_log(eps2);
         const T um = m_sqrt(u2);
@@ -590,36 +637,11 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
         T kph = (T)0;
         if (tau < (T)0) {
           kph = tab.sample_k(eps2, lne, cd.d);
-          const Uni4<T> pd = draws<T>(id, R.seed, step, SLOT_PHOTON);
-          tau = -m_log((T)1 - pd.c);
-          // photon direction about the electron direction
-          T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
-          th = th < (T)kPi ? th : (T)kPi;
-          T dxp = ux, dyp = uy, dzp = uz;
-          rotate(dxp, dyp, dzp, th, twopi * pd.b);
-          T cx = dxp / um;
-          cx = cx > (T)1 ? (T)1 : (cx < (T)-1 ? (T)-1 : cx);
-          const T tq = m_acos(cx) * (T)R.nth * (T)(1.0 / kPi);
-          const int it = tq >= (T)0 ? (tq < (T)(R.nth - 1) ? (int)tq : R.nth - 1) : 0;
-          const T eq = (m_log(kph) - (T)R.ln_Elo) * (T)R.e_bin_scale;
-          const int ie = !(eq >= (T)0) ? -1 : (eq >= (T)R.nE ? R.nE : (int)eq);
-          const T wph = wn * (T)R.inv_boost;
-          const long long vE = to_fixed(kph * wph * ledS);
-          const long long vN = to_fixed(wph * ledS);
-          const int nbin = R.nE * R.nth;
-          if (ie < 0) {
-            atomic_add_i64(&R.acc_hist[2 * nbin + 0], vE);
-            atomic_add_i64(&R.acc_hist[2 * nbin + 1], vN);
-          } else if (ie >= R.nE) {
-            atomic_add_i64(&R.acc_hist[2 * nbin + 2], vE);
-            atomic_add_i64(&R.acc_hist[2 * nbin + 3], vN);
-          } else {
-            atomic_add_i64(&R.acc_hist[ie * R.nth + it], vE);
-            atomic_add_i64(&R.acc_hist[nbin + ie * R.nth + it], vN);
-          }
-          if (kph >= (T)R.Ethr) acc[L_PHOTON_THR] += vE;
-          acc[L_RAD_D] += vE;
-          acc[L_N + C_EMITTED] += 1;
+          tau = -m_log((T)1 - draws<T>(id, R.seed, step, SLOT_PHOTON).c);
+          // the photon's tally waits in LDS for the end of this electron's step
+          const int t = threadIdx.x;
+          S.ph[0][t] = kph; S.ph[1][t] = ux; S.ph[2][t] = uy; S.ph[3][t] = uz; S.ph[4][t] = um; S.ph[5][t] = g;
+          emitted = true;
         }
         const T kb = kph * (T)R.inv_boost;
         const T room = eps2 - kb;                   // >= 0: k <= eps2, boost >= 1
@@ -651,14 +673,14 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
 
       // --- boundaries: x (slab faces), y, z (domain walls) ---
       T eps = eps3;
-      bool alive = boundary_axis(R, 0, ci, ox, R.ix_lo, R.ix_hi, ux, uy, uz, eps, wn, id, step, acc);
-      if (alive) alive = boundary_axis(R, 1, cj, oy, 0, ny, ux, uy, uz, eps, wn, id, step, acc);
-      if (alive) alive = boundary_axis(R, 2, ck, oz, 0, nz, ux, uy, uz, eps, wn, id, step, acc);
+      bool alive = boundary_axis(R, 0, ci, ox, R.ix_lo, R.ix_hi, ux, uy, uz, eps, wn, id, step, S.led);
+      if (alive) alive = boundary_axis(R, 1, cj, oy, 0, ny, ux, uy, uz, eps, wn, id, step, S.led);
+      if (alive) alive = boundary_axis(R, 2, ck, oz, 0, nz, ux, uy, uz, eps, wn, id, step, S.led);
 
       // --- removal below e_min, energy to the cell's heat ---
       if (alive && eps < (T)R.e_min) {
-        acc[L_STOPPED] += to_fixed(eps * wn * ledS);
-        acc[L_N + C_STOPPED] += 1;
+        lds_add(&S.led[L_STOPPED], to_fixed(eps * wn * ledS));
+        lds_add(&S.led[L_N + C_STOPPED], 1LL);
         heat += to_fixed(eps * wn * (T)kHeatScale);
         alive = false;
       }
@@ -680,6 +702,13 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
           if (dest_bin < 0) atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
         }
       }
+      if (emitted) {
+        // emission is rare: its tally runs here, where little of the
+        // electron's state is still live; the empty asm keeps the compiler
+        // from carrying the queued values in registers instead of LDS
+        asm volatile("" ::: "memory");
+        photon_tally(R, S, wn, id, step);
+      }
     }
     if (count) {
       // most electrons of a chunk land in one tile: count it with one atomic
@@ -696,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_particle(const RunDesc* __restrict__
     if (hm2.ok && thi != tlo) lds_flush_region(R, S, 1, hm2);
     if (count) lds_flush_counts(R, S, hm);
   }
-  block_flush<L_N, C_N>(acc, R.acc_led, R.events);
+  block_flush<L_N, C_N>(acc, R.acc_led, R.events, S.led);
 }
 
 // ---------------------------------------------------------------------------
