@@ -29,6 +29,11 @@ constexpr int kRedBlocks = 1024;   // partial-sum slots of the kinetic reduction
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// words per copy of the photon-tally accumulators (rounded to 128 bytes)
+size_t hist_stride(const hyb_config& c) {
+  return align_up(2 * (size_t)c.tally_nE * c.tally_ntheta + 4, 16);
+}
+
 // Sizes of everything a run keeps in device memory.
 struct Layout {
   size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta, off_heat;
@@ -65,7 +70,7 @@ Layout make_layout(const hyb_config& c) {
   L.off_tabSUB = take((size_t)c.table_nT * ts);
   const size_t nh = 2 * (size_t)c.tally_nE * c.tally_ntheta + 4;
   L.off_acc_led = take(16 * 8);
-  L.off_acc_hist = take(nh * 8);
+  L.off_acc_hist = take(hist_stride(c) * kHistCopies * 8);
   L.off_events = take(16 * 8);
   L.off_tot_led = take(16 * 8);
   L.off_tot_led_c = take(16 * 8);
@@ -254,6 +259,7 @@ static void fill_desc(hyb_run* r) {
   h.ntz = (c.nz + kTile - 1) / kTile;
   h.ntiles = h.ntx * h.nty * h.ntz;
   h.scan_nblk = (h.ntiles + kScanTile - 1) / kScanTile;
+  h.hist_stride = (long long)hist_stride(c);
   set_units(h, r->w_ref > 0 ? r->w_ref : 1.0);
   r->solid_cells = (int64_t)(h.ix_hi - h.ix_lo) * c.ny * c.nz;
 }
@@ -885,7 +891,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   if (st->eta) HIPCHK(r, hipMemcpy(r->h.eta, st->eta, cells * 8, hipMemcpyHostToDevice));
   HIPCHK(r, hipMemset(r->h.ion_heat, 0, cells * 8));
   HIPCHK(r, hipMemset(r->h.acc_led, 0, 16 * 8));
-  HIPCHK(r, hipMemset(r->h.acc_hist, 0, (2 * (size_t)c.tally_nE * c.tally_ntheta + 4) * 8));
+  HIPCHK(r, hipMemset(r->h.acc_hist, 0, hist_stride(c) * kHistCopies * 8));
   Counters ctr{};
   ctr.n_total = (long long)n;
   ctr.step = st->step;

@@ -126,7 +126,8 @@ struct RunDesc {
   Counters* ctr;
   const SourceDesc* src;
   long long* acc_led;       // [L_N] this step
-  long long* acc_hist;      // [2*nE*nth + 4] this step: energy bins, number bins, flow
+  long long* acc_hist;      // [kHistCopies][hist_stride] this step: energy bins, number bins, flow
+  long long hist_stride;    // >= 2*nE*nth + 4, in words
   long long* events;        // [C_N] whole run
   double* tot_led; double* tot_led_c;     // Kahan sum and compensation
   double* tot_hist; double* tot_hist_c;
@@ -143,6 +144,11 @@ struct RunDesc {
 };
 
 constexpr int kTile = 4;           // tile edge in cells
+// Photon tallies are accumulated in this many copies (workgroup b adds into
+// copy b % kHistCopies), so that the memory-side atomics on the few hot bins
+// of the spectrum do not all queue on one address; the step's finalisation
+// sums the copies.
+constexpr int kHistCopies = 32;
 constexpr int kScanTile = 1024;    // tiles per scan block
 
 // Does the step `step` end with a tile sort?
@@ -293,9 +299,9 @@ struct TableView {
     int j; T f; row(lneps, j, f);
     return SUB[j] + f * (SUB[j + 1] - SUB[j]);
   }
-  // photon energy for an electron of kinetic energy eps > k_cut and variate r
-  __device__ __forceinline__ T sample_k(T eps, T lneps, T r) const {
-    int j; T f; row(lneps, j, f);
+  // exponent of the inverse CDF at row j (fraction f) and variate r: the
+  // photon energy is k_cut exp(x (ln eps - ln k_cut))
+  __device__ __forceinline__ T x_at(int j, T f, T r) const {
     const T q = r * (T)(nr - 1);
     int i = (int)m_floor(q);
     i = i > nr - 2 ? nr - 2 : i;
@@ -304,8 +310,12 @@ struct TableView {
     const gptr<const T> r1 = r0 + nr;
     const T x0 = r0[i] + g * (r0[i + 1] - r0[i]);
     const T x1 = r1[i] + g * (r1[i + 1] - r1[i]);
-    const T x = x0 + f * (x1 - x0);
-    return kcut * m_exp(x * (lneps - ln_kcut));
+    return x0 + f * (x1 - x0);
+  }
+  // photon energy for an electron of kinetic energy eps > k_cut and variate r
+  __device__ __forceinline__ T sample_k(T eps, T lneps, T r) const {
+    int j; T f; row(lneps, j, f);
+    return kcut * m_exp(x_at(j, f, r) * (lneps - ln_kcut));
   }
 };
 

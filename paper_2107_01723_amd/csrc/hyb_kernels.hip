@@ -271,6 +271,7 @@ template <> struct JAcc<float> {
   static constexpr int shift = 16, copies = 8;
 };
 constexpr int kHeatCopies = 4;
+constexpr int kLdsTab = 128;   // table rows staged in LDS
 constexpr int kNoTile = 0x7FFFFFFF;
 
 // A chunk has two home tiles: the smallest and the largest tile among its
@@ -286,6 +287,7 @@ struct ChunkLds {
   int lo[2], hi[2];
   long long led[L_N + C_N];   // rare ledger terms and event counts of the block
   T ph[6][kBlock];            // emitted photon of each lane: k, u (3), |u|, gamma
+  T tsig[kLdsTab], tsub[kLdsTab];   // cross-section columns of the tables, if they fit
 };
 
 struct Home {
@@ -441,15 +443,16 @@ __device__ __forceinline__ void photon_tally(const RunDesc& R, ChunkLds<T>& S, T
   const long long vE = to_fixed(kph * wph * (T)kLedScale);
   const long long vN = to_fixed(wph * (T)kLedScale);
   const int nbin = R.nE * R.nth;
+  long long* hist = R.acc_hist + (blockIdx.x & (kHistCopies - 1)) * R.hist_stride;
   if (ie < 0) {
-    atomic_add_i64(&R.acc_hist[2 * nbin + 0], vE);
-    atomic_add_i64(&R.acc_hist[2 * nbin + 1], vN);
+    atomic_add_i64(&hist[2 * nbin + 0], vE);
+    atomic_add_i64(&hist[2 * nbin + 1], vN);
   } else if (ie >= R.nE) {
-    atomic_add_i64(&R.acc_hist[2 * nbin + 2], vE);
-    atomic_add_i64(&R.acc_hist[2 * nbin + 3], vN);
+    atomic_add_i64(&hist[2 * nbin + 2], vE);
+    atomic_add_i64(&hist[2 * nbin + 3], vN);
   } else {
-    atomic_add_i64(&R.acc_hist[ie * R.nth + it], vE);
-    atomic_add_i64(&R.acc_hist[nbin + ie * R.nth + it], vN);
+    atomic_add_i64(&hist[ie * R.nth + it], vE);
+    atomic_add_i64(&hist[nbin + ie * R.nth + it], vN);
   }
   if (kph >= (T)R.Ethr) lds_add(&S.led[L_PHOTON_THR], vE);
   lds_add(&S.led[L_RAD_D], vE);
@@ -508,15 +511,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
 
   const ChunkRange cr = chunk_range(bm, n);
   lds_init(S);
+  const bool lds_tab = R.tab_nT <= kLdsTab;
+  if (lds_tab)
+    for (int t = threadIdx.x; t < R.tab_nT; t += kBlock) {
+      S.tsig[t] = tab.SIG[t];
+      S.tsub[t] = tab.SUB[t];
+    }
   __syncthreads();
+  uint32_t cell_next = kDead;   // packed cell of this thread's electron in the next chunk
+  if (cr.beg < cr.end && cr.beg * kBlock + threadIdx.x < n) cell_next = P.cell[cr.beg * kBlock + threadIdx.x];
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
     const long long i = ch * kBlock + threadIdx.x;
-    const uint32_t cell = i < n ? P.cell[i] : kDead;
+    const uint32_t cell = cell_next;
+    {
+      const long long in = (ch + cr.stride) * kBlock + threadIdx.x;
+      cell_next = ch + cr.stride < cr.end && in < n ? P.cell[in] : kDead;
+    }
     int ci = 0, cj = 0, ck = 0, my_tile = -1;
+    // the electron's state is in flight while the chunk's homes are reduced
+    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0;
+    uint32_t id = 0;
     if (cell != kDead) {
       ci = cell_i(cell); cj = cell_j(cell); ck = cell_k(cell);
       my_tile = tile_of(R, ci, cj, ck);
+      ox = P.ox[i]; oy = P.oy[i]; oz = P.oz[i];
+      ux = P.ux[i]; uy = P.uy[i]; uz = P.uz[i];
+      wn = P.wn[i]; tau = P.tau[i]; id = P.id[i];
     }
     {
       int lo = cell != kDead ? my_tile : kNoTile, hi = my_tile;
@@ -544,11 +565,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       typename JAcc<T>::type* Js = reg >= 0 ? S.J[reg] : nullptr;
       const int heat_cell = ci + nx * (cj + ny * ck);
       const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
-      T ox = P.ox[i], oy = P.oy[i], oz = P.oz[i];
-      T ux = P.ux[i], uy = P.uy[i], uz = P.uz[i];
-      const T wn = P.wn[i];
-      T tau = P.tau[i];
-      const uint32_t id = P.id[i];
 
       T u2 = ux * ux + uy * uy + uz * uz;
       const T eps0 = kinetic(u2, m_sqrt((T)1 + u2));
@@ -630,13 +646,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       bool emitted = false;
       if ((phys & PHYS_BREM) && u2 > (T)0) {
         const T lne = m_log(eps2);
+        int tj;
+        T tf;
+        tab.row(lne, tj, tf);
+        const bool above = eps2 > tab.kcut;   // no emission at or below k_cut
+        // the inverse-CDF exponent of a possible emission is fetched together
+        // with the cross sections, so one memory round trip serves both
+        const T xs = above ? tab.x_at(tj, tf, cd.d) : (T)0;
+        T sg0, sg1, sb0, sb1;
+        if (lds_tab) {
+          sg0 = S.tsig[tj]; sg1 = S.tsig[tj + 1]; sb0 = S.tsub[tj]; sb1 = S.tsub[tj + 1];
+        } else {
+          sg0 = tab.SIG[tj]; sg1 = tab.SIG[tj + 1]; sb0 = tab.SUB[tj]; sb1 = tab.SUB[tj + 1];
+        }
         const T um = m_sqrt(u2);
         const T beta = um / g;
-        tau -= (T)R.k_brem * tab.sigma(eps2, lne) * beta;
-        const T sub = (T)R.k_sub * tab.sub(eps2, lne) * beta;
+        tau -= (T)R.k_brem * (above ? sg0 + tf * (sg1 - sg0) : (T)0) * beta;
+        const T sub = (T)R.k_sub * (above ? sb0 + tf * (sb1 - sb0) : eps2) * beta;
         T kph = (T)0;
         if (tau < (T)0) {
-          kph = tab.sample_k(eps2, lne, cd.d);
+          kph = tab.kcut * m_exp(xs * (lne - tab.ln_kcut));
           tau = -m_log((T)1 - draws<T>(id, R.seed, step, SLOT_PHOTON).c);
           // the photon's tally waits in LDS for the end of this electron's step
           const int t = threadIdx.x;
@@ -828,22 +857,42 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
   const PartG<T> B = part_g<T>(R.p[ctr->cur ^ 1]);
   __shared__ unsigned cnt[kNbN];
   __shared__ unsigned base[kNbN];
-  __shared__ int home;
+  __shared__ int home[2];   // alternating between chunks, like the particle kernel's homes
+  if (threadIdx.x < kNbN) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 2) home[threadIdx.x] = kNoTile;
+  __syncthreads();
   const ChunkRange cr = chunk_range(bm, n);
-  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride) {
-    if (threadIdx.x < kNbN) cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) home = 0x7FFFFFFF;
-    __syncthreads();
+  uint32_t cell_next = kDead;   // packed cell of this thread's electron in the next chunk
+  if (cr.beg < cr.end && cr.beg * kBlock + threadIdx.x < n) cell_next = A.cell[cr.beg * kBlock + threadIdx.x];
+  int hs = 0;
+  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, hs ^= 1) {
     const long long i = ch * kBlock + threadIdx.x;
-    const uint32_t cell = i < n ? A.cell[i] : kDead;
+    const uint32_t cell = cell_next;
+    {
+      const long long in = (ch + cr.stride) * kBlock + threadIdx.x;
+      cell_next = ch + cr.stride < cr.end && in < n ? A.cell[in] : kDead;
+    }
+    // the electron's state is in flight while its slot is worked out
+    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0;
+    uint32_t id = 0;
     int t = -1, tx = 0, ty = 0, tz = 0;
     if (cell != kDead) {
+      ox = A.ox[i]; oy = A.oy[i]; oz = A.oz[i];
+      ux = A.ux[i]; uy = A.uy[i]; uz = A.uz[i];
+      wn = A.wn[i]; tau = A.tau[i]; id = A.id[i];
       tx = cell_i(cell) >> 2; ty = cell_j(cell) >> 2; tz = cell_k(cell) >> 2;
       t = tx + R.ntx * (ty + R.nty * tz);
-      atomicMin(&home, t);
+    }
+    {
+      int m = t >= 0 ? t : kNoTile;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+      if ((threadIdx.x & 63) == 0 && m != kNoTile) atomicMin(&home[hs], m);
     }
     __syncthreads();
-    const Home hm = make_home(R, home);
+    const Home hm = make_home(R, __builtin_amdgcn_readfirstlane(home[hs]));
+    // the other slot was last read before the previous chunk's second barrier
+    if (threadIdx.x == 0) home[hs ^ 1] = kNoTile;
     int b = -1;
     unsigned rank = 0;
     long long slot = -1;
@@ -853,26 +902,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
       else slot = atomic_add_u32(&R.tile_cursor[t], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kNbN && cnt[threadIdx.x] != 0) {
+    if (threadIdx.x < kNbN) {
       const int l = threadIdx.x;
-      const int bx = hm.tx + l % kNb - 2, by = hm.ty + (l / kNb) % kNb - 2, bz = hm.tz + l / (kNb * kNb) - 2;
-      base[l] = atomic_add_u32(&R.tile_cursor[bx + R.ntx * (by + R.nty * bz)], cnt[l]);
+      const unsigned c = cnt[l];
+      if (c != 0) {
+        const int bx = hm.tx + l % kNb - 2, by = hm.ty + (l / kNb) % kNb - 2, bz = hm.tz + l / (kNb * kNb) - 2;
+        base[l] = atomic_add_u32(&R.tile_cursor[bx + R.ntx * (by + R.nty * bz)], c);
+        cnt[l] = 0;
+      }
     }
     __syncthreads();
     if (b >= 0) slot = (long long)base[b] + rank;
     if (t >= 0 && slot >= 0 && slot < R.capacity) {   // counts and scatter agree; the bound is a guard
       B.cell[slot] = cell;
-      B.ox[slot] = A.ox[i];
-      B.oy[slot] = A.oy[i];
-      B.oz[slot] = A.oz[i];
-      B.ux[slot] = A.ux[i];
-      B.uy[slot] = A.uy[i];
-      B.uz[slot] = A.uz[i];
-      B.wn[slot] = A.wn[i];
-      B.tau[slot] = A.tau[i];
-      B.id[slot] = A.id[i];
+      B.ox[slot] = ox; B.oy[slot] = oy; B.oz[slot] = oz;
+      B.ux[slot] = ux; B.uy[slot] = uy; B.uz[slot] = uz;
+      B.wn[slot] = wn; B.tau[slot] = tau; B.id[slot] = id;
     }
-    __syncthreads();
   }
 }
 
@@ -1031,14 +1077,21 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDesc* __restrict__
   const int nbin = R.nE * R.nth;
   const long long nh = 2LL * nbin + 4;
   for (long long b = (long long)bm.lb * kBlock + threadIdx.x; b < nh; b += (long long)bm.nb * kBlock) {
-    const long long x = G(R.acc_hist)[b];
+    long long x = 0;
+    for (int c = 0; c < kHistCopies; ++c) {
+      const gptr<long long> a = G(R.acc_hist) + c * R.hist_stride + b;
+      const long long v = *a;
+      if (v != 0) {
+        x += v;
+        *a = 0;
+      }
+    }
     if (x == 0) continue;
     bool is_energy;
     if (b < nbin) is_energy = true;
     else if (b < 2 * nbin) is_energy = false;
     else is_energy = ((b - 2 * nbin) & 1) == 0;
     kahan(G(R.tot_hist) + b, G(R.tot_hist_c) + b, (double)x * (is_energy ? R.led_unit : R.cnt_unit));
-    G(R.acc_hist)[b] = 0;
   }
   if (bm.lb == 0 && threadIdx.x < L_N) {
     const int l = threadIdx.x;
