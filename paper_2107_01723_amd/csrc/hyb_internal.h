@@ -234,6 +234,11 @@ __device__ __forceinline__ float m_cos(float x) { return cosf(x); }
 __device__ __forceinline__ double m_cos(double x) { return cos(x); }
 __device__ __forceinline__ float m_sin(float x) { return sinf(x); }
 __device__ __forceinline__ double m_sin(double x) { return sin(x); }
+// sine and cosine of x, and of 2 pi t (one argument reduction each)
+__device__ __forceinline__ void m_sincos(float x, float& s, float& c) { sincosf(x, &s, &c); }
+__device__ __forceinline__ void m_sincos(double x, double& s, double& c) { sincos(x, &s, &c); }
+__device__ __forceinline__ void m_sincos2pi(float t, float& s, float& c) { sincospif(2.0f * t, &s, &c); }
+__device__ __forceinline__ void m_sincos2pi(double t, double& s, double& c) { sincospi(2.0 * t, &s, &c); }
 __device__ __forceinline__ float m_acos(float x) { return acosf(x); }
 __device__ __forceinline__ double m_acos(double x) { return acos(x); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }
@@ -249,11 +254,12 @@ __device__ __forceinline__ T kinetic(T u2, T g) { return u2 / ((T)1 + g); }
 template <typename T>
 __device__ __forceinline__ T umag_of(T e) { return m_sqrt(e * (e + (T)2)); }
 
-// Turn direction of (ux,uy,uz) by dth at azimuth phi, keeping |u|.  Basis:
-// a = unit(uhat x e_m), e_m the axis of the smallest |uhat_i| (ties -> lowest
-// index), b = uhat x a; uhat' = cos dth uhat + sin dth (cos phi a + sin phi b).
+// Turn direction of (ux,uy,uz) by dth at azimuth phi = 2 pi t, keeping |u|.
+// Basis: a = unit(uhat x e_m), e_m the axis of the smallest |uhat_i| (ties ->
+// lowest index), b = uhat x a; uhat' = cos dth uhat + sin dth (cos phi a +
+// sin phi b).
 template <typename T>
-__device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T phi) {
+__device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T t) {
   const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
   const T inv = (T)1 / um;
   const T hx = ux * inv, hy = uy * inv, hz = uz * inv;
@@ -265,7 +271,9 @@ __device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T phi) {
   const T an = (T)1 / m_sqrt(ax * ax + ay * ay + az * az);
   ax *= an; ay *= an; az *= an;
   const T bx = hy * az - hz * ay, by = hz * ax - hx * az, bz = hx * ay - hy * ax;
-  const T c = m_cos(dth), s = m_sin(dth), cp = m_cos(phi), sp = m_sin(phi);
+  T c, s, cp, sp;
+  m_sincos(dth, s, c);
+  m_sincos2pi(t, sp, cp);
   T dx = c * hx + s * (cp * ax + sp * bx);
   T dy = c * hy + s * (cp * ay + sp * by);
   T dz = c * hz + s * (cp * az + sp * bz);

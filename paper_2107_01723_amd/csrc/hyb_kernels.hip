@@ -95,7 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
   long long acc[L_N + C_N];
 #pragma unroll
   for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
-  const T twopi = (T)(2.0 * kPi);
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
     int s = 0;
     long long off = 0;
@@ -105,16 +104,18 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     const Uni4<T> a = draws<T>(id, R.seed, step, SLOT_INJ_A);
     const Uni4<T> b = draws<T>(id, R.seed, step, SLOT_INJ_B);
     const T r = m_sqrt((T)-2 * (T)S->sig2 * m_log((T)1 - (T)0.5 * a.a));
-    const T ps = twopi * a.b;
-    const T y = (T)S->y0 + r * m_cos(ps);
-    const T z = (T)S->z0 + r * m_sin(ps);
+    T sps, cps;
+    m_sincos2pi(a.b, sps, cps);
+    const T y = (T)S->y0 + r * cps;
+    const T z = (T)S->z0 + r * sps;
     const T eps = -(T)S->t_hot * m_log((T)1 - a.c);
     const T ct = (T)1 - a.d * (T)S->one_minus_cos;
     T st2 = (T)1 - ct * ct;
     const T st = m_sqrt(st2 > (T)0 ? st2 : (T)0);
-    const T pc = twopi * b.a;
+    T spc, cpc;
+    m_sincos2pi(b.a, spc, cpc);
     const T um = umag_of(eps);
-    const T ux = um * ct, uy = um * st * m_cos(pc), uz = um * st * m_sin(pc);
+    const T ux = um * ct, uy = um * st * cpc, uz = um * st * spc;
     const T tau = -m_log((T)1 - b.b);
     const long long slot = n0 + t;
     if (slot >= R.capacity) break;   // never write past the particle arrays
@@ -202,8 +203,9 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   if (c2 >= hi) { c2 = hi - 1; o2 = (T)1 - (T)(sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16); }
   c = c2;
   o = o2;
-  T& un = axis == 0 ? ux : (axis == 1 ? uy : uz);
-  un = -un;
+  if (axis == 0) ux = -ux;
+  else if (axis == 1) uy = -uy;
+  else uz = -uz;
   // energy or momentum loss
   const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
   T scale;
@@ -225,14 +227,16 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   eps = eps_a;
   if (u2 > (T)0) {
     const Uni4<T> rd = draws<T>(id, R.seed, step, SLOT_REFLUX0 + (uint32_t)axis);
-    rotate(ux, uy, uz, (rd.a - (T)0.5) * (T)R.sigma_dth, (T)(2.0 * kPi) * rd.b);
+    rotate(ux, uy, uz, (rd.a - (T)0.5) * (T)R.sigma_dth, rd.b);
     const T v2 = ux * ux + uy * uy + uz * uz;
     const T eps_r = kinetic(v2, m_sqrt((T)1 + v2));
     lds_add(&led[L_RESIDUAL], to_fixed((eps - eps_r) * wn * (T)kLedScale));
     eps = eps_r;
   }
-  T& un2 = axis == 0 ? ux : (axis == 1 ? uy : uz);
-  un2 = below ? fabs(un2) : -fabs(un2);
+  // leave the face inwards
+  if (axis == 0) ux = below ? fabs(ux) : -fabs(ux);
+  else if (axis == 1) uy = below ? fabs(uy) : -fabs(uy);
+  else uz = below ? fabs(uz) : -fabs(uz);
   return true;
 }
 
@@ -432,7 +436,7 @@ __device__ __forceinline__ void photon_tally(const RunDesc& R, ChunkLds<T>& S, T
   // photon direction about the electron direction
   T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
   th = th < (T)kPi ? th : (T)kPi;
-  rotate(dxp, dyp, dzp, th, (T)(2.0 * kPi) * pd.b);
+  rotate(dxp, dyp, dzp, th, pd.b);
   T cx = dxp / um;
   cx = cx > (T)1 ? (T)1 : (cx < (T)-1 ? (T)-1 : cx);
   const T tq = m_acos(cx) * (T)R.nth * (T)(1.0 / kPi);
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
                    (T)R.tab_ln_kcut, (T)R.tab_s_scale, (T)R.tab_kcut};
   const T e_kick = (T)R.e_kick, b_rot = (T)R.b_rot, cdt = (T)R.cdt_dx;
   const T ledS = (T)kLedScale;
-  const T twopi = (T)(2.0 * kPi);
+
 
   const ChunkRange cr = chunk_range(bm, n);
   lds_init(S);
@@ -690,8 +694,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         T lg = m_log((T)R.l_dav * um);
         lg = lg > (T)0 ? lg : (T)0;
         const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
-        const T gam = m_sqrt((T)-2 * m_log(cd.a)) * m_cos(twopi * cd.b);
-        rotate(ux, uy, uz, gam * m_sqrt(s2), twopi * cd.c);
+        T sb, cb;
+        m_sincos2pi(cd.b, sb, cb);
+        const T gam = m_sqrt((T)-2 * m_log(cd.a)) * cb;
+        rotate(ux, uy, uz, gam * m_sqrt(s2), cd.c);
         // elastic: any change of the stored energy is rounding, booked apart
         u2 = ux * ux + uy * uy + uz * uz;
         g = m_sqrt((T)1 + u2);
@@ -702,9 +708,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
 
       // --- boundaries: x (slab faces), y, z (domain walls) ---
       T eps = eps3;
-      bool alive = boundary_axis(R, 0, ci, ox, R.ix_lo, R.ix_hi, ux, uy, uz, eps, wn, id, step, S.led);
-      if (alive) alive = boundary_axis(R, 1, cj, oy, 0, ny, ux, uy, uz, eps, wn, id, step, S.led);
-      if (alive) alive = boundary_axis(R, 2, ck, oz, 0, nz, ux, uy, uz, eps, wn, id, step, S.led);
+      bool alive = true;
+      {
+        // one copy of the boundary code for the three axes: (c0, o0) is the
+        // axis being checked, and the triples rotate by one per axis
+        int c0 = ci, c1 = cj, c2 = ck;
+        T o0 = ox, o1 = oy, o2 = oz;
+#pragma unroll 1
+        for (int a = 0; a < 3; ++a) {
+          const int lo = a == 0 ? R.ix_lo : 0, hi = a == 0 ? R.ix_hi : (a == 1 ? ny : nz);
+          if (alive) alive = boundary_axis(R, a, c0, o0, lo, hi, ux, uy, uz, eps, wn, id, step, S.led);
+          const int ct = c0; c0 = c1; c1 = c2; c2 = ct;
+          const T ot = o0; o0 = o1; o1 = o2; o2 = ot;
+        }
+        ci = c0; cj = c1; ck = c2;
+        ox = o0; oy = o1; oz = o2;
+      }
 
       // --- removal below e_min, energy to the cell's heat ---
       if (alive && eps < (T)R.e_min) {
