@@ -214,8 +214,11 @@ hyb_status hyb_init(const hyb_config* cfg, const hyb_device* dev, hyb_run** out)
 
 /* Schedule an injection source; ids n..n+n_macro-1 go to its electrons in
  * step order.  No device work.  HYB_ENOSPACE when all sources together
- * exceed max_particles; HYB_EINVAL when the spot leaves the slab face or the
- * window is empty; HYB_ESTATE when the run already started past t_start. */
+ * exceed max_particles; HYB_EINVAL when the spot leaves the slab face, the
+ * window is empty, or the macro-electron weight exceeds the accumulator
+ * limit (the fixed-point unit w_ref is the largest weight scheduled before
+ * the first step; later weights may reach 64 w_ref in FP64 and 2 w_ref in
+ * FP32-mixed runs); HYB_ESTATE when the run already started past t_start. */
 hyb_status hyb_inject(hyb_run* run, const hyb_source* src);
 
 /* Enqueue nsteps full hybrid-PIC steps (inject, push and collide, deposit,
@@ -233,7 +236,8 @@ hyb_status hyb_get_state(hyb_run* run, hyb_state* st);
 
 /* Replace particles, fields, temperatures, resistivity, step and next id
  * (NULL field/cell pointers keep the current arrays).  Clears the step's
- * current and heat buffers.  Synchronises the stream. */
+ * current and heat buffers.  HYB_EINVAL when a weight is not positive or
+ * exceeds the accumulator limit of hyb_inject.  Synchronises the stream. */
 hyb_status hyb_set_state(hyb_run* run, const hyb_state* st);
 
 hyb_status hyb_run_info_get(const hyb_run* run, hyb_run_info* info);

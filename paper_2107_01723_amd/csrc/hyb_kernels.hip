@@ -255,24 +255,24 @@ constexpr int kNb = 5;                        // destination tiles: home +-2 per
 constexpr int kNbN = kNb * kNb * kNb;         // 125
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
 // (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
-// contribution to 2^24 units -- already finer than the FP32 state -- so the
-// LDS sums fit 32-bit words, which are widened to the 2^40 HBM accumulators at
-// the flush.  Every contribution is rounded the same way whether it goes
-// through LDS or straight to HBM, so the sums stay independent of the
-// electron order.
+// contribution to 2^23 units -- as fine as the FP32 state itself -- so the LDS
+// sums fit 32-bit words, which are widened to the 2^40 HBM accumulators at the
+// flush.  Every contribution is rounded the same way whether it goes through
+// LDS or straight to HBM, so the sums stay independent of the electron order.
 //
 // Electrons of a dense tile hit the same few LDS words; each accumulator has
 // `copies` interleaved copies (lane l adds into copy l % copies), which
-// divides the same-address serialisation of the LDS atomics.  With 8 copies
-// one 32-bit word takes at most kBlock / 8 = 32 contributions of magnitude
-// below 2^25 (w / w_ref <= 2), so it cannot overflow.
+// divides the same-address serialisation of the LDS atomics, at the price of
+// more LDS to clear and sum at the flush.  With 2 copies one 32-bit word takes
+// at most kBlock / 2 = 128 contributions of magnitude below 2^24
+// (w / w_ref <= 2), so it cannot overflow.
 template <typename T> struct JAcc {
   using type = long long;
   static constexpr int shift = 0, copies = 4;
 };
 template <> struct JAcc<float> {
   using type = int;
-  static constexpr int shift = 16, copies = 8;
+  static constexpr int shift = 17, copies = 2;
 };
 constexpr int kHeatCopies = 4;
 constexpr int kLdsTab = 128;   // table rows staged in LDS
@@ -425,6 +425,27 @@ __device__ __forceinline__ void deposit8(long long* __restrict__ J, typename JAc
   }
 }
 
+// Ranks of the lanes in their bins (b < 0: none), taken in lane order from
+// the block's LDS counters: one LDS atomic per distinct bin of the wave, so
+// lanes of one bin get consecutive ranks and their writes coalesce.
+__device__ __forceinline__ unsigned wave_rank(unsigned* cnt, int b) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned rank = 0;
+  unsigned long long todo = __ballot(b >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lb = __shfl(b, leader, 64);
+    const unsigned long long m = __ballot(b == lb);
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[lb], (unsigned)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (b == lb) rank = base + (unsigned)__popcll(m & below);
+    todo &= ~m;
+  }
+  return rank;
+}
+
 // Tally of one photon (Sec. II.C, Table I bins): emitted at energy k about
 // the electron direction u (|u| = um, Lorentz factor g), weight wn / boost.
 template <typename T>
@@ -482,8 +503,11 @@ __device__ __forceinline__ ChunkRange chunk_range(const BlockMap& bm, long long 
 // the particle step: gather, Boris, deposit, move, ionisation,
 // bremsstrahlung, Davies scatter, boundaries, low-energy removal
 // ---------------------------------------------------------------------------
+// Waves per SIMD the register allocation of the particle kernel is held to.
+// The kernel is latency bound (dependent HBM round trips per chunk), so
+// occupancy pays for a few spills: 2 in FP64 (256 registers), 4 in FP32.
 template <typename T> struct PartOcc { static constexpr int waves = 2; };
-template <> struct PartOcc<float> { static constexpr int waves = 3; };
+template <> struct PartOcc<float> { static constexpr int waves = 4; };
 template <typename T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<T>::waves))) void k_particle(const RunDesc* __restrict__ runs,
                                                      const BlockMap* __restrict__ bmap) {
@@ -913,13 +937,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
     // the other slot was last read before the previous chunk's second barrier
     if (threadIdx.x == 0) home[hs ^ 1] = kNoTile;
     int b = -1;
-    unsigned rank = 0;
     long long slot = -1;
     if (t >= 0) {
       b = nb_bin(hm, tx, ty, tz);
-      if (b >= 0) rank = atomicAdd(&cnt[b], 1u);
-      else slot = atomic_add_u32(&R.tile_cursor[t], 1u);
+      if (b < 0) slot = atomic_add_u32(&R.tile_cursor[t], 1u);
     }
+    const unsigned rank = wave_rank(cnt, b);
     __syncthreads();
     if (threadIdx.x < kNbN) {
       const int l = threadIdx.x;
