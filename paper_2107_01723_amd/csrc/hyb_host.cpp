@@ -40,7 +40,8 @@ struct Layout {
   size_t off_part[2][10];
   size_t off_tabX, off_tabSIG, off_tabSUB;
   size_t off_acc_led, off_acc_hist, off_events, off_tot_led, off_tot_led_c, off_tot_hist, off_tot_hist_c;
-  size_t off_series, off_ctr, off_src, off_tile_cnt, off_tile_start, off_tile_cursor, off_scan_blk, off_red, off_desc;
+  size_t off_series, off_ctr, off_src, off_tile_cnt, off_tile_start, off_scan_blk,
+         off_chunk_home, off_chunk_base, off_far, off_red, off_desc;
   size_t total;
 };
 
@@ -83,8 +84,11 @@ Layout make_layout(const hyb_config& c) {
                         ((c.nz + kTile - 1) / kTile);
   L.off_tile_cnt = take(ntiles * 4);
   L.off_tile_start = take(ntiles * 4);
-  L.off_tile_cursor = take(ntiles * 4);
   L.off_scan_blk = take(((ntiles + kScanTile - 1) / kScanTile) * 4);
+  const size_t nchunks = (cap + kChunk - 1) / kChunk;
+  L.off_chunk_home = take(nchunks * 4);
+  L.off_chunk_base = take(nchunks * kNbN * 4);
+  L.off_far = take(cap * 4);
   L.off_red = take(2 * kRedBlocks * 8);
   L.off_desc = take(sizeof(RunDesc));
   L.total = o;
@@ -300,7 +304,9 @@ static void point_desc(hyb_run* r) {
   h.src = (const SourceDesc*)(b + L.off_src);
   h.tile_cnt = (unsigned*)(b + L.off_tile_cnt);
   h.tile_start = (unsigned*)(b + L.off_tile_start);
-  h.tile_cursor = (unsigned*)(b + L.off_tile_cursor);
+  h.chunk_home = (int*)(b + L.off_chunk_home);
+  h.chunk_base = (unsigned*)(b + L.off_chunk_base);
+  h.far_off = (unsigned*)(b + L.off_far);
   h.scan_blk = (unsigned*)(b + L.off_scan_blk);
   h.red = (double*)(b + L.off_red);
 }

@@ -138,12 +138,22 @@ struct RunDesc {
   int scan_nblk;            // scan blocks of kScanTile tiles
   unsigned* tile_cnt;       // [ntiles] electrons per destination tile
   unsigned* tile_start;     // [ntiles] exclusive scan of tile_cnt
-  unsigned* tile_cursor;    // [ntiles] scatter cursors
   unsigned* scan_blk;       // [scan_nblk] block sums
+  // Where the scatter puts each electron, fixed by the particle kernel's
+  // counting: a chunk's electrons bound for tile t occupy
+  // tile_start[t] + chunk_base[chunk][bin of t] + [0, count), and an electron
+  // bound outside its chunk's neighbourhood sits at tile_start[t] + far_off[i].
+  int* chunk_home;          // [chunks] smallest start-of-step tile of the chunk (none: kNoTile)
+  unsigned* chunk_base;     // [chunks][kNbN]
+  unsigned* far_off;        // [capacity]
   double* red;              // per-block partial sums for host-side reductions
 };
 
 constexpr int kTile = 4;           // tile edge in cells
+constexpr int kChunk = 256;        // electrons per chunk of the particle kernels (one workgroup)
+constexpr int kNb = 5;             // destination tiles counted per chunk: home +-2 per axis
+constexpr int kNbN = kNb * kNb * kNb;
+constexpr int kNoTile = 0x7FFFFFFF;
 // Photon tallies are accumulated in this many copies (workgroup b adds into
 // copy b % kHistCopies), so that the memory-side atomics on the few hot bins
 // of the spectrum do not all queue on one address; the step's finalisation

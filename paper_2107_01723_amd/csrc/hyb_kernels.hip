@@ -14,7 +14,7 @@
 
 namespace hyb {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kChunk;
 constexpr int kWaves = kBlock / 64;
 
 // integer adds into LDS words
@@ -251,8 +251,6 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 // ---------------------------------------------------------------------------
 constexpr int kHalo = kTile + 2;              // node span of a tile's stencils
 constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
-constexpr int kNb = 5;                        // destination tiles: home +-2 per axis
-constexpr int kNbN = kNb * kNb * kNb;         // 125
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
 // (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
 // contribution to 2^23 units -- as fine as the FP32 state itself -- so the LDS
@@ -276,7 +274,6 @@ template <> struct JAcc<float> {
 };
 constexpr int kHeatCopies = 4;
 constexpr int kLdsTab = 128;   // table rows staged in LDS
-constexpr int kNoTile = 0x7FFFFFFF;
 
 // A chunk has two home tiles: the smallest and the largest tile among its
 // electrons.  The electrons of a tile-sorted chunk of kBlock rarely span
@@ -368,16 +365,21 @@ __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& 
   }
 }
 
-// destination counts of the chunk (bins around home tile h) to HBM, cleared
+// Destination counts of chunk ch (bins around home tile h) to the tile
+// counters, cleared.  The counter's old value is the chunk's offset inside
+// the tile; it is stored one chunk later (pend_*), when the atomic is back.
 template <typename T>
-__device__ __forceinline__ void lds_flush_counts(const RunDesc& R, ChunkLds<T>& L, const Home& h) {
+__device__ __forceinline__ void lds_flush_counts(const RunDesc& R, ChunkLds<T>& L, const Home& h, long long ch,
+                                                 unsigned& pend_val, long long& pend_at) {
   if (threadIdx.x < kNbN) {
     const unsigned v = L.cnt[threadIdx.x];
     L.cnt[threadIdx.x] = 0;
     const int l = threadIdx.x;
     const int tx = h.tx + l % kNb - 2, ty = h.ty + (l / kNb) % kNb - 2, tz = h.tz + l / (kNb * kNb) - 2;
-    if (v != 0 && tx >= 0 && ty >= 0 && tz >= 0 && tx < R.ntx && ty < R.nty && tz < R.ntz)
-      atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], v);
+    if (v != 0 && tx >= 0 && ty >= 0 && tz >= 0 && tx < R.ntx && ty < R.nty && tz < R.ntz) {
+      pend_val = atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], v);
+      pend_at = ch * kNbN + l;
+    }
   }
 }
 
@@ -548,8 +550,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   __syncthreads();
   uint32_t cell_next = kDead;   // packed cell of this thread's electron in the next chunk
   if (cr.beg < cr.end && cr.beg * kBlock + threadIdx.x < n) cell_next = P.cell[cr.beg * kBlock + threadIdx.x];
+  // tile offsets returned by the counting atomics, stored a chunk later
+  unsigned base_val = 0, far_val = 0;
+  long long base_at = -1, far_at = -1;
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
+    if (base_at >= 0) { G(R.chunk_base)[base_at] = base_val; base_at = -1; }
+    if (far_at >= 0) { G(R.far_off)[far_at] = far_val; far_at = -1; }
     const long long i = ch * kBlock + threadIdx.x;
     const uint32_t cell = cell_next;
     {
@@ -771,7 +778,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         if (count) {   // destination tile for the sort that ends this step
           const int tx = ci >> 2, ty = cj >> 2, tz = ck >> 2;
           dest_bin = nb_bin(hm, tx, ty, tz);
-          if (dest_bin < 0) atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
+          if (dest_bin < 0) {
+            far_val = atomic_add_u32(&R.tile_cnt[tx + R.ntx * (ty + R.nty * tz)], 1u);
+            far_at = i;
+          }
         }
       }
       if (emitted) {
@@ -795,8 +805,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     // LDS only after its own barrier
     if (hm.ok) lds_flush_region(R, S, 0, hm);
     if (hm2.ok && thi != tlo) lds_flush_region(R, S, 1, hm2);
-    if (count) lds_flush_counts(R, S, hm);
+    if (count) {
+      lds_flush_counts(R, S, hm, ch, base_val, base_at);
+      if (threadIdx.x == 0) G(R.chunk_home)[ch] = tlo;
+    }
   }
+  if (base_at >= 0) G(R.chunk_base)[base_at] = base_val;
+  if (far_at >= 0) G(R.far_off)[far_at] = far_val;
   block_flush<L_N, C_N>(acc, R.acc_led, R.events, S.led);
 }
 
@@ -880,12 +895,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
   for (int q = 0; q < per; ++q) {
     if (t0 + q < R.ntiles) {
       G(R.tile_start)[t0 + q] = run;
-      G(R.tile_cursor)[t0 + q] = run;
     }
     run += v[q];
   }
 }
 
+// Scatter of the electrons into the other particle buffer in tile order
+// (dead electrons dropped).  The particle kernel fixed every electron's slot
+// when it counted the destinations; here each chunk ranks its electrons
+// inside their bins and copies them.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ runs,
                                                     const BlockMap* __restrict__ bmap) {
@@ -898,64 +916,33 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
   n = n < R.capacity ? n : R.capacity;
   const PartG<T> A = part_g<T>(R.p[ctr->cur]);
   const PartG<T> B = part_g<T>(R.p[ctr->cur ^ 1]);
-  __shared__ unsigned cnt[kNbN];
-  __shared__ unsigned base[kNbN];
-  __shared__ int home[2];   // alternating between chunks, like the particle kernel's homes
-  if (threadIdx.x < kNbN) cnt[threadIdx.x] = 0;
-  if (threadIdx.x < 2) home[threadIdx.x] = kNoTile;
-  __syncthreads();
+  __shared__ unsigned cnt[2][kNbN];   // rank counters, alternating between chunks
+  if (threadIdx.x < kNbN) { cnt[0][threadIdx.x] = 0; cnt[1][threadIdx.x] = 0; }
   const ChunkRange cr = chunk_range(bm, n);
-  uint32_t cell_next = kDead;   // packed cell of this thread's electron in the next chunk
-  if (cr.beg < cr.end && cr.beg * kBlock + threadIdx.x < n) cell_next = A.cell[cr.beg * kBlock + threadIdx.x];
-  int hs = 0;
-  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, hs ^= 1) {
+  int p = 0;
+  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, p ^= 1) {
+    // the counters of the other parity were last used by the previous chunk
+    __syncthreads();
+    if (threadIdx.x < kNbN) cnt[p ^ 1][threadIdx.x] = 0;
     const long long i = ch * kBlock + threadIdx.x;
-    const uint32_t cell = cell_next;
-    {
-      const long long in = (ch + cr.stride) * kBlock + threadIdx.x;
-      cell_next = ch + cr.stride < cr.end && in < n ? A.cell[in] : kDead;
-    }
-    // the electron's state is in flight while its slot is worked out
+    const uint32_t cell = i < n ? A.cell[i] : kDead;
+    const Home hm = make_home(R, __builtin_amdgcn_readfirstlane(G(R.chunk_home)[ch]));
     T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0;
     uint32_t id = 0;
-    int t = -1, tx = 0, ty = 0, tz = 0;
+    int t = -1, b = -1;
+    unsigned off = 0;
     if (cell != kDead) {
       ox = A.ox[i]; oy = A.oy[i]; oz = A.oz[i];
       ux = A.ux[i]; uy = A.uy[i]; uz = A.uz[i];
       wn = A.wn[i]; tau = A.tau[i]; id = A.id[i];
-      tx = cell_i(cell) >> 2; ty = cell_j(cell) >> 2; tz = cell_k(cell) >> 2;
+      const int tx = cell_i(cell) >> 2, ty = cell_j(cell) >> 2, tz = cell_k(cell) >> 2;
       t = tx + R.ntx * (ty + R.nty * tz);
-    }
-    {
-      int m = t >= 0 ? t : kNoTile;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
-      if ((threadIdx.x & 63) == 0 && m != kNoTile) atomicMin(&home[hs], m);
-    }
-    __syncthreads();
-    const Home hm = make_home(R, __builtin_amdgcn_readfirstlane(home[hs]));
-    // the other slot was last read before the previous chunk's second barrier
-    if (threadIdx.x == 0) home[hs ^ 1] = kNoTile;
-    int b = -1;
-    long long slot = -1;
-    if (t >= 0) {
       b = nb_bin(hm, tx, ty, tz);
-      if (b < 0) slot = atomic_add_u32(&R.tile_cursor[t], 1u);
+      off = G(R.tile_start)[t] + (b >= 0 ? G(R.chunk_base)[ch * kNbN + b] : G(R.far_off)[i]);
     }
-    const unsigned rank = wave_rank(cnt, b);
-    __syncthreads();
-    if (threadIdx.x < kNbN) {
-      const int l = threadIdx.x;
-      const unsigned c = cnt[l];
-      if (c != 0) {
-        const int bx = hm.tx + l % kNb - 2, by = hm.ty + (l / kNb) % kNb - 2, bz = hm.tz + l / (kNb * kNb) - 2;
-        base[l] = atomic_add_u32(&R.tile_cursor[bx + R.ntx * (by + R.nty * bz)], c);
-        cnt[l] = 0;
-      }
-    }
-    __syncthreads();
-    if (b >= 0) slot = (long long)base[b] + rank;
-    if (t >= 0 && slot >= 0 && slot < R.capacity) {   // counts and scatter agree; the bound is a guard
+    const unsigned rank = wave_rank(cnt[p], b);
+    const long long slot = (long long)off + (b >= 0 ? rank : 0u);
+    if (t >= 0 && slot < R.capacity) {   // counts and scatter agree; the bound is a guard
       B.cell[slot] = cell;
       B.ox[slot] = ox; B.oy[slot] = oy; B.oz[slot] = oz;
       B.ux[slot] = ux; B.uy[slot] = uy; B.uz[slot] = uz;
