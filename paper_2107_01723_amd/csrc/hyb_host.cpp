@@ -191,11 +191,12 @@ static std::string validate(const hyb_config& c) {
 }
 
 static int n_sub_auto(const hyb_config& c, double n_i) {
+  const Solid sol = make_solid(c.Z, c.A, c.rho, n_i, c.lambda1, c.lambda2);
   double eta_max = 0.0;
   const double a = log10(c.T0), b = 9.0;
   for (int i = 0; i < 400; ++i) {
     const double T = i == 399 ? 1e9 : pow(10.0, a + i * (b - a) / 399.0);
-    eta_max = fmax(eta_max, resistivity(T, T, c.Z, c.A, c.rho, n_i, c.lambda1, c.lambda2));
+    eta_max = fmax(eta_max, resistivity(sol, T, T));
   }
   const double dt_max = 0.9 * kMu0 * c.dx * c.dx / (6.0 * eta_max);
   return std::max(1, (int)ceil(c.dt / dt_max));
@@ -255,8 +256,8 @@ static void fill_desc(hyb_run* r) {
   h.ln_Elo = log(c.tally_Elo / kMec2);
   h.e_bin_scale = c.tally_nE / log(c.tally_Ehi / c.tally_Elo);
   h.Ethr = c.tally_Ethr / kMec2;
-  h.Z = c.Z; h.A = c.A; h.rho = c.rho; h.n_i = n_i; h.m_i = c.A * kAmu;
-  h.lambda1 = c.lambda1; h.lambda2 = c.lambda2; h.eta_fixed = c.eta_fixed;
+  h.solid = make_solid(c.Z, c.A, c.rho, n_i, c.lambda1, c.lambda2);
+  h.eta_fixed = c.eta_fixed;
   h.sort_every = c.sort_every;
   h.ntx = (c.nx + kTile - 1) / kTile;
   h.nty = (c.ny + kTile - 1) / kTile;
@@ -428,7 +429,7 @@ static hyb_status create_run(const hyb_config* cfg, const hyb_device* dev, hyb_r
   {
     std::vector<double> T(ncells, c.T0), eta(ncells, 0.0);
     const double e0 = c.eta_fixed > 0 ? c.eta_fixed
-                                      : resistivity(c.T0, c.T0, c.Z, c.A, c.rho, r->h.n_i, c.lambda1, c.lambda2);
+                                      : resistivity(r->h.solid, c.T0, c.T0);
     for (int k = 0; k < c.nz; ++k)
       for (int j = 0; j < c.ny; ++j)
         for (int i = r->h.ix_lo; i < r->h.ix_hi; ++i) eta[i + (size_t)c.nx * (j + (size_t)c.ny * k)] = e0;
@@ -681,7 +682,7 @@ hyb_status hyb_run_info_get(const hyb_run* r, hyb_run_info* info) {
   info->n_sub = r->h.n_sub;
   info->a0 = 8.5e-6 * sqrt(c.I0 * c.wavelength * c.wavelength);
   info->eps_esc = r->h.eps_esc * kMec2;
-  info->n_i = r->h.n_i;
+  info->n_i = r->h.solid.n_i;
   info->c_z = cz_of(c.Z);
   info->w_ref = r->h.w_ref;
   info->nodes = r->h.nodes;

@@ -84,6 +84,18 @@ struct PartPtrs {
   uint32_t* id;
 };
 
+// Material of the background solid (App. A), with the combinations of
+// constants its per-cell formulas need, computed once per run.
+struct Solid {
+  double Z, A, rho, n_i, m_i, lambda1, lambda2;
+  double z43;     // Z^(4/3)
+  double lnR;     // ln(rho[g/cm^3] / (A Z)), More's reduced density
+  double tf_c;    // Fermi temperature / n_e^(2/3): hbar^2 (3 pi^2)^(2/3) / (2 m_e k_B)
+  double r0;      // ion-sphere radius (3 / (4 pi n_i))^(1/3)
+  double th_c;    // tau_hot = th_c (k_B Te)^1.5 / (Z*^2 n_i lnL)
+  double tc_c;    // electron-ion exchange: 1 / tau = tc_c lnL / (Te m_i + Ti m_e)^1.5
+};
+
 // Read-only description of one run (device memory; one per resident run).
 struct RunDesc {
   int nx, ny, nz, ix_lo, ix_hi;
@@ -116,7 +128,8 @@ struct RunDesc {
   double led_unit;    // J per fixed unit of the ledger
   double cnt_unit;    // photons per fixed unit of the number tally
   // solid (heat update, FP64)
-  double Z, A, rho, n_i, m_i, lambda1, lambda2, eta_fixed;
+  Solid solid;
+  double eta_fixed;
   // arrays
   void* E[3]; void* B[3];
   long long* J[3];

@@ -1068,6 +1068,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
   const long long ns = (long long)w * ny * R.nz;
   const double ju = 0.25 * R.j_unit, dV = R.dx * R.dx * R.dx;
   const bool fixed = R.eta_fixed > 0.0;
+  const Solid sol = R.solid;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < ns; t += (long long)bm.nb * kBlock) {
     const int i = R.ix_lo + (int)(t % w);
     const long long q = t / w;
@@ -1081,8 +1082,8 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const double jy = (double)(Jy[n] + Jy[n + 1] + Jy[n + sxy] + Jy[n + 1 + sxy]) * ju;
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
     double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = G(R.eta)[c];
-    heat_cell(Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)G(R.ion_heat)[c] * R.heat_unit, R.dt, dV,
-              R.Z, R.A, R.rho, R.n_i, R.m_i, R.lambda1, R.lambda2, fixed);
+    heat_cell(sol, Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)G(R.ion_heat)[c] * R.heat_unit, R.dt, dV,
+              fixed);
     G(R.Te)[c] = Te;
     G(R.Ti)[c] = Ti;
     G(R.eta)[c] = eta;
