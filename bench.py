@@ -11,11 +11,16 @@ The same workload is also timed in FP32-mixed precision.
 Prints one JSON line.  `value` is FP64 macro-electron steps per second
 (alive electrons x steps / wall time of the timed steps, inputs resident in
 HBM).  `roofline` is the particle kernel's algorithmic bytes per launch over
-its mean duration, measured with HIP events on the run's stream.
+its mean duration, measured with HIP events on the run's stream; its
+`traffic` is the HBM bytes per launch that rocprofv3's FETCH_SIZE and
+WRITE_SIZE counters gave for the same kernel (per electron, from the summary
+under profiles/, times this run's mean alive count), or null when that
+summary was taken on other kernel sources.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +41,37 @@ def particle_bytes(precision: int) -> int:
     read = 4 + 3 * t + 3 * t + t + t + 4
     write = 4 + 3 * t + 3 * t + t
     return read + write
+
+
+KERNEL_SOURCES = ("paper_2107_01723_amd/csrc/hyb_kernels.hip", "paper_2107_01723_amd/csrc/hyb_internal.h",
+                  "paper_2107_01723_amd/csrc/hyb_solid.h")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "particle_kernel_hbm_bytes_gold_slab_256x128x128_2e7.txt")
+
+
+def kernel_digest() -> str:
+    """Digest of the device sources; a counter summary holds the digest of
+    the kernels it was taken on."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_bytes_per_electron(label: str):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe factors)
+    per electron-step of the particle kernel, from the committed counter
+    summary; None when the summary is missing or was taken on other kernels."""
+    try:
+        with open(COUNTER_SUMMARY) as fh:
+            kv = dict(ln.split(":", 1) for ln in fh if ":" in ln and not ln.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_digest") != kernel_digest():
+        return None
+    v = kv.get(f"{label}_hbm_bytes_per_electron")
+    return float(v) if v else None
 
 
 def time_run(P, cfg, srcs, steps, warmup, label):
@@ -60,8 +96,10 @@ def time_run(P, cfg, srcs, steps, warmup, label):
                conversion=t1["conversion"], n_alive_end=t1["n_alive"])
     pb = particle_bytes(cfg["precision"])
     achieved = pb * alive / (res["kernel_ms"] * 1e-3) / 1e9
+    bpe = counted_bytes_per_electron(label)
+    traffic = None if bpe is None else round(bpe * alive)
     res["roofline"] = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                           frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                            bytes_per_particle_step=pb)
     led = t1["ledger"]
     out = (t1["kinetic"] + led["field_loss"] - led["field_gain"] + led["ionisation"] + led["stopped"]
@@ -114,14 +152,17 @@ def main():
     import paper_2107_01723_amd as P
 
     if a.copy_probe:
+        # reference kernel for the HBM byte counters: one 512 MiB device copy
+        # whose source was pushed out of the caches by writing 2 GiB elsewhere
         import torch
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        evict = torch.ones(512 << 20, dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
-        print("# copy probe: 3 x 512 MiB read + 512 MiB written", file=sys.stderr, flush=True)
-        del src, dst
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# copy probe: 512 MiB read + 512 MiB written", file=sys.stderr, flush=True)
+        del src, dst, evict
 
     cfg, srcs, total_steps = W.config_fp64_large()
     if a.particles:
