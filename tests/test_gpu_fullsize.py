@@ -1,0 +1,127 @@
+"""GPU parity at the benchmark's full size, in the launch configuration
+bench.py times: the gold slab of 256x128x128 cells with 2e7 macro-electrons
+(FP64, and the same workload in FP32-mixed), and the 256^3 FP32-mixed slab
+with 1e8 macro-electrons.
+
+At this size the oracle cannot step the whole run, but every electron's step
+depends only on its own state and the fields at the start of the step.  So a
+sample of electrons is taken from the GPU state, stepped once by the oracle
+in those fields, and compared with the same electrons after the GPU's step of
+the whole population.  Quantities that involve all electrons are checked
+through properties that hold at any size: the energy ledger closes, the
+photon tallies add up to the radiated energy, and the particle buffer is in
+tile order after each sort.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import OracleRun
+
+from parity_util import particle_errors
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2107_01723_amd as P
+    P.check_abi()
+    return P
+
+
+def _closure(t):
+    led = t["ledger"]
+    out = (t["kinetic"] + led["field_loss"] - led["field_gain"] + led["ionisation"] + led["stopped"]
+           + led["rad_discrete"] + led["rad_subcut"] + led["escaped"] + led["reflux"] + led["residual"])
+    return abs(led["injected"] - out) / led["injected"]
+
+
+def _subset(st, ids):
+    sel = np.isin(st["ids"], ids)
+    return {k: (st[k][sel] if k in ("pos", "p", "w", "tau", "ids") else st[k]) for k in st}
+
+
+@pytest.mark.parametrize("precision,n_pre,tol", [(W.FP64, 30, 1e-10), (W.FP64, 60, 1e-10),
+                                                  (W.FP32_MIXED, 60, 1e-5)])
+def test_fullsize_sampled_electrons(P, precision, n_pre, tol):
+    """2000 electrons drawn from the full 2e7 population (during and after the
+    injection), one step: oracle vs GPU per electron within the precision's
+    bar; FP32 electrons whose discrete path differs are counted (<= 0.5 %)."""
+    cfg, srcs, _ = W.config_fp64_large()
+    cfg["precision"] = precision
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(n_pre)
+    st0 = run.get_state()
+    run.step(1)
+    st1 = run.get_state()
+    run.close()
+    n0 = len(st0["ids"])
+    print(f"  precision {precision}, step {n_pre}: {n0} electrons alive", flush=True)
+    assert n0 > 5_000_000
+    pick = np.random.default_rng(7).choice(n0, 2000, replace=False)
+    ids = st0["ids"][pick]
+    ora = OracleRun(cfg)
+    ora.set_state(dict(_subset(st0, ids), step=st0["step"], next_id=st0["next_id"]))
+    ora.step()
+    ref = ora.state()
+    got = _subset(st1, ids)
+    err, only = particle_errors(got, ref, cfg["dx"])
+    bad = (err["p"] > tol) | (err["pos"] > tol) | (err["tau"] > tol)
+    nflip = int(np.sum(bad)) + len(only)
+    print(f"  compared {len(err['ids'])}: max|dp|={err['p'][~bad].max():.2e} "
+          f"max|dx|/dx={err['pos'][~bad].max():.2e} max|dtau|={err['tau'][~bad].max():.2e} "
+          f"flips={nflip}", flush=True)
+    assert len(err["ids"]) > 1800
+    assert nflip <= (0 if precision == W.FP64 else 0.005 * len(ids)), (nflip, only[:10])
+    assert err["w"].max() <= tol
+
+
+def _check_run_properties(t, st):
+    """Properties of a whole run at any size."""
+    assert _closure(t) < 1e-6
+    led = t["ledger"]
+    # every photon's energy went to exactly one bin or flow slot
+    radiated = float(np.sum(t["hist_E"])) + t["flow"][0] + t["flow"][2]
+    assert radiated == pytest.approx(led["rad_discrete"], rel=1e-9)
+    assert 0 <= led["photon_thr"] <= led["rad_discrete"] * (1 + 1e-12)
+    assert t["counters"]["n_emitted"] > 0 and t["counters"]["n_reflux"] > 0
+
+
+def test_fullsize_fp64_run_properties(P):
+    """60 steps of the 2e7-electron FP64 workload (all of the 1 ps injection):
+    ledger closure, tally sums and the tile order of the sorted buffer."""
+    cfg, srcs, _ = W.config_fp64_large()
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(60)
+    t = run.tally()
+    st = run.get_state()
+    run.close()
+    print(f"  closure {_closure(t):.2e}, alive {t['n_alive']}", flush=True)
+    _check_run_properties(t, st)
+    assert len(st["ids"]) == t["n_alive"]
+    # the buffer is in tile order after the step's sort (4^3-cell tiles, x fastest)
+    c = np.floor(st["pos"] / cfg["dx"]).astype(np.int64)
+    ntx, nty = cfg["nx"] // 4, cfg["ny"] // 4
+    tile = (c[:, 0] >> 2) + ntx * ((c[:, 1] >> 2) + nty * (c[:, 2] >> 2))
+    assert np.all(np.diff(tile) >= 0)
+    # ids are unique
+    assert len(np.unique(st["ids"])) == len(st["ids"])
+
+
+def test_fullsize_fp32_256cube_properties(P):
+    """The 1e8-electron FP32-mixed 256^3 workload through its injection:
+    ledger closure and tally sums at full size."""
+    cfg, srcs, _ = W.config_mixed_large()
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(55)
+    t = run.tally()
+    run.close()
+    print(f"  closure {_closure(t):.2e}, alive {t['n_alive']}", flush=True)
+    assert t["n_alive"] > 50_000_000
+    _check_run_properties(t, None)
