@@ -16,6 +16,8 @@ namespace hyb {
 
 constexpr int kBlock = kChunk;
 constexpr int kWaves = kBlock / 64;
+constexpr int kHalo = kTile + 2;              // node span of a tile's stencils
+constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
 
 // integer adds into LDS words
 __device__ __forceinline__ void lds_add(long long* p, long long v) {
@@ -178,6 +180,20 @@ __device__ __forceinline__ T gather8(gptr<const T> F, int sx, int sxy, const Axi
   return az.w0 * (ay.w0 * v00 + ay.w1 * v10) + az.w1 * (ay.w0 * v01 + ay.w1 * v11);
 }
 
+// The same from a 6^3-node halo in LDS whose first node is (bx, by, bz).
+template <typename T>
+__device__ __forceinline__ T gather8_lds(const T* __restrict__ F, int bx, int by, int bz, const Axis<T>& ax,
+                                         const Axis<T>& ay, const Axis<T>& az) {
+  const int i0 = ax.i0 - bx, i1 = ax.i1 - bx;
+  const int j0 = (ay.i0 - by) * kHalo, j1 = (ay.i1 - by) * kHalo;
+  const int k0 = (az.i0 - bz) * kHalo * kHalo, k1 = (az.i1 - bz) * kHalo * kHalo;
+  const T v00 = ax.w0 * F[j0 + k0 + i0] + ax.w1 * F[j0 + k0 + i1];
+  const T v10 = ax.w0 * F[j1 + k0 + i0] + ax.w1 * F[j1 + k0 + i1];
+  const T v01 = ax.w0 * F[j0 + k1 + i0] + ax.w1 * F[j0 + k1 + i1];
+  const T v11 = ax.w0 * F[j1 + k1 + i0] + ax.w1 * F[j1 + k1 + i1];
+  return az.w0 * (ay.w0 * v00 + ay.w1 * v10) + az.w1 * (ay.w0 * v01 + ay.w1 * v11);
+}
+
 // ---------------------------------------------------------------------------
 // reflux / escape on one axis (Sec. II.A).  Returns false if the electron
 // leaves the simulation.
@@ -249,8 +265,6 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 // electrons can move to in one step; everything else falls back to global
 // atomics.  The LDS sums are flushed with one atomic per non-zero entry.
 // ---------------------------------------------------------------------------
-constexpr int kHalo = kTile + 2;              // node span of a tile's stencils
-constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
 // (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
 // contribution to 2^23 units -- as fine as the FP32 state itself -- so the LDS
@@ -266,7 +280,7 @@ constexpr int kHaloN = kHalo * kHalo * kHalo; // 216
 // (w / w_ref <= 2), so it cannot overflow.
 template <typename T> struct JAcc {
   using type = long long;
-  static constexpr int shift = 0, copies = 4;
+  static constexpr int shift = 0, copies = 2;
 };
 template <> struct JAcc<float> {
   using type = int;
@@ -289,6 +303,7 @@ struct ChunkLds {
   long long led[L_N + C_N];   // rare ledger terms and event counts of the block
   T ph[6][kBlock];            // emitted photon of each lane: k, u (3), |u|, gamma
   T tsig[kLdsTab], tsub[kLdsTab];   // cross-section columns of the tables, if they fit
+  T F[2][6][kHaloN];                // E, B on the 6^3-node halos of the two homes
 };
 
 struct Home {
@@ -450,8 +465,10 @@ __device__ __forceinline__ unsigned wave_rank(unsigned* cnt, int b) {
 
 // Tally of one photon (Sec. II.C, Table I bins): emitted at energy k about
 // the electron direction u (|u| = um, Lorentz factor g), weight wn / boost.
+// Returns the emitting electron's new optical depth, drawn from the same
+// variates.
 template <typename T>
-__device__ __forceinline__ void photon_tally(const RunDesc& R, ChunkLds<T>& S, T wn, uint32_t id, long long step) {
+__device__ __forceinline__ T photon_tally(const RunDesc& R, ChunkLds<T>& S, T wn, uint32_t id, long long step) {
   const int t = threadIdx.x;
   const T kph = S.ph[0][t], um = S.ph[4][t], g = S.ph[5][t];
   T dxp = S.ph[1][t], dyp = S.ph[2][t], dzp = S.ph[3][t];
@@ -484,6 +501,7 @@ __device__ __forceinline__ void photon_tally(const RunDesc& R, ChunkLds<T>& S, T
   if (kph >= (T)R.Ethr) lds_add(&S.led[L_PHOTON_THR], vE);
   lds_add(&S.led[L_RAD_D], vE);
   lds_add(&S.led[L_N + C_EMITTED], 1LL);
+  return -m_log((T)1 - pd.c);   // the electron's next optical depth
 }
 
 // XCD-aware chunk range of a workgroup: workgroup b runs on XCD b % 8, so
@@ -592,6 +610,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     // the other slot was last read before the previous chunk's flush
     if (threadIdx.x == 0) { S.lo[slot ^ 1] = kNoTile; S.hi[slot ^ 1] = -1; }
     const Home hm = make_home(R, tlo), hm2 = make_home(R, thi);
+    if (phys & PHYS_FIELDS) {
+      // the field halos of the two homes, staged in LDS (rows of 6 nodes along
+      // x are contiguous in HBM); nodes outside the grid are never gathered
+      const int nreg = hm.ok ? (hm2.ok && thi != tlo ? 2 : 1) : 0;
+#pragma unroll 1
+      for (int f = 0; f < 6; ++f) {
+        const gptr<const T> src = f == 0 ? E0 : f == 1 ? E1 : f == 2 ? E2 : f == 3 ? B0 : f == 4 ? B1 : B2;
+        for (int t = threadIdx.x; t < nreg * kHaloN; t += kBlock) {
+          const int r = t >= kHaloN, l = t - r * kHaloN;
+          const int i = (r ? hm2.bx : hm.bx) + l % kHalo, j = (r ? hm2.by : hm.by) + (l / kHalo) % kHalo;
+          const int k = (r ? hm2.bz : hm.bz) + l / (kHalo * kHalo);
+          T v = (T)0;
+          if (i >= 0 && j >= 0 && k >= 0 && i <= nx && j <= ny && k <= nz) v = src[i + sx * j + sxy * k];
+          S.F[r][f][l] = v;
+        }
+      }
+      __syncthreads();
+    }
     int dest_bin = -1;
     if (cell != kDead) {
       // home region of the electron: 0 (smallest tile), 1 (largest), -1 none
@@ -610,12 +646,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
 
       // --- gather + Boris push (q = -e) ---
       if (phys & PHYS_FIELDS) {
-        const T Ex = gather8(E0, sx, sxy, sxa, nya, nza);
-        const T Ey = gather8(E1, sx, sxy, nxa, sya, nza);
-        const T Ez = gather8(E2, sx, sxy, nxa, nya, sza);
-        const T Bx = gather8(B0, sx, sxy, nxa, sya, sza);
-        const T By = gather8(B1, sx, sxy, sxa, nya, sza);
-        const T Bz = gather8(B2, sx, sxy, sxa, sya, nza);
+        T Ex, Ey, Ez, Bx, By, Bz;
+        if (reg >= 0) {   // from the home halo staged in LDS
+          const T* F = &S.F[reg][0][0];
+          Ex = gather8_lds(F, rbx, rby, rbz, sxa, nya, nza);
+          Ey = gather8_lds(F + kHaloN, rbx, rby, rbz, nxa, sya, nza);
+          Ez = gather8_lds(F + 2 * kHaloN, rbx, rby, rbz, nxa, nya, sza);
+          Bx = gather8_lds(F + 3 * kHaloN, rbx, rby, rbz, nxa, sya, sza);
+          By = gather8_lds(F + 4 * kHaloN, rbx, rby, rbz, sxa, nya, sza);
+          Bz = gather8_lds(F + 5 * kHaloN, rbx, rby, rbz, sxa, sya, nza);
+        } else {
+          Ex = gather8(E0, sx, sxy, sxa, nya, nza);
+          Ey = gather8(E1, sx, sxy, nxa, sya, nza);
+          Ez = gather8(E2, sx, sxy, nxa, nya, sza);
+          Bx = gather8(B0, sx, sxy, nxa, sya, sza);
+          By = gather8(B1, sx, sxy, sxa, nya, sza);
+          Bz = gather8(B2, sx, sxy, sxa, sya, nza);
+        }
         const T ex = e_kick * Ex, ey = e_kick * Ey, ez = e_kick * Ez;
         const T mx = ux + ex, my = uy + ey, mz = uz + ez;
         const T gi = b_rot / m_sqrt((T)1 + mx * mx + my * my + mz * mz);
@@ -701,7 +748,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         T kph = (T)0;
         if (tau < (T)0) {
           kph = tab.kcut * m_exp(xs * (lne - tab.ln_kcut));
-          tau = -m_log((T)1 - draws<T>(id, R.seed, step, SLOT_PHOTON).c);
+          // the optical depth is redrawn with the photon's tally below
           // the photon's tally waits in LDS for the end of this electron's step
           const int t = threadIdx.x;
           S.ph[0][t] = kph; S.ph[1][t] = ux; S.ph[2][t] = uy; S.ph[3][t] = uz; S.ph[4][t] = um; S.ph[5][t] = g;
@@ -789,7 +836,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         // electron's state is still live; the empty asm keeps the compiler
         // from carrying the queued values in registers instead of LDS
         asm volatile("" ::: "memory");
-        photon_tally(R, S, wn, id, step);
+        const T tau_new = photon_tally(R, S, wn, id, step);
+        if (alive) P.tau[i] = tau_new;
       }
     }
     if (count) {
