@@ -573,8 +573,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   long long base_at = -1, far_at = -1;
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
-    if (base_at >= 0) { G(R.chunk_base)[base_at] = base_val; base_at = -1; }
-    if (far_at >= 0) { G(R.far_off)[far_at] = far_val; far_at = -1; }
     const long long i = ch * kBlock + threadIdx.x;
     const uint32_t cell = cell_next;
     {
@@ -628,6 +626,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       }
       __syncthreads();
     }
+    // offsets returned by the previous chunk's atomics: waiting for them here
+    // costs nothing, this chunk's loads (issued later) have landed
+    if (base_at >= 0) { G(R.chunk_base)[base_at] = base_val; base_at = -1; }
+    if (far_at >= 0) { G(R.far_off)[far_at] = far_val; far_at = -1; }
     int dest_bin = -1;
     if (cell != kDead) {
       // home region of the electron: 0 (smallest tile), 1 (largest), -1 none
