@@ -296,8 +296,10 @@ constexpr int kLdsTab = 128;   // table rows staged in LDS
 // chunks, so that a chunk's reduction never races the previous chunk's reads.
 template <typename T>
 struct ChunkLds {
-  typename JAcc<T>::type J[2][3 * kHaloN * JAcc<T>::copies];
-  long long heat[2][kTile * kTile * kTile * kHeatCopies];
+  // three region slots: the chunk's two homes and the region carried over
+  // from the previous chunk of the workgroup
+  typename JAcc<T>::type J[3][3 * kHaloN * JAcc<T>::copies];
+  long long heat[3][kTile * kTile * kTile * kHeatCopies];
   unsigned cnt[kNbN];
   int lo[2], hi[2];
   long long led[L_N + C_N];   // rare ledger terms and event counts of the block
@@ -339,8 +341,8 @@ __device__ __forceinline__ int nb_bin(const Home& h, int tx, int ty, int tz) {
 
 template <typename T>
 __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
-  for (int t = threadIdx.x; t < 2 * 3 * kHaloN * JAcc<T>::copies; t += kBlock) (&L.J[0][0])[t] = 0;
-  for (int t = threadIdx.x; t < 2 * kTile * kTile * kTile * kHeatCopies; t += kBlock) (&L.heat[0][0])[t] = 0;
+  for (int t = threadIdx.x; t < 3 * 3 * kHaloN * JAcc<T>::copies; t += kBlock) (&L.J[0][0])[t] = 0;
+  for (int t = threadIdx.x; t < 3 * kTile * kTile * kTile * kHeatCopies; t += kBlock) (&L.heat[0][0])[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x < 2) { L.lo[threadIdx.x] = kNoTile; L.hi[threadIdx.x] = -1; }
   if (threadIdx.x < L_N + C_N) L.led[threadIdx.x] = 0;
@@ -508,6 +510,22 @@ __device__ __forceinline__ T photon_tally(const RunDesc& R, ChunkLds<T>& S, T wn
 // each XCD gets one contiguous eighth of the (tile-sorted) chunks.
 struct ChunkRange { long long beg, end, stride; };
 
+// The same eighth cut into one contiguous run of chunks per workgroup (a
+// tile split between two chunks then stays in one workgroup's LDS).
+__device__ __forceinline__ ChunkRange chunk_run(const BlockMap& bm, long long n) {
+  const long long nch = (n + kBlock - 1) / kBlock;
+  const long long per = (nch + 7) >> 3;
+  const int xcd = bm.lb & 7;
+  const long long lo = (long long)xcd * per, hi = lo + per < nch ? lo + per : nch;
+  const long long nbx = bm.nb >> 3, q = bm.lb >> 3;
+  const long long m = (hi - lo + nbx - 1) / nbx;
+  ChunkRange r;
+  r.beg = lo + q * m;
+  r.end = r.beg + m < hi ? r.beg + m : hi;
+  r.stride = 1;
+  return r;
+}
+
 __device__ __forceinline__ ChunkRange chunk_range(const BlockMap& bm, long long n) {
   const long long nch = (n + kBlock - 1) / kBlock;
   const long long per = (nch + 7) >> 3;
@@ -557,7 +575,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   const T ledS = (T)kLedScale;
 
 
-  const ChunkRange cr = chunk_range(bm, n);
+  const ChunkRange cr = chunk_run(bm, n);
   lds_init(S);
   const bool lds_tab = R.tab_nT <= kLdsTab;
   if (lds_tab)
@@ -571,6 +589,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   // tile offsets returned by the counting atomics, stored a chunk later
   unsigned base_val = 0, far_val = 0;
   long long base_at = -1, far_at = -1;
+  int carry_js = -1, carry_tile = -1;   // LDS region slot carried over, and its tile
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
     const long long i = ch * kBlock + threadIdx.x;
@@ -608,6 +627,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     // the other slot was last read before the previous chunk's flush
     if (threadIdx.x == 0) { S.lo[slot ^ 1] = kNoTile; S.hi[slot ^ 1] = -1; }
     const Home hm = make_home(R, tlo), hm2 = make_home(R, thi);
+    // LDS region slots of the homes: a home that is the tile carried over
+    // keeps its slot (its sums go on accumulating), the others take clean slots
+    const bool two = hm2.ok && thi != tlo;
+    int js_lo = -1, js_hi = -1;
+    if (hm.ok) js_lo = carry_js >= 0 && carry_tile == tlo ? carry_js : (carry_js == 0 ? 1 : 0);
+    if (two) {
+      if (carry_js >= 0 && carry_tile == thi) js_hi = carry_js;
+      else {
+        js_hi = 0;
+        while (js_hi == js_lo || js_hi == carry_js) ++js_hi;
+      }
+    }
     if (phys & PHYS_FIELDS) {
       // the field halos of the two homes, staged in LDS (rows of 6 nodes along
       // x are contiguous in HBM); nodes outside the grid are never gathered
@@ -635,7 +666,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       // home region of the electron: 0 (smallest tile), 1 (largest), -1 none
       const int reg = my_tile == tlo ? 0 : (my_tile == thi ? 1 : -1);
       const int rbx = reg == 1 ? hm2.bx : hm.bx, rby = reg == 1 ? hm2.by : hm.by, rbz = reg == 1 ? hm2.bz : hm.bz;
-      typename JAcc<T>::type* Js = reg >= 0 ? S.J[reg] : nullptr;
+      const int js = reg == 0 ? js_lo : (reg == 1 ? js_hi : -1);
+      typename JAcc<T>::type* Js = js >= 0 ? S.J[js] : nullptr;
       const int heat_cell = ci + nx * (cj + ny * ck);
       const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
 
@@ -814,7 +846,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       }
       if (heat != 0) {
         if (reg >= 0)
-          lds_add(&S.heat[reg][heat_local * kHeatCopies + (threadIdx.x & (kHeatCopies - 1))], heat);
+          lds_add(&S.heat[js][heat_local * kHeatCopies + (threadIdx.x & (kHeatCopies - 1))], heat);
         else atomic_add_i64(&R.ion_heat[heat_cell], heat);
       }
       if (!alive) {
@@ -853,8 +885,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     __syncthreads();
     // LDS sums to HBM; the flush also clears them, and the next chunk writes
     // LDS only after its own barrier
-    if (hm.ok) lds_flush_region(R, S, 0, hm);
-    if (hm2.ok && thi != tlo) lds_flush_region(R, S, 1, hm2);
+    {
+      // the region of the largest home carries over to the next chunk (its
+      // tile usually continues there); the rest is flushed
+      const bool last = ch + cr.stride >= cr.end;
+      const int keep = last ? -1 : (two ? js_hi : js_lo);
+      if (hm.ok && js_lo != keep) lds_flush_region(R, S, js_lo, hm);
+      if (two && js_hi != keep) lds_flush_region(R, S, js_hi, hm2);
+      if (carry_js >= 0 && carry_js != js_lo && carry_js != js_hi) lds_flush_region(R, S, carry_js, make_home(R, carry_tile));
+      carry_js = keep;
+      carry_tile = keep < 0 ? -1 : (two ? thi : tlo);
+    }
     if (count) {
       lds_flush_counts(R, S, hm, ch, base_val, base_at);
       if (threadIdx.x == 0) G(R.chunk_home)[ch] = tlo;
@@ -968,7 +1009,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
   const PartG<T> B = part_g<T>(R.p[ctr->cur ^ 1]);
   __shared__ unsigned cnt[2][kNbN];   // rank counters, alternating between chunks
   if (threadIdx.x < kNbN) { cnt[0][threadIdx.x] = 0; cnt[1][threadIdx.x] = 0; }
-  const ChunkRange cr = chunk_range(bm, n);
+  const ChunkRange cr = chunk_run(bm, n);
   int p = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, p ^= 1) {
     // the counters of the other parity were last used by the previous chunk
