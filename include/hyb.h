@@ -63,7 +63,11 @@ enum {
   HYB_PHYS_EVOLVE_E = 1 << 4,  /* E from eq. (Ampere_Maxwell) each sub-cycle */
   HYB_PHYS_EVOLVE_B = 1 << 5,  /* B from eq. (Faraday_Lens) */
   HYB_PHYS_HEAT = 1 << 6,      /* App. A heating, exchange and resistivity */
-  HYB_PHYS_ALL = 0x7F
+  HYB_PHYS_ALL = 0x7F,
+  /* bremsstrahlung cross-sections enhanced by the background ionisation,
+   * eq. (F_sigma), per cell from the start-of-step temperatures; not part
+   * of HYB_PHYS_ALL */
+  HYB_PHYS_FSIGMA = 1 << 7
 };
 
 /* energy ledger terms (hyb_tally_out.ledger), J */

@@ -10,7 +10,9 @@ the reading both implementations follow):
   4. move x^{n+1} = x^n + v dt
   5. ionisation loss (eq. stop_ion) -> ledger and the cell's heat
   6. bremsstrahlung by the optical-depth method (App. B), at most one
-     emission per step, boosted cross-section (Sec. II.B); sub-cut loss
+     emission per step, boosted cross-section (Sec. II.B); sub-cut loss;
+     optionally both enhanced by eq. F_sigma of the cell at x^n, from the
+     temperatures at the start of the step
   7. Davies elastic scatter (App. B)
   8. boundaries x, y, z: escape or reflux (Sec. II.A)
   9. removal below e_min, remaining energy -> the cell's heat
@@ -40,6 +42,7 @@ PHYS_SCATTER = 1 << 3
 PHYS_EVOLVE_E = 1 << 4
 PHYS_EVOLVE_B = 1 << 5
 PHYS_HEAT = 1 << 6
+PHYS_FSIGMA = 1 << 7
 
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
                "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr", "residual")
@@ -175,6 +178,12 @@ class OracleRun:
         phys = int(c["physics"])
         L = self.ledger
         self._inject(n)
+        # eq. F_sigma from the temperatures at the start of the step
+        fsig = None
+        if phys & PHYS_FSIGMA:
+            fsig = np.ones_like(self.Te)
+            s = self.solid
+            fsig[s] = S.f_sigma(self.Te[s], self.Ti[s], self.Z, self.A, self.rho)
 
         idx = np.nonzero(self.alive)[0]
         pos = self.X[idx].copy()
@@ -227,9 +236,11 @@ class OracleRun:
             B_ = float(c["brem_boost"])
             g2 = PT.gamma_of(p)
             beta2 = np.sqrt(np.sum(p * p, axis=-1)) / (g2 * K.ME * K.C)
-            tau = tau - B_ * self.n_i * self.cz * self.table.sigma(eps2) * beta2 * K.C * dt
+            # cross-sections of the cell at x^n, enhanced by eq. F_sigma if enabled
+            fs = fsig[cell] if fsig is not None else 1.0
+            tau = tau - B_ * self.n_i * self.cz * fs * self.table.sigma(eps2) * beta2 * K.C * dt
             emit = tau < 0.0
-            sub = self.n_i * self.cz * self.table.sub(eps2) * beta2 * K.C * dt
+            sub = self.n_i * self.cz * fs * self.table.sub(eps2) * beta2 * K.C * dt
             if np.any(emit):
                 kph[emit] = self.table.sample_k(eps2[emit], u_c[3][emit])
             p_pre = p.copy()

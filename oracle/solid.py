@@ -134,6 +134,25 @@ def heat_update(Te, Ti, j2, ion_heat, eta, dt, dV, Z, A, rho, lambda1, lambda2):
     return Te2, Ti2, eta2
 
 
+def f_sigma(Te, Ti, Z, A, rho):
+    """Enhancement factor of the bremsstrahlung cross-sections by the
+    ionisation of the background (eq. F_sigma, Sec. II.B):
+      F = 1 + ln|lambda_D / a_s| / ln|a_s m_e c / hbar| (Z*/Z)^2,
+    lambda_D the Debye length of the background ions,
+    lambda_D^-2 = Z*^2 e^2 n_i / (eps0 kB Ti), a_s = 1.4 a_B Z^(-1/3).
+    Reading: the printed ln|a_s m_e c^2 / hbar| is not dimensionless; with
+    m_e c (a_s over the reduced Compton wavelength) it is the complete-
+    screening logarithm ln(192 Z^(-1/3)), so a fully ionised cell has the
+    ratio of the two screening logarithms, ln(lambda_D/lbar_C)/ln(a_s/lbar_C)."""
+    Te = np.asarray(Te, dtype=np.float64)
+    Ti = np.asarray(Ti, dtype=np.float64)
+    n_i = ion_density(rho, A)
+    Zs = zstar_more(Z, A, rho, Te)
+    lam = np.sqrt(K.EPS0 * K.KB * Ti / (Zs * Zs * K.E * K.E * n_i))
+    a_s = 1.4 * K.A_BOHR * Z ** (-1.0 / 3.0)
+    return 1.0 + np.log(np.abs(lam / a_s)) / np.log(abs(a_s * K.ME * K.C / K.HBAR)) * (Zs / Z) ** 2
+
+
 def n_sub_auto(dt, dx, Z, A, rho, T0, lambda1, lambda2):
     """Field sub-cycles for the explicit resistive diffusion of
     eqs. (Ampere_Maxwell, Faraday_Lens): stable for dt_sub <= mu0 dx^2/(6 eta).

@@ -36,7 +36,7 @@ size_t hist_stride(const hyb_config& c) {
 
 // Sizes of everything a run keeps in device memory.
 struct Layout {
-  size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta, off_heat;
+  size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta, off_heat, off_fsig;
   size_t off_part[2][10];
   size_t off_tabX, off_tabSIG, off_tabSUB;
   size_t off_acc_led, off_acc_hist, off_events, off_tot_led, off_tot_led_c, off_tot_hist, off_tot_hist_c;
@@ -60,6 +60,7 @@ Layout make_layout(const hyb_config& c) {
   L.off_Ti = take(cells * 8);
   L.off_eta = take(cells * 8);
   L.off_heat = take(cells * 8);
+  L.off_fsig = take(cells * ts);
   for (int b = 0; b < 2; ++b) {
     L.off_part[b][0] = take(cap * 4);                       // cell
     for (int f = 1; f < 9; ++f) L.off_part[b][f] = take(cap * ts);
@@ -183,7 +184,7 @@ static std::string validate(const hyb_config& c) {
   if (c.tally_nE < 1 || c.tally_ntheta < 1 || !(c.tally_Ehi > c.tally_Elo) || !(c.tally_Elo > 0)) return "bad tally bins";
   if (c.series_len < 0) return "series_len must be >= 0";
   if (c.max_particles < 1 || c.max_particles > 2000000000LL) return "max_particles out of range";
-  if ((c.physics & ~0x7Fu) != 0) return "unknown physics bits";
+  if ((c.physics & ~0xFFu) != 0) return "unknown physics bits";
   if (c.eta_fixed < 0) return "eta_fixed must be >= 0";
   if (c.n_sub < 0 || c.n_sub > 1000) return "n_sub out of range";
   if (c.sort_every < 0) return "sort_every must be >= 0";
@@ -282,6 +283,7 @@ static void point_desc(hyb_run* r) {
   h.Ti = (double*)(b + L.off_Ti);
   h.eta = (double*)(b + L.off_eta);
   h.ion_heat = (long long*)(b + L.off_heat);
+  h.fsig = b + L.off_fsig;
   for (int k = 0; k < 2; ++k) {
     PartPtrs& p = h.p[k];
     p.cell = (uint32_t*)(b + L.off_part[k][0]);
@@ -385,6 +387,26 @@ static hyb_status upload_plans(hyb_run* owner, hipStream_t s, const PlanSpec& ps
 }
 
 // Allocate and initialise a run's device state (no plans).
+// eq. F_sigma of every cell from the temperatures on the device (1 outside
+// the solid), in the run's precision.
+static hipError_t refresh_fsig(hyb_run* r) {
+  const hyb_config& c = r->cfg;
+  const size_t cells = (size_t)r->h.cells;
+  std::vector<double> Te(cells), Ti(cells), f(cells, 1.0);
+  hipError_t e = hipMemcpy(Te.data(), r->h.Te, cells * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(Ti.data(), r->h.Ti, cells * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < c.nz; ++k)
+    for (int j = 0; j < c.ny; ++j)
+      for (int i = r->h.ix_lo; i < r->h.ix_hi; ++i) {
+        const size_t q = i + (size_t)c.nx * (j + (size_t)c.ny * k);
+        f[q] = f_sigma(r->h.solid, Ti[q], zstar(r->h.solid, Te[q]));
+      }
+  if (c.precision == HYB_FP64) return hipMemcpy(r->h.fsig, f.data(), cells * 8, hipMemcpyHostToDevice);
+  std::vector<float> g(f.begin(), f.end());
+  return hipMemcpy(r->h.fsig, g.data(), cells * 4, hipMemcpyHostToDevice);
+}
+
 static hyb_status create_run(const hyb_config* cfg, const hyb_device* dev, hyb_run** out) {
   if (!cfg || !dev || !out) return HYB_EINVAL;
   *out = nullptr;
@@ -437,6 +459,7 @@ static hyb_status create_run(const hyb_config* cfg, const hyb_device* dev, hyb_r
     HIPCHK(r, hipMemcpy(r->h.Ti, T.data(), ncells * 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemcpy(r->h.eta, eta.data(), ncells * 8, hipMemcpyHostToDevice));
   }
+  HIPCHK(r, refresh_fsig(r));
   (void)nodes;
   Counters ctr{};
   ctr.active = 1;
@@ -896,6 +919,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   if (st->Te) HIPCHK(r, hipMemcpy(r->h.Te, st->Te, cells * 8, hipMemcpyHostToDevice));
   if (st->Ti) HIPCHK(r, hipMemcpy(r->h.Ti, st->Ti, cells * 8, hipMemcpyHostToDevice));
   if (st->eta) HIPCHK(r, hipMemcpy(r->h.eta, st->eta, cells * 8, hipMemcpyHostToDevice));
+  if (st->Te || st->Ti) HIPCHK(r, refresh_fsig(r));
   HIPCHK(r, hipMemset(r->h.ion_heat, 0, cells * 8));
   HIPCHK(r, hipMemset(r->h.acc_led, 0, 16 * 8));
   HIPCHK(r, hipMemset(r->h.acc_hist, 0, hist_stride(c) * kHistCopies * 8));

@@ -39,7 +39,7 @@ enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_N };
 
 enum : uint32_t {
   PHYS_FIELDS = 1u << 0, PHYS_ION = 1u << 1, PHYS_BREM = 1u << 2, PHYS_SCATTER = 1u << 3,
-  PHYS_EVOLVE_E = 1u << 4, PHYS_EVOLVE_B = 1u << 5, PHYS_HEAT = 1u << 6
+  PHYS_EVOLVE_E = 1u << 4, PHYS_EVOLVE_B = 1u << 5, PHYS_HEAT = 1u << 6, PHYS_FSIGMA = 1u << 7
 };
 
 constexpr uint32_t kDead = 0xFFFFFFFFu;
@@ -93,6 +93,8 @@ struct Solid {
   double tf_c;    // Fermi temperature / n_e^(2/3): hbar^2 (3 pi^2)^(2/3) / (2 m_e k_B)
   double r0;      // ion-sphere radius (3 / (4 pi n_i))^(1/3)
   double th_c;    // tau_hot = th_c (k_B Te)^1.5 / (Z*^2 n_i lnL)
+  double a_s;     // atomic screening length 1.4 a_B Z^(-1/3)
+  double ln_as;   // ln(a_s m_e c / hbar), the complete-screening logarithm
   double tc_c;    // electron-ion exchange: 1 / tau = tc_c lnL / (Te m_i + Ti m_e)^1.5
 };
 
@@ -134,6 +136,7 @@ struct RunDesc {
   void* E[3]; void* B[3];
   long long* J[3];
   double* Te; double* Ti; double* eta;
+  void* fsig;               // [cells] eq. F_sigma of each cell (run precision), start of step
   long long* ion_heat;
   PartPtrs p[2];
   Counters* ctr;

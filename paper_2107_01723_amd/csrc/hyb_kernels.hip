@@ -777,8 +777,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         }
         const T um = m_sqrt(u2);
         const T beta = um / g;
-        tau -= (T)R.k_brem * (above ? sg0 + tf * (sg1 - sg0) : (T)0) * beta;
-        const T sub = (T)R.k_sub * (above ? sb0 + tf * (sb1 - sb0) : eps2) * beta;
+        // cross-sections of the start-of-step cell, optionally times eq. F_sigma
+        const T fs = (phys & PHYS_FSIGMA) ? G((const T*)R.fsig)[heat_cell] : (T)1;
+        tau -= (T)R.k_brem * fs * (above ? sg0 + tf * (sg1 - sg0) : (T)0) * beta;
+        const T sub = (T)R.k_sub * fs * (above ? sb0 + tf * (sb1 - sb0) : eps2) * beta;
         T kph = (T)0;
         if (tau < (T)0) {
           kph = tab.kcut * m_exp(xs * (lne - tab.ln_kcut));
@@ -1159,6 +1161,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
   const long long ns = (long long)w * ny * R.nz;
   const double ju = 0.25 * R.j_unit, dV = R.dx * R.dx * R.dx;
   const bool fixed = R.eta_fixed > 0.0;
+  const bool want_fs = (R.physics & PHYS_FSIGMA) != 0;
   const Solid sol = R.solid;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < ns; t += (long long)bm.nb * kBlock) {
     const int i = R.ix_lo + (int)(t % w);
@@ -1172,9 +1175,13 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const double jx = (double)(Jx[n] + Jx[n + sx] + Jx[n + sxy] + Jx[n + sx + sxy]) * ju;
     const double jy = (double)(Jy[n] + Jy[n + 1] + Jy[n + sxy] + Jy[n + 1 + sxy]) * ju;
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
-    double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = G(R.eta)[c];
+    double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = G(R.eta)[c], fs = 1.0;
     heat_cell(sol, Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)G(R.ion_heat)[c] * R.heat_unit, R.dt, dV,
-              fixed);
+              fixed, want_fs ? &fs : nullptr);
+    if (want_fs) {
+      if (R.precision == 0) G((double*)R.fsig)[c] = fs;
+      else G((float*)R.fsig)[c] = (float)fs;
+    }
     G(R.Te)[c] = Te;
     G(R.Ti)[c] = Ti;
     G(R.eta)[c] = eta;

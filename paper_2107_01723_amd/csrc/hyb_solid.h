@@ -21,6 +21,9 @@ __host__ __device__ inline Solid make_solid(double Z, double A, double rho, doub
   s.r0 = cbrt(3.0 / (4.0 * kPi * n_i));
   s.th_c = 128.0 * kPi * kEps0 * kEps0 / (3.0 * kE * kE * kE * kE) * sqrt(kMe / (2.0 * kPi));
   s.tc_c = 2.0 / (3.0 * pow(2.0 * kPi * kKb, 1.5)) * sqrt(kMe * s.m_i) / (kEps0 * kEps0);
+  const double a_bohr = 4.0 * kPi * kEps0 * kHbar * kHbar / (kMe * kE * kE);
+  s.a_s = 1.4 * a_bohr / cbrt(Z);
+  s.ln_as = log(s.a_s * kMe * kC / kHbar);
   return s;
 }
 
@@ -62,15 +65,28 @@ __host__ __device__ inline double coulomb_log(const Solid& s, double Te, double 
   return fmax(2.0, 0.5 * log(1.0 + r * r));
 }
 
+// Bremsstrahlung enhancement by the ionised background, eq. (F_sigma):
+// 1 + ln|lambda_D / a_s| / ln(a_s m_e c / hbar) (Z*/Z)^2, lambda_D the Debye
+// length of the background ions (the printed m_e c^2 read as m_e c, which
+// makes the denominator the dimensionless complete-screening logarithm).
+__host__ __device__ inline double f_sigma(const Solid& s, double Ti, double Zs) {
+  const double lam = sqrt(kEps0 * kKb * Ti / (Zs * Zs * kE * kE * s.n_i));
+  const double q = Zs / s.Z;
+  return 1.0 + log(fabs(lam / s.a_s)) / s.ln_as * q * q;
+}
+
 // Reduced Lee-More resistivity eq. (LeeMoreGeneral) times lambda2, with
-// tau = max(hot, cold) limits of App. A.
-__host__ __device__ inline double resistivity(const Solid& s, double Te, double Ti) {
-  const double Zs = zstar(s, Te);
+// tau = max(hot, cold) limits of App. A; Zs = Z*(Te).
+__host__ __device__ inline double resistivity_z(const Solid& s, double Te, double Ti, double Zs) {
   const double lnL = coulomb_log(s, Te, Ti, Zs);
   const double kT = kKb * Te;
   const double tau_hot = s.th_c * kT * sqrt(kT) / (Zs * Zs * s.n_i * lnL);
   const double tau_cold = s.lambda1 * s.r0 / sqrt(3.0 * kT / kMe);
   return s.lambda2 * kMe / (Zs * s.n_i * kE * kE * fmax(tau_hot, tau_cold));
+}
+
+__host__ __device__ inline double resistivity(const Solid& s, double Te, double Ti) {
+  return resistivity_z(s, Te, Ti, zstar(s, Te));
 }
 
 // Heat capacity per electron in units of kB, App. A.
@@ -80,9 +96,11 @@ __host__ __device__ inline double heat_capacity(const Solid& s, double Te) {
 }
 
 // One cell: Ohmic + collisional heating eq. (Te_rise), exact electron-ion
-// exchange with rates frozen after heating, new resistivity.
+// exchange with rates frozen after heating, new resistivity and, if fs is
+// given, the new eq. (F_sigma) factor.
 __host__ __device__ inline void heat_cell(const Solid& s, double& Te, double& Ti, double& eta, double j2,
-                                          double ion_heat_J, double dt, double dV, bool fixed_eta) {
+                                          double ion_heat_J, double dt, double dV, bool fixed_eta,
+                                          double* fs = nullptr) {
   const double rho_eps = eta * j2 * dt + ion_heat_J / dV;
   const double C = heat_capacity(s, Te);
   const double Te1 = Te + rho_eps / (s.Z * s.n_i * C * kKb);
@@ -100,7 +118,10 @@ __host__ __device__ inline void heat_cell(const Solid& s, double& Te, double& Ti
   const double Ti2 = M - b / sum * D;
   Te = Te2;
   Ti = Ti2;
-  if (!fixed_eta) eta = resistivity(s, Te2, Ti2);
+  if (fixed_eta && !fs) return;
+  const double Zs2 = zstar(s, Te2);
+  if (!fixed_eta) eta = resistivity_z(s, Te2, Ti2, Zs2);
+  if (fs) *fs = f_sigma(s, Ti2, Zs2);
 }
 
 }  // namespace hyb

@@ -303,3 +303,39 @@ def test_tile_sort_changes_nothing(P, precision):
         assert np.array_equal(t["hist_E"], outs[0][0]["hist_E"])
         assert t["ledger"] == outs[0][0]["ledger"]
         assert t["n_alive"] == outs[0][0]["n_alive"]
+
+
+@pytest.mark.parametrize("precision,tol", [(W.FP64, 1e-10), (W.FP32_MIXED, 1e-5)])
+def test_f_sigma_enhancement(P, precision, tol):
+    """Eq. F_sigma on (hot, unevenly heated solid so that the factor departs
+    from 1): two steps from an identical state at 1/100 weight (fields weak,
+    so the coupled run is not chaotic); the second step uses the factors the
+    GPU computed from its own heat update.  Every electron, and the tallies."""
+    from oracle import particles as PT
+    from oracle import solid as S
+    cfg, srcs, _ = small_config(10000, precision=precision, brem_boost=10.0,
+                                physics=W.PHYS_ALL | W.PHYS_FSIGMA)
+    srcs[0]["weight"] = PT.default_weight(srcs[0], cfg["I0"]) * 0.01
+    ora = oracle_at(cfg, srcs, 40)
+    rng = np.random.default_rng(11)
+    s = ora.solid
+    ora.Te[s] = rng.uniform(5e5, 5e6, int(s.sum()))
+    ora.Ti[s] = rng.uniform(1e5, 2e7, int(s.sum()))
+    fs = S.f_sigma(ora.Te[s], ora.Ti[s], cfg["Z"], cfg["A"], cfg["rho"])
+    assert fs.min() < 0.99 or fs.max() > 1.01
+    run = gpu_from_oracle(P, cfg, srcs, ora)
+    h0 = ora.hist_E.copy()
+    ora.run(2)
+    run.step(2)
+    err, only = particle_errors(run.get_state(), ora.state(), cfg["dx"])
+    bad = (err["p"] > tol) | (err["pos"] > tol) | (err["tau"] > tol)
+    nflip = int(np.sum(bad)) + len(only)
+    print(f"  F_sigma in [{fs.min():.3f}, {fs.max():.3f}]; max|dp|={err['p'][~bad].max():.2e} "
+          f"max|dtau|={err['tau'][~bad].max():.2e} flips={nflip}", flush=True)
+    assert nflip <= (0 if precision == W.FP64 else 2e-3 * len(err["ids"]))
+    t = run.tally()
+    dh = ora.hist_E - h0
+    l1 = np.sum(np.abs(t["hist_E"] - dh)) / np.sum(np.abs(dh))   # the GPU tallies the 2 steps
+    assert l1 <= (1e-9 if precision == W.FP64 else 1e-3), l1
+    assert np.sum(dh) > 0
+    run.close()

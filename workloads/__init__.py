@@ -38,6 +38,7 @@ PHYS_SCATTER = 1 << 3     # Davies elastic scatter
 PHYS_EVOLVE_E = 1 << 4    # recompute E from Ohm's law each step
 PHYS_EVOLVE_B = 1 << 5    # advance B with Faraday's law
 PHYS_HEAT = 1 << 6        # temperature and resistivity update
+PHYS_FSIGMA = 1 << 7       # eq. F_sigma enhancement of the brem cross-sections (opt-in)
 PHYS_ALL = (PHYS_FIELDS | PHYS_ION | PHYS_BREM | PHYS_SCATTER |
             PHYS_EVOLVE_E | PHYS_EVOLVE_B | PHYS_HEAT)
 
