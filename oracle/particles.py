@@ -240,3 +240,75 @@ def inject(src, first_id, count, step, seed, ix_lo, dx, I0):
     tau = -np.log(1.0 - b1)
     w = np.full(count, default_weight(src, I0))
     return pos, p, w, tau, ids.astype(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# the paper's injection envelope (Sec. II.B, eq. N_cell, App. B)
+# ---------------------------------------------------------------------------
+def envelope_cells(env, ny, nz, dx):
+    """Face cells (j, k) that inject, in k-major order, with their f:
+    f = 2^-(2r/r_fwhm)^2 at the cell centre, kept where f >= f_min."""
+    out = []
+    for k in range(nz):
+        for j in range(ny):
+            r = math.hypot((j + 0.5) * dx - env["y0"], (k + 0.5) * dx - env["z0"])
+            f = 2.0 ** (-(2.0 * r / env["r_fwhm"]) ** 2)
+            if f >= env["f_min"]:
+                out.append((j, k, f))
+    return out
+
+
+def envelope_g(env, step, dt):
+    """Temporal envelope at the middle of step `step`: 2^-(2(t - t_peak)/t_fwhm)^2."""
+    t = (step + 0.5) * dt
+    return 2.0 ** (-(2.0 * (t - env["t_peak"]) / env["t_fwhm"]) ** 2)
+
+
+def envelope_steps(env, dt):
+    """(first step, number of steps) with g >= g_min; g is unimodal, so they
+    are contiguous."""
+    half = 0.5 * env["t_fwhm"] * math.sqrt(math.log2(1.0 / env["g_min"]))
+    lo = max(0, int(math.floor((env["t_peak"] - half) / dt)) - 2)
+    steps = [n for n in range(lo, lo + int((2 * half) / dt) + 6) if envelope_g(env, n, dt) >= env["g_min"]]
+    return steps[0], len(steps)
+
+
+def envelope_weight_max(env, I0, a0, dx, dt):
+    """Real electrons per macro-electron where f = g = 1: eq. N_cell with
+    <eps_k> = a0 m c^2, transverse cell area dx^2, divided by per_cell.  A cell
+    of envelope fg carries this times sqrt(fg) (its mean energy is
+    a0 sqrt(fg) m c^2)."""
+    return I0 * dx * dx * dt * env["eta_l2e"] / (a0 * K.MEC2 * env["per_cell"])
+
+
+def inject_envelope(env, cells, first_id, step, seed, ix_lo, dx, dt, I0, a0):
+    """per_cell macro-electrons in each injecting face cell at step `step`,
+    ids first_id.. in (cell, electron) order:
+      position: uniform over the cell's face on the slab front
+      energy: exponential with mean a m c^2, a = a0 sqrt(f g)
+      direction: uniform in a cone about +x of half-angle
+                 min(cap, atan(sqrt(2/(gamma - 1)))) (Moore scaling)
+      optical depth: tau = -ln(1 - u)
+    Returns X (cell units), p, w, tau, ids."""
+    per = int(env["per_cell"])
+    n = per * len(cells)
+    ids = (np.arange(n, dtype=np.uint64) + np.uint64(first_id)).astype(np.uint64)
+    a0_, a1, a2, a3 = P.uniforms(ids, seed, step, P.SLOT_INJECT_A)
+    b0, b1, _, _ = P.uniforms(ids, seed, step, P.SLOT_INJECT_B)
+    jj = np.repeat(np.array([c[0] for c in cells], dtype=np.float64), per)
+    kk = np.repeat(np.array([c[1] for c in cells], dtype=np.float64), per)
+    f = np.repeat(np.array([c[2] for c in cells]), per)
+    g = envelope_g(env, step, dt)
+    sq = np.sqrt(f * g)
+    pos = np.stack([np.full(n, float(ix_lo)), jj + a0_, kk + a1], axis=-1)
+    eps = -(a0 * sq * K.MEC2) * np.log(1.0 - a2)
+    gm1 = eps / K.MEC2
+    th_max = np.minimum(env["max_half_angle"], np.arctan(np.sqrt(2.0 / gm1)))
+    ct = 1.0 - a3 * (1.0 - np.cos(th_max))
+    st = np.sqrt(np.maximum(1.0 - ct * ct, 0.0))
+    pc = 2.0 * math.pi * b0
+    d = np.stack([ct, st * np.cos(pc), st * np.sin(pc)], axis=-1)
+    p = d * momentum_of_energy(eps)[:, None]
+    tau = -np.log(1.0 - b1)
+    w = envelope_weight_max(env, I0, a0, dx, dt) * sq
+    return pos, p, w, tau, ids.astype(np.uint32)

@@ -124,8 +124,29 @@ class OracleRun:
         self.next_id += int(s["n_macro"])
         self.sources.append(s)
 
+    def add_envelope(self, env: dict):
+        """Schedule the paper's envelope injection (Sec. II.B): per_cell
+        macro-electrons per step in every face cell with f >= f_min, over the
+        steps with g >= g_min; ids in (step, cell, electron) order."""
+        s = dict(env)
+        s["_kind"] = "envelope"
+        s["_cells"] = PT.envelope_cells(s, self.ny, self.nz, self.dx)
+        s["_s0"], s["_ns"] = PT.envelope_steps(s, self.dt)
+        s["_id0"] = self.next_id
+        s["_per_step"] = int(s["per_cell"]) * len(s["_cells"])
+        self.next_id += s["_per_step"] * s["_ns"]
+        self.sources.append(s)
+
     def _inject(self, n):
         for s in self.sources:
+            if s.get("_kind") == "envelope":
+                i = n - s["_s0"]
+                if 0 <= i < s["_ns"] and s["_per_step"] > 0:
+                    pos, p, w, tau, ids = PT.inject_envelope(
+                        s, s["_cells"], s["_id0"] + i * s["_per_step"], n, self.cfg["seed"],
+                        self.ix_lo, self.dx, self.dt, self.cfg["I0"], self.a0)
+                    self._append(pos, p, w, tau, ids)
+                continue
             i = n - s["_s0"]
             if i < 0 or i >= s["_ns"]:
                 continue
@@ -139,14 +160,18 @@ class OracleRun:
             src["weight"] = s["_w"]
             pos, p, w, tau, ids = PT.inject(src, first, cnt, n, self.cfg["seed"],
                                             self.ix_lo, self.dx, self.cfg["I0"])
-            self.ledger["injected"] += float(np.sum(w * PT.kinetic(p)))
-            self.counters["n_injected"] += cnt
-            self.X = np.concatenate([self.X, pos])
-            self.p = np.concatenate([self.p, p])
-            self.w = np.concatenate([self.w, w])
-            self.tau = np.concatenate([self.tau, tau])
-            self.ids = np.concatenate([self.ids, ids])
-            self.alive = np.concatenate([self.alive, np.ones(cnt, dtype=bool)])
+            self._append(pos, p, w, tau, ids)
+
+    def _append(self, pos, p, w, tau, ids):
+        cnt = len(ids)
+        self.ledger["injected"] += float(np.sum(w * PT.kinetic(p)))
+        self.counters["n_injected"] += cnt
+        self.X = np.concatenate([self.X, pos])
+        self.p = np.concatenate([self.p, p])
+        self.w = np.concatenate([self.w, w])
+        self.tau = np.concatenate([self.tau, tau])
+        self.ids = np.concatenate([self.ids, ids])
+        self.alive = np.concatenate([self.alive, np.ones(cnt, dtype=bool)])
 
     def _tally(self, k, wph, dirx, n):
         """Photon tallies: energy (log bins in [E_lo, E_hi)) x angle to +x
