@@ -148,6 +148,24 @@ typedef struct hyb_source {
   double weight;            /* real electrons per macro-electron; 0 -> from I0 */
 } hyb_source;
 
+/* The paper's own injection (Sec. II.B, eq. N_cell, App. B): in every step
+ * whose middle time t has g(t) = 2^-(2(t - t_peak)/t_fwhm)^2 >= g_min, each
+ * face cell (transverse cell of the slab's front face) whose centre has
+ * f = 2^-(2r/r_fwhm)^2 >= f_min (r from (y0, z0)) injects per_cell
+ * macro-electrons, uniform over the cell's face, with exponential kinetic
+ * energies of mean a m c^2, a = a0 sqrt(f g) (eq. a0 from cfg.I0 and
+ * cfg.wavelength), directions uniform in a cone about +x of half-angle
+ * min(max_half_angle, atan(sqrt(2/(gamma - 1)))) (Moore scaling), and the
+ * weight of eq. N_cell: I0 f g dx^2 dt eta_l2e / (a m c^2 per_cell). */
+typedef struct hyb_envelope {
+  int32_t per_cell;         /* macro-electrons per face cell per step */
+  double t_peak, t_fwhm;    /* temporal envelope [s] */
+  double y0, z0, r_fwhm;    /* spatial envelope [m] */
+  double g_min, f_min;      /* cut-offs (the paper: 0.1 and 0.5) */
+  double max_half_angle;    /* cone cap [rad] (the paper: 20 deg) */
+  double eta_l2e;           /* laser-to-electron efficiency */
+} hyb_envelope;
+
 typedef void* (*hyb_alloc_fn)(size_t bytes, void* user);
 typedef void (*hyb_free_fn)(void* ptr, void* user);
 
@@ -225,6 +243,14 @@ hyb_status hyb_init(const hyb_config* cfg, const hyb_device* dev, hyb_run** out)
  * FP32-mixed runs); HYB_ESTATE when the run already started past t_start. */
 hyb_status hyb_inject(hyb_run* run, const hyb_source* src);
 
+/* Schedule the envelope injection of hyb_envelope; it counts as a source
+ * (at most 8 per run) and ids continue the run's counter in (step, cell,
+ * electron) order.  No device work beyond uploading the cell list.
+ * HYB_EINVAL for bad parameters or when no cell or step injects;
+ * HYB_ENOSPACE when the schedule exceeds max_particles; HYB_ESTATE as for
+ * hyb_inject. */
+hyb_status hyb_inject_envelope(hyb_run* run, const hyb_envelope* env);
+
 /* Enqueue nsteps full hybrid-PIC steps (inject, push and collide, deposit,
  * Ohm + Faraday sub-cycles, heating, tallies; optional cell sort). */
 hyb_status hyb_step(hyb_run* run, int32_t nsteps);
@@ -272,8 +298,8 @@ const char* hyb_last_error(const hyb_run* run);
 const char* hyb_status_string(hyb_status s);
 
 /* sizeof of the ABI structs, for bindings to check their layouts:
- * config, source, device, tally_out, state, run_info. */
-void hyb_abi_sizes(int64_t sizes[6]);
+ * config, source, device, tally_out, state, run_info, envelope. */
+void hyb_abi_sizes(int64_t sizes[7]);
 
 /* ---------------- serving engine (continuous batching) -------------------
  * Independent runs share one device.  Each engine tick advances every

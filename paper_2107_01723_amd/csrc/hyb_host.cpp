@@ -40,7 +40,7 @@ struct Layout {
   size_t off_part[2][10];
   size_t off_tabX, off_tabSIG, off_tabSUB;
   size_t off_acc_led, off_acc_hist, off_events, off_tot_led, off_tot_led_c, off_tot_hist, off_tot_hist_c;
-  size_t off_series, off_ctr, off_src, off_tile_cnt, off_tile_start, off_scan_blk,
+  size_t off_series, off_ctr, off_src, off_env, off_tile_cnt, off_tile_start, off_scan_blk,
          off_chunk_home, off_chunk_base, off_far, off_red, off_desc;
   size_t total;
 };
@@ -81,6 +81,7 @@ Layout make_layout(const hyb_config& c) {
   L.off_series = take((size_t)std::max(1, c.series_len) * 8);
   L.off_ctr = take(sizeof(Counters));
   L.off_src = take(sizeof(SourceDesc) * kMaxSources);
+  L.off_env = take((size_t)kMaxSources * c.ny * c.nz * 4);
   const size_t ntiles = (size_t)((c.nx + kTile - 1) / kTile) * ((c.ny + kTile - 1) / kTile) *
                         ((c.nz + kTile - 1) / kTile);
   L.off_tile_cnt = take(ntiles * 4);
@@ -529,6 +530,73 @@ static hyb_status add_source(hyb_run* r, const hyb_source* s) {
   return HYB_OK;
 }
 
+static hyb_status add_envelope(hyb_run* r, const hyb_envelope* e) {
+  const hyb_config& c = r->cfg;
+  if (!e) return fail(r, HYB_EINVAL, "null envelope");
+  if ((int)r->srcs.size() >= kMaxSources) return fail(r, HYB_EINVAL, "too many sources");
+  if (e->per_cell < 1 || !(e->t_fwhm > 0) || !(e->r_fwhm > 0) || !(e->g_min > 0) || e->g_min > 1 ||
+      !(e->f_min > 0) || e->f_min > 1 || !(e->max_half_angle > 0) || e->max_half_angle > kPi ||
+      !(e->eta_l2e > 0) || !(e->t_peak >= 0))
+    return fail(r, HYB_EINVAL, "bad envelope parameters");
+  // injecting face cells, k-major: f at the cell centre >= f_min
+  std::vector<int> cells;
+  for (int k = 0; k < c.nz; ++k)
+    for (int j = 0; j < c.ny; ++j) {
+      const double rr = hypot((j + 0.5) * c.dx - e->y0, (k + 0.5) * c.dx - e->z0);
+      const double q = 2.0 * rr / e->r_fwhm;
+      if (exp2(-q * q) >= e->f_min) cells.push_back(j | (k << 16));
+    }
+  if (cells.empty()) return fail(r, HYB_EINVAL, "no face cell reaches f_min");
+  // injecting steps: g at the step's middle >= g_min (a contiguous run)
+  auto g_of = [&](long long n) {
+    const double q = 2.0 * ((n + 0.5) * c.dt - e->t_peak) / e->t_fwhm;
+    return exp2(-q * q);
+  };
+  const double half = 0.5 * e->t_fwhm * sqrt(log2(1.0 / e->g_min));
+  long long n = std::max(0LL, (long long)floor((e->t_peak - half) / c.dt) - 2);
+  const long long n_end = (long long)floor((e->t_peak + half) / c.dt) + 3;
+  while (n <= n_end && g_of(n) < e->g_min) ++n;
+  const long long s0 = n;
+  while (n <= n_end && g_of(n) >= e->g_min) ++n;
+  const long long ns = n - s0;
+  if (ns < 1) return fail(r, HYB_EINVAL, "no step reaches g_min");
+  if (s0 < r->host_step) return fail(r, HYB_ESTATE, "source starts before the current step");
+  const long long per_step = (long long)cells.size() * e->per_cell;
+  if (r->scheduled + per_step * ns > c.max_particles)
+    return fail(r, HYB_ENOSPACE, "sources exceed max_particles");
+  // eq. N_cell where f = g = 1 (a cell-step of envelope fg carries sqrt(fg) times this)
+  const double a0 = 8.5e-6 * sqrt(c.I0 * c.wavelength * c.wavelength);
+  const double w = c.I0 * c.dx * c.dx * c.dt * e->eta_l2e / (a0 * kMec2 * e->per_cell);
+  if (!r->w_locked && r->host_step == 0) r->w_ref = std::max(r->w_ref, w);
+  const double wref = r->w_ref > 0 ? r->w_ref : w;
+  const double wmax = c.precision == HYB_FP64 ? 64.0 : 2.0;
+  if (w / wref > wmax) return fail(r, HYB_EINVAL, "source weight too large for the accumulator scale");
+  int* dcells = (int*)((char*)r->base + r->lay.off_env) + r->srcs.size() * (size_t)c.ny * c.nz;
+  HIPCHK(r, hipStreamSynchronize(r->stream));
+  HIPCHK(r, hipMemcpy(dcells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice));
+  SourceDesc d{};
+  d.kind = 1;
+  d.s0 = s0;
+  d.ns = ns;
+  d.base = per_step;
+  d.rem = 0;
+  d.id0 = r->next_id;
+  d.per_cell = e->per_cell;
+  d.cells = dcells;
+  d.y0 = e->y0 / c.dx;
+  d.z0 = e->z0 / c.dx;
+  d.rf = e->r_fwhm / c.dx;
+  d.tp = e->t_peak / c.dt;
+  d.tf = e->t_fwhm / c.dt;
+  d.a0 = a0;
+  d.cap = e->max_half_angle;
+  d.wn = w;   // absolute here; divided by w_ref when uploaded
+  r->srcs.push_back(d);
+  r->next_id += per_step * ns;
+  r->scheduled += per_step * ns;
+  return HYB_OK;
+}
+
 static hyb_status upload_sources(hyb_run* r) {
   if (r->w_ref <= 0) r->w_ref = 1.0;
   set_units(r->h, r->w_ref);
@@ -611,13 +679,14 @@ const char* hyb_status_string(hyb_status s) {
 
 const char* hyb_last_error(const hyb_run* run) { return run ? run->err.c_str() : g_err.c_str(); }
 
-void hyb_abi_sizes(int64_t sizes[6]) {
+void hyb_abi_sizes(int64_t sizes[7]) {
   sizes[0] = sizeof(hyb_config);
   sizes[1] = sizeof(hyb_source);
   sizes[2] = sizeof(hyb_device);
   sizes[3] = sizeof(hyb_tally_out);
   sizes[4] = sizeof(hyb_state);
   sizes[5] = sizeof(hyb_run_info);
+  sizes[6] = sizeof(hyb_envelope);
 }
 
 hyb_status hyb_footprint(const hyb_config* cfg, int64_t* bytes) {
@@ -647,6 +716,14 @@ hyb_status hyb_inject(hyb_run* r, const hyb_source* src) {
   if (!r) return HYB_EINVAL;
   if (r->eng) return fail(r, HYB_ESTATE, "engine runs take their sources at admission");
   hyb_status st = add_source(r, src);
+  if (st != HYB_OK) return st;
+  return upload_sources(r);
+}
+
+hyb_status hyb_inject_envelope(hyb_run* r, const hyb_envelope* env) {
+  if (!r) return HYB_EINVAL;
+  if (r->eng) return fail(r, HYB_ESTATE, "engine runs take their sources at admission");
+  hyb_status st = add_envelope(r, env);
   if (st != HYB_OK) return st;
   return upload_sources(r);
 }

@@ -60,8 +60,15 @@ struct SourceDesc {
   double y0, z0;          // spot centre [cells]
   double sig2;            // r_fwhm^2 / (8 ln 2) [cells^2]
   double t_hot;           // [m c^2]
-  double one_minus_cos;   // 1 - cos(half angle)
-  double wn;              // weight / w_ref
+  double one_minus_cos;   // 1 - cos(half angle); envelope: of the cap
+  double wn;              // weight / w_ref; envelope: where f = g = 1
+  // envelope injection (kind 1): per_cell electrons in each listed face cell
+  int kind, per_cell;
+  const int* cells;       // injecting face cells, j | k << 16, k-major
+  double tp, tf;          // peak time and fwhm [steps]; step n is at n + 1/2
+  double rf;              // spatial fwhm [cells]
+  double a0;              // mean kinetic energy a0 sqrt(f g) [m c^2]
+  double cap;             // cone half-angle cap [rad]
 };
 
 // Mutable per-run counters (device memory).
@@ -265,6 +272,8 @@ __device__ __forceinline__ void m_sincos(float x, float& s, float& c) { sincosf(
 __device__ __forceinline__ void m_sincos(double x, double& s, double& c) { sincos(x, &s, &c); }
 __device__ __forceinline__ void m_sincos2pi(float t, float& s, float& c) { sincospif(2.0f * t, &s, &c); }
 __device__ __forceinline__ void m_sincos2pi(double t, double& s, double& c) { sincospi(2.0 * t, &s, &c); }
+__device__ __forceinline__ float m_atan(float x) { return atanf(x); }
+__device__ __forceinline__ double m_atan(double x) { return atan(x); }
 __device__ __forceinline__ float m_acos(float x) { return acosf(x); }
 __device__ __forceinline__ double m_acos(double x) { return acos(x); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }

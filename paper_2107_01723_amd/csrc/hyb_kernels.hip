@@ -105,13 +105,35 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     const uint32_t id = (uint32_t)(first[s] + (t - off));
     const Uni4<T> a = draws<T>(id, R.seed, step, SLOT_INJ_A);
     const Uni4<T> b = draws<T>(id, R.seed, step, SLOT_INJ_B);
-    const T r = m_sqrt((T)-2 * (T)S->sig2 * m_log((T)1 - (T)0.5 * a.a));
-    T sps, cps;
-    m_sincos2pi(a.b, sps, cps);
-    const T y = (T)S->y0 + r * cps;
-    const T z = (T)S->z0 + r * sps;
-    const T eps = -(T)S->t_hot * m_log((T)1 - a.c);
-    const T ct = (T)1 - a.d * (T)S->one_minus_cos;
+    int cy, cz;
+    T oy, oz, eps, omc, wn;
+    if (S->kind == 1) {
+      // the paper's envelope: a face cell from the list, position uniform
+      // over it, mean energy a0 sqrt(f g), Moore-scaling cone, eq. N_cell weight
+      const int cell = G(S->cells)[(int)((t - off) / S->per_cell)];
+      const int j = cell & 0xFFFF, k = cell >> 16;
+      const T qr = (T)2 * m_sqrt(((T)j + (T)0.5 - (T)S->y0) * ((T)j + (T)0.5 - (T)S->y0) +
+                                 ((T)k + (T)0.5 - (T)S->z0) * ((T)k + (T)0.5 - (T)S->z0)) / (T)S->rf;
+      const T qt = (T)2 * ((T)step + (T)0.5 - (T)S->tp) / (T)S->tf;
+      const T ln2 = (T)0.69314718055994530942;
+      const T sq = m_sqrt(m_exp(-qr * qr * ln2) * m_exp(-qt * qt * ln2));
+      cy = j; oy = a.a;
+      cz = k; oz = a.b;
+      eps = -(T)S->a0 * sq * m_log((T)1 - a.c);
+      const T th_moore = m_atan(m_sqrt((T)2 / eps));
+      omc = (T)1 - m_cos(th_moore < (T)S->cap ? th_moore : (T)S->cap);
+      wn = (T)S->wn * sq;
+    } else {
+      const T r = m_sqrt((T)-2 * (T)S->sig2 * m_log((T)1 - (T)0.5 * a.a));
+      T sps, cps;
+      m_sincos2pi(a.b, sps, cps);
+      to_cell((T)S->y0 + r * cps, R.ny, cy, oy);
+      to_cell((T)S->z0 + r * sps, R.nz, cz, oz);
+      eps = -(T)S->t_hot * m_log((T)1 - a.c);
+      omc = (T)S->one_minus_cos;
+      wn = (T)S->wn;
+    }
+    const T ct = (T)1 - a.d * omc;
     T st2 = (T)1 - ct * ct;
     const T st = m_sqrt(st2 > (T)0 ? st2 : (T)0);
     T spc, cpc;
@@ -121,10 +143,6 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     const T tau = -m_log((T)1 - b.b);
     const long long slot = n0 + t;
     if (slot >= R.capacity) break;   // never write past the particle arrays
-    int cy, cz;
-    T oy, oz;
-    to_cell(y, R.ny, cy, oy);
-    to_cell(z, R.nz, cz, oz);
     P.cell[slot] = pack_cell(R.ix_lo, cy, cz);
     P.ox[slot] = (T)0;
     P.oy[slot] = oy;
@@ -132,11 +150,11 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     P.ux[slot] = ux;
     P.uy[slot] = uy;
     P.uz[slot] = uz;
-    P.wn[slot] = (T)S->wn;
+    P.wn[slot] = wn;
     P.tau[slot] = tau;
     P.id[slot] = id;
     const T u2 = ux * ux + uy * uy + uz * uz;
-    acc[L_INJECTED] += to_fixed(kinetic(u2, m_sqrt((T)1 + u2)) * (T)S->wn * (T)kLedScale);
+    acc[L_INJECTED] += to_fixed(kinetic(u2, m_sqrt((T)1 + u2)) * wn * (T)kLedScale);
     acc[L_N + C_INJECTED] += 1;
   }
   block_flush<L_N, C_N>(acc, R.acc_led, R.events);

@@ -23,7 +23,7 @@ LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
 COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped")
 
 ABI_FUNCTIONS = (
-    "hyb_init", "hyb_inject", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
+    "hyb_init", "hyb_inject", "hyb_inject_envelope", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
     "hyb_run_info_get", "hyb_table_get", "hyb_timing_enable", "hyb_timing_get", "hyb_use_graph",
     "hyb_footprint", "hyb_free", "hyb_last_error", "hyb_status_string", "hyb_abi_sizes",
     "hyb_engine_create", "hyb_engine_admit", "hyb_engine_step", "hyb_engine_poll",
@@ -74,6 +74,16 @@ class Source(C.Structure):
         ("y0", C.c_double), ("z0", C.c_double),
         ("r_fwhm", C.c_double), ("T_hot", C.c_double), ("half_angle", C.c_double),
         ("eta_l2e", C.c_double), ("weight", C.c_double),
+    ]
+
+
+class Envelope(C.Structure):
+    _fields_ = [
+        ("per_cell", C.c_int32),
+        ("t_peak", C.c_double), ("t_fwhm", C.c_double),
+        ("y0", C.c_double), ("z0", C.c_double), ("r_fwhm", C.c_double),
+        ("g_min", C.c_double), ("f_min", C.c_double),
+        ("max_half_angle", C.c_double), ("eta_l2e", C.c_double),
     ]
 
 
@@ -135,6 +145,7 @@ def lib():
     sig = {
         "hyb_init": (C.c_int, [P(Config), P(Device), P(vp)]),
         "hyb_inject": (C.c_int, [vp, P(Source)]),
+        "hyb_inject_envelope": (C.c_int, [vp, P(Envelope)]),
         "hyb_step": (C.c_int, [vp, C.c_int32]),
         "hyb_tally": (C.c_int, [vp, P(TallyOut)]),
         "hyb_get_state": (C.c_int, [vp, P(State)]),
@@ -167,9 +178,9 @@ def lib():
 
 def check_abi():
     """Compare the ctypes struct sizes with the library's."""
-    a = (C.c_int64 * 6)()
+    a = (C.c_int64 * 7)()
     lib().hyb_abi_sizes(a)
-    mine = [C.sizeof(t) for t in (Config, Source, Device, TallyOut, State, RunInfo)]
+    mine = [C.sizeof(t) for t in (Config, Source, Device, TallyOut, State, RunInfo, Envelope)]
     if list(a) != mine:
         raise RuntimeError(f"ABI struct sizes differ: library {list(a)} binding {mine}")
     return mine
@@ -187,6 +198,13 @@ def make_source(d: dict) -> Source:
     for name, _ in Source._fields_:
         setattr(s, name, d[name])
     return s
+
+
+def make_envelope(d: dict) -> Envelope:
+    e = Envelope()
+    for name, _ in Envelope._fields_:
+        setattr(e, name, d[name])
+    return e
 
 
 def footprint(cfg: dict) -> int:
@@ -272,6 +290,10 @@ class Run:
 
     def inject(self, src: dict):
         self._check(self.L.hyb_inject(self.h, C.byref(make_source(src))), "hyb_inject")
+
+    def inject_envelope(self, env: dict):
+        """The paper's envelope injection (hyb_inject_envelope)."""
+        self._check(self.L.hyb_inject_envelope(self.h, C.byref(make_envelope(env))), "hyb_inject_envelope")
 
     def step(self, n: int = 1):
         self._check(self.L.hyb_step(self.h, int(n)), "hyb_step")

@@ -339,3 +339,36 @@ def test_f_sigma_enhancement(P, precision, tol):
     assert l1 <= (1e-9 if precision == W.FP64 else 1e-3), l1
     assert np.sum(dh) > 0
     run.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(W.FP64, 1e-10), (W.FP32_MIXED, 1e-5)])
+def test_envelope_injection(P, precision, tol):
+    """The paper's envelope injection (hyb_inject_envelope) through its whole
+    window plus a few steps, collisions on and field feedback off (particles
+    independent): every electron, the injected energy and the counts."""
+    cfg = W.base_config(nx=20, ny=24, nz=24, dx=0.7e-6, dt=5e-15, x_lo=1.4e-6, x_hi=12.6e-6,
+                        precision=precision, I0=W.intensity_wcm2(1e21), brem_boost=10.0,
+                        physics=W.PHYS_ALL & ~W.PHYS_FIELDS, max_particles=40000, series_len=64)
+    env = dict(per_cell=60, t_peak=40e-15, t_fwhm=40e-15, y0=8.1e-6, z0=8.6e-6, r_fwhm=5e-6,
+               g_min=0.1, f_min=0.5, max_half_angle=math.radians(20.0), eta_l2e=0.3)
+    ora = OracleRun(cfg)
+    ora.add_envelope(env)
+    run = P.Run(cfg)
+    run.inject_envelope(env)
+    nsteps = 25
+    ora.run(nsteps)
+    run.step(nsteps)
+    t = run.tally()
+    assert t["counters"]["n_injected"] == ora.counters["n_injected"] > 10000
+    assert t["ledger"]["injected"] == pytest.approx(ora.ledger["injected"], rel=1e-9 if precision == W.FP64 else 1e-5)
+    err, only = particle_errors(run.get_state(), ora.state(), cfg["dx"])
+    if precision == W.FP64:
+        assert not only
+        assert err["p"].max() < tol and err["pos"].max() < tol and err["tau"].max() < tol
+        assert err["w"].max() < tol
+    else:
+        pct = np.percentile(err["p"], [50, 99])
+        print(f"  FP32 envelope run: |dp| p50/p99 {pct}, one side only {len(only)}", flush=True)
+        assert len(only) < 0.01 * len(err["ids"])
+        assert err["w"].max() < 1e-6
+    run.close()
