@@ -61,3 +61,9 @@ SLOT_PHOTON = 1
 SLOT_REFLUX = (2, 3, 4)
 SLOT_INJECT_A = 8
 SLOT_INJECT_B = 9
+# Delta rays: azimuth and new optical depth of an emission; optical depths
+# of a newborn delta ray (keyed by its own id); rejection candidates of the
+# energy sampler, two per slot, in slots SLOT_DELTA_TRY .. SLOT_DELTA_TRY + 15.
+SLOT_DELTA_K = 12
+SLOT_BIRTH = 13
+SLOT_DELTA_TRY = 16

@@ -8,7 +8,11 @@ the reading both implementations follow):
   3. deposit j_h at x^n with the pushed velocity (every particle alive at
      the start of the step)
   4. move x^{n+1} = x^n + v dt
-  5. ionisation loss (eq. stop_ion) -> ledger and the cell's heat
+  5. ionisation loss (eq. stop_ion) -> ledger and the cell's heat; with
+     delta rays, the restricted loss below the cut instead (App. B)
+  5b. delta rays (App. B), optional: Moller scatter above the cut by the
+     optical-depth method with a depth of its own, at most one per step;
+     the delta ray is born at x^n, below e_min its energy is the cell's heat
   6. bremsstrahlung by the optical-depth method (App. B), at most one
      emission per step, boosted cross-section (Sec. II.B); sub-cut loss;
      optionally both enhanced by eq. F_sigma of the cell at x^n, from the
@@ -18,6 +22,8 @@ the reading both implementations follow):
   9. removal below e_min, remaining energy -> the cell's heat
  10. n_sub sub-cycles of Ohm + Faraday (App. A)
  11. Ohmic + ionisation heating, electron-ion exchange, resistivity (App. A)
+ 12. the step's delta rays join the run, ids in (tile of the birth cell,
+     parent id) order after those of earlier steps
 The heat of a particle goes to the cell that contains x^n.
 Positions are held in cell units X = x / dx so that the slab faces and the
 walls are exact integers.
@@ -30,6 +36,7 @@ import numpy as np
 
 from . import constants as K
 from . import fields as F
+from . import moller as M
 from . import particles as PT
 from . import philox as P
 from . import solid as S
@@ -43,10 +50,13 @@ PHYS_EVOLVE_E = 1 << 4
 PHYS_EVOLVE_B = 1 << 5
 PHYS_HEAT = 1 << 6
 PHYS_FSIGMA = 1 << 7
+PHYS_DELTA = 1 << 8
+DELTA_ID_BIT = 0x80000000    # delta rays take ids DELTA_ID_BIT + 0, 1, ...
 
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
                "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr", "residual")
-COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped")
+COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped", "n_delta",
+                "n_delta_lost")
 
 
 class OracleRun:
@@ -93,10 +103,13 @@ class OracleRun:
         self.p = np.zeros((0, 3))
         self.w = np.zeros(0)
         self.tau = np.zeros(0)
+        self.taud = np.zeros(0)       # optical depth to the next delta ray
         self.ids = np.zeros(0, dtype=np.uint32)
         self.alive = np.zeros(0, dtype=bool)
         self.step_index = 0
         self.next_id = 0
+        self.delta_next = 0
+        self.e_cut = float(c.get("delta_cut", 1e3 * K.E))
         self.sources = []
         self.ledger = {k: 0.0 for k in LEDGER_KEYS}
         self.counters = {k: 0 for k in COUNTER_KEYS}
@@ -145,7 +158,7 @@ class OracleRun:
                     pos, p, w, tau, ids = PT.inject_envelope(
                         s, s["_cells"], s["_id0"] + i * s["_per_step"], n, self.cfg["seed"],
                         self.ix_lo, self.dx, self.dt, self.cfg["I0"], self.a0)
-                    self._append(pos, p, w, tau, ids)
+                    self._append(pos, p, w, tau, ids, n)
                 continue
             i = n - s["_s0"]
             if i < 0 or i >= s["_ns"]:
@@ -160,18 +173,27 @@ class OracleRun:
             src["weight"] = s["_w"]
             pos, p, w, tau, ids = PT.inject(src, first, cnt, n, self.cfg["seed"],
                                             self.ix_lo, self.dx, self.cfg["I0"])
-            self._append(pos, p, w, tau, ids)
+            self._append(pos, p, w, tau, ids, n)
 
-    def _append(self, pos, p, w, tau, ids):
+    def _append(self, pos, p, w, tau, ids, n):
+        """Injected electrons; their delta-ray depth is -ln(1 - u) from the
+        third draw of the injection's second slot."""
         cnt = len(ids)
         self.ledger["injected"] += float(np.sum(w * PT.kinetic(p)))
         self.counters["n_injected"] += cnt
+        taud = np.zeros(cnt)
+        if int(self.cfg["physics"]) & PHYS_DELTA:
+            taud = -np.log(1.0 - P.uniforms(ids, self.cfg["seed"], n, P.SLOT_INJECT_B)[2])
+        self._add(pos, p, w, tau, taud, ids)
+
+    def _add(self, pos, p, w, tau, taud, ids):
         self.X = np.concatenate([self.X, pos])
         self.p = np.concatenate([self.p, p])
         self.w = np.concatenate([self.w, w])
         self.tau = np.concatenate([self.tau, tau])
+        self.taud = np.concatenate([self.taud, taud])
         self.ids = np.concatenate([self.ids, ids])
-        self.alive = np.concatenate([self.alive, np.ones(cnt, dtype=bool)])
+        self.alive = np.concatenate([self.alive, np.ones(len(ids), dtype=bool)])
 
     def _tally(self, k, wph, dirx, n):
         """Photon tallies: energy (log bins in [E_lo, E_hi)) x angle to +x
@@ -215,8 +237,10 @@ class OracleRun:
         p = self.p[idx].copy()
         w = self.w[idx]
         tau = self.tau[idx].copy()
+        taud = self.taud[idx].copy()
         ids = self.ids[idx]
         m = len(idx)
+        pos_n = pos.copy()             # x^n: birth place of this step's delta rays
 
         # push
         eps0 = PT.kinetic(p)
@@ -245,7 +269,10 @@ class OracleRun:
 
         # ionisation
         if phys & PHYS_ION:
-            Sion = PT.stopping_ion(eps1, p, self.Z, self.n_i, self.I_ex)
+            if phys & PHYS_DELTA:
+                Sion = M.restricted_stopping(eps1, self.Z, self.n_i, self.I_ex, self.e_cut)
+            else:
+                Sion = PT.stopping_ion(eps1, p, self.Z, self.n_i, self.I_ex)
             v = np.sqrt(np.sum(vel * vel, axis=-1))
             dE = np.minimum(Sion * v * dt, eps1)
             p = PT.with_energy(p, eps1 - dE)
@@ -253,6 +280,33 @@ class OracleRun:
         ion = eps1 - eps2
         L["ionisation"] += float(np.sum(w * ion))
         np.add.at(self.ion_heat, cell, w * ion)
+
+        # delta rays: Moller scatter above the cut, own optical depth
+        born = None
+        if phys & PHYS_DELTA:
+            g2 = PT.gamma_of(p)
+            beta = np.sqrt(np.sum(p * p, axis=-1)) / (g2 * K.ME * K.C)
+            taud = taud - self.n_i * M.moller_sigma(eps2, self.Z, self.e_cut) * beta * K.C * dt
+            ie = np.nonzero(taud < 0.0)[0]
+            if len(ie):
+                x = M.sample_fraction(eps2[ie], self.e_cut, M.sampler_uniforms(ids[ie], c["seed"], n))
+                e_d = x * eps2[ie]
+                uk = P.uniforms(ids[ie], c["seed"], n, P.SLOT_DELTA_K)
+                q, d = M.delta_kinematics(p[ie], eps2[ie], e_d, 2.0 * math.pi * uk[0])
+                p[ie] = q
+                taud[ie] = -np.log(1.0 - uk[1])
+                self.counters["n_delta"] += len(ie)
+                L["residual"] += float(np.sum(w[ie] * (eps2[ie] - PT.kinetic(q) - e_d)))
+                low = e_d < c["e_min"]
+                # below e_min the delta ray stops where it is born
+                cl = tuple(ci[ie[low]] for ci in cell)
+                L["stopped"] += float(np.sum(w[ie[low]] * e_d[low]))
+                np.add.at(self.ion_heat, cl, w[ie[low]] * e_d[low])
+                k = ~low
+                L["residual"] += float(np.sum(w[ie[k]] * (e_d[k] - PT.kinetic(d[k]))))
+                born = dict(pos=pos_n[ie[k]], p=d[k], w=w[ie[k]], parent=ids[ie[k]],
+                            cell=tuple(ci[ie[k]] for ci in cell))
+            eps2 = PT.kinetic(p)
 
         # bremsstrahlung
         u_c = P.uniforms(ids, c["seed"], n, P.SLOT_COLLIDE)
@@ -367,6 +421,7 @@ class OracleRun:
         self.X[idx] = pos
         self.p[idx] = p
         self.tau[idx] = tau
+        self.taud[idx] = taud
         self.alive[idx] = alive
 
         # fields
@@ -385,7 +440,28 @@ class OracleRun:
             self.Te[s], self.Ti[s] = Te, Ti
             if c["eta_fixed"] <= 0.0:
                 self.eta[s] = eta
+        if born is not None and len(born["w"]):
+            self._add_delta_rays(born, n)
         self.step_index += 1
+
+    def _add_delta_rays(self, born, n):
+        """The step's delta rays join the run: ids DELTA_ID_BIT + delta_next +
+        rank, ranked by (tile of the birth cell, parent id), tiles of 4^3
+        cells numbered x fastest; optical depths -ln(1 - u) from the first
+        two draws of the birth slot of the new id."""
+        ci, cj, ck = born["cell"]
+        ntx, nty = (self.nx + 3) // 4, (self.ny + 3) // 4
+        tile = (ci >> 2) + ntx * ((cj >> 2) + nty * (ck >> 2))
+        order = np.lexsort((born["parent"].astype(np.int64), tile))
+        cnt = len(order)
+        if self.delta_next + cnt > DELTA_ID_BIT:
+            raise OverflowError("delta-ray ids exhausted")
+        ids = (np.uint64(DELTA_ID_BIT + self.delta_next)
+               + np.arange(cnt, dtype=np.uint64)).astype(np.uint32)
+        u = P.uniforms(ids, self.cfg["seed"], n, P.SLOT_BIRTH)
+        self._add(born["pos"][order], born["p"][order], born["w"][order],
+                  -np.log(1.0 - u[0]), -np.log(1.0 - u[1]), ids)
+        self.delta_next += cnt
 
     def run(self, nsteps: int):
         for _ in range(nsteps):
@@ -417,12 +493,12 @@ class OracleRun:
         """Alive particles (in id order, positions in metres), fields, temperatures."""
         a = self.alive
         return dict(pos=self.X[a] * self.dx, p=self.p[a].copy(), w=self.w[a].copy(),
-                    tau=self.tau[a].copy(), ids=self.ids[a].copy(),
+                    tau=self.tau[a].copy(), tau_d=self.taud[a].copy(), ids=self.ids[a].copy(),
                     E=tuple(x.copy() for x in self.E), B=tuple(x.copy() for x in self.B),
                     j=tuple(x.copy() for x in self.j),
                     Te=self.Te.copy(), Ti=self.Ti.copy(), eta=self.eta.copy(),
                     ion_heat=self.ion_heat.copy(), step=self.step_index,
-                    next_id=self.next_id)
+                    next_id=self.next_id, delta_next=self.delta_next)
 
     def set_state(self, st):
         self.X = np.array(st["pos"], dtype=np.float64).reshape(-1, 3) / self.dx
@@ -430,9 +506,15 @@ class OracleRun:
         self.w = np.array(st["w"], dtype=np.float64)
         self.tau = np.array(st["tau"], dtype=np.float64)
         self.ids = np.array(st["ids"], dtype=np.uint32)
+        if st.get("tau_d") is not None:
+            self.taud = np.array(st["tau_d"], dtype=np.float64)
+        elif int(self.cfg["physics"]) & PHYS_DELTA:
+            raise ValueError("delta rays need the electrons' tau_d")
+        else:
+            self.taud = np.zeros(len(self.ids))
         order = np.argsort(self.ids, kind="stable")
-        self.X, self.p, self.w, self.tau, self.ids = (a[order] for a in
-                                                       (self.X, self.p, self.w, self.tau, self.ids))
+        self.X, self.p, self.w, self.tau, self.taud, self.ids = (
+            a[order] for a in (self.X, self.p, self.w, self.tau, self.taud, self.ids))
         self.alive = np.ones(len(self.ids), dtype=bool)
         for key in ("E", "B"):
             if key in st and st[key] is not None:
@@ -444,3 +526,5 @@ class OracleRun:
             self.step_index = int(st["step"])
         if "next_id" in st:
             self.next_id = int(st["next_id"])
+        if "delta_next" in st:
+            self.delta_next = int(st["delta_next"])

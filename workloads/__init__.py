@@ -39,6 +39,7 @@ PHYS_EVOLVE_E = 1 << 4    # recompute E from Ohm's law each step
 PHYS_EVOLVE_B = 1 << 5    # advance B with Faraday's law
 PHYS_HEAT = 1 << 6        # temperature and resistivity update
 PHYS_FSIGMA = 1 << 7       # eq. F_sigma enhancement of the brem cross-sections (opt-in)
+PHYS_DELTA = 1 << 8        # delta rays + restricted ionisation loss (opt-in)
 PHYS_ALL = (PHYS_FIELDS | PHYS_ION | PHYS_BREM | PHYS_SCATTER |
             PHYS_EVOLVE_E | PHYS_EVOLVE_B | PHYS_HEAT)
 
@@ -70,6 +71,7 @@ def base_config(**over) -> dict:
         brem_boost=1.0, k_cut=1e3 * EV,
         table_shape=TABLE_CSBH, table_nT=128, table_nr=256, table_emax=10e9 * EV,
         e_min=10e3 * EV,
+        delta_cut=1e3 * EV,           # delta-ray cut (App. B: 1 keV)
         tally_nE=16, tally_ntheta=32, tally_Elo=10e3 * EV, tally_Ehi=1e9 * EV,
         tally_Ethr=1.0 * MEV,
         series_len=256,
