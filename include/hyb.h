@@ -67,8 +67,22 @@ enum {
   /* bremsstrahlung cross-sections enhanced by the background ionisation,
    * eq. (F_sigma), per cell from the start-of-step temperatures; not part
    * of HYB_PHYS_ALL */
-  HYB_PHYS_FSIGMA = 1 << 7
+  HYB_PHYS_FSIGMA = 1 << 7,
+  /* delta rays (App. B): the ionisation loss splits at the energy
+   * cfg.delta_cut given to a background electron; below it the restricted
+   * continuous stopping power of App. B replaces eq. (stop_ion), above it
+   * Moller scatter by the optical-depth method (a depth of its own per
+   * electron, at most one delta ray per electron and step) adds the delta
+   * ray as a new macro-electron at the parent's start-of-step position,
+   * with the parent's weight, ids HYB_DELTA_ID_BIT + 0, 1, ... in the order
+   * (4x4x4-cell tile of the birth cell, x fastest; parent id); a delta ray
+   * below e_min stops at once (ledger term STOPPED, the cell's heat).  Only
+   * with HYB_PHYS_ION; not part of HYB_PHYS_ALL. */
+  HYB_PHYS_DELTA = 1 << 8
 };
+
+/* ids of delta rays have this bit set; injected electrons' ids stay below it */
+#define HYB_DELTA_ID_BIT 0x80000000u
 
 /* energy ledger terms (hyb_tally_out.ledger), J */
 enum {
@@ -91,7 +105,11 @@ enum {
 /* event counters (hyb_tally_out.counters) */
 enum {
   HYB_C_INJECTED = 0, HYB_C_EMITTED = 1, HYB_C_REFLUX = 2, HYB_C_ESCAPED = 3,
-  HYB_C_STOPPED = 4, HYB_COUNTER_N = 5
+  HYB_C_STOPPED = 4,
+  HYB_C_DELTA = 5,        /* delta rays emitted (those below e_min included) */
+  HYB_C_DELTA_LOST = 6,   /* delta rays that found no free particle slot: their
+                             energy is booked as STOPPED in the birth cell */
+  HYB_COUNTER_N = 7
 };
 
 /* Run configuration (copied by hyb_init).  The solid is one element filling
@@ -131,6 +149,7 @@ typedef struct hyb_config {
   double eta_fixed;         /* > 0: hold the solid's resistivity at this value */
   int32_t n_sub;            /* field sub-cycles per step; 0 = from the stability scan */
   int32_t sort_every;       /* cell-sort and compact particles every this many steps; 0 = never */
+  double delta_cut;         /* delta-ray cut [J] (App. B: 1 keV), > 0 with HYB_PHYS_DELTA */
 } hyb_config;
 
 /* An injection source (App. B, Sec. II.B): n_macro electrons spread evenly
@@ -211,6 +230,9 @@ typedef struct hyb_state {
   double* ion_heat;         /* [cells] J, get only: the last step's collisional deposit */
   int64_t step;             /* steps completed */
   int64_t next_id;          /* next particle id (set_state: ids of later sources) */
+  double* tau_d;            /* [n] remaining optical depth to the next delta ray;
+                               required by set_state with HYB_PHYS_DELTA, else may be NULL */
+  int64_t delta_next;       /* delta rays numbered so far (next id HYB_DELTA_ID_BIT + this) */
 } hyb_state;
 
 /* Derived run quantities (for tests and reports). */
@@ -264,10 +286,11 @@ hyb_status hyb_tally(hyb_run* run, hyb_tally_out* out);
  * Synchronises the stream. */
 hyb_status hyb_get_state(hyb_run* run, hyb_state* st);
 
-/* Replace particles, fields, temperatures, resistivity, step and next id
- * (NULL field/cell pointers keep the current arrays).  Clears the step's
- * current and heat buffers.  HYB_EINVAL when a weight is not positive or
- * exceeds the accumulator limit of hyb_inject.  Synchronises the stream. */
+/* Replace particles, fields, temperatures, resistivity, step, next id and
+ * delta-ray count (NULL field/cell pointers keep the current arrays).
+ * Clears the step's current and heat buffers.  HYB_EINVAL when a weight is
+ * not positive or exceeds the accumulator limit of hyb_inject, or when tau_d
+ * is NULL with HYB_PHYS_DELTA.  Synchronises the stream. */
 hyb_status hyb_set_state(hyb_run* run, const hyb_state* st);
 
 hyb_status hyb_run_info_get(const hyb_run* run, hyb_run_info* info);

@@ -287,7 +287,8 @@ class OracleRun:
             g2 = PT.gamma_of(p)
             beta = np.sqrt(np.sum(p * p, axis=-1)) / (g2 * K.ME * K.C)
             taud = taud - self.n_i * M.moller_sigma(eps2, self.Z, self.e_cut) * beta * K.C * dt
-            ie = np.nonzero(taud < 0.0)[0]
+            # no delta ray once eps <= 2 cut (the depth then stays put)
+            ie = np.nonzero((taud < 0.0) & (eps2 > 2.0 * self.e_cut))[0]
             if len(ie):
                 x = M.sample_fraction(eps2[ie], self.e_cut, M.sampler_uniforms(ids[ie], c["seed"], n))
                 e_d = x * eps2[ie]

@@ -37,7 +37,8 @@ size_t hist_stride(const hyb_config& c) {
 // Sizes of everything a run keeps in device memory.
 struct Layout {
   size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta, off_heat, off_fsig;
-  size_t off_part[2][10];
+  size_t off_part[2][11];
+  size_t off_sp_cell, off_sp_pid, off_sp_f[7], off_sp_cnt, off_sp_start, off_sp_blk, off_sp_grp, off_sp_gpid;
   size_t off_tabX, off_tabSIG, off_tabSUB;
   size_t off_acc_led, off_acc_hist, off_events, off_tot_led, off_tot_led_c, off_tot_hist, off_tot_hist_c;
   size_t off_series, off_ctr, off_src, off_env, off_tile_cnt, off_tile_start, off_scan_blk,
@@ -51,6 +52,7 @@ Layout make_layout(const hyb_config& c) {
   const size_t nodes = (size_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
   const size_t cells = (size_t)c.nx * c.ny * c.nz;
   const size_t cap = (size_t)c.max_particles;
+  const bool delta = (c.physics & HYB_PHYS_DELTA) != 0;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
   for (int d = 0; d < 3; ++d) L.off_E[d] = take(nodes * ts);
@@ -65,6 +67,7 @@ Layout make_layout(const hyb_config& c) {
     L.off_part[b][0] = take(cap * 4);                       // cell
     for (int f = 1; f < 9; ++f) L.off_part[b][f] = take(cap * ts);
     L.off_part[b][9] = take(cap * 4);                       // id
+    L.off_part[b][10] = take(delta ? cap * ts : 0);         // delta-ray depth
   }
   const size_t tabn = (size_t)c.table_nT * c.table_nr;
   L.off_tabX = take(tabn * ts);
@@ -91,6 +94,16 @@ Layout make_layout(const hyb_config& c) {
   L.off_chunk_home = take(nchunks * 4);
   L.off_chunk_base = take(nchunks * kNbN * 4);
   L.off_far = take(cap * 4);
+  // delta-ray records: one per particle slot at most
+  const size_t spc = delta ? cap : 0;
+  L.off_sp_cell = take(spc * 4);
+  L.off_sp_pid = take(spc * 4);
+  for (int f = 0; f < 7; ++f) L.off_sp_f[f] = take(spc * ts);
+  L.off_sp_cnt = take(delta ? ntiles * 4 : 0);
+  L.off_sp_start = take(delta ? ntiles * 4 : 0);
+  L.off_sp_blk = take(delta ? ((ntiles + kScanTile - 1) / kScanTile) * 4 : 0);
+  L.off_sp_grp = take(spc * 4);
+  L.off_sp_gpid = take(spc * 4);
   L.off_red = take(2 * kRedBlocks * 8);
   L.off_desc = take(sizeof(RunDesc));
   L.total = o;
@@ -185,7 +198,11 @@ static std::string validate(const hyb_config& c) {
   if (c.tally_nE < 1 || c.tally_ntheta < 1 || !(c.tally_Ehi > c.tally_Elo) || !(c.tally_Elo > 0)) return "bad tally bins";
   if (c.series_len < 0) return "series_len must be >= 0";
   if (c.max_particles < 1 || c.max_particles > 2000000000LL) return "max_particles out of range";
-  if ((c.physics & ~0xFFu) != 0) return "unknown physics bits";
+  if ((c.physics & ~0x1FFu) != 0) return "unknown physics bits";
+  if (c.physics & HYB_PHYS_DELTA) {
+    if (!(c.physics & HYB_PHYS_ION)) return "delta rays need HYB_PHYS_ION";
+    if (!(c.delta_cut > 0)) return "delta_cut must be positive";
+  }
   if (c.eta_fixed < 0) return "eta_fixed must be >= 0";
   if (c.n_sub < 0 || c.n_sub > 1000) return "n_sub out of range";
   if (c.sort_every < 0) return "sort_every must be >= 0";
@@ -236,6 +253,16 @@ static void fill_desc(hyb_run* r) {
   const double e4 = kE * kE * kE * kE;
   h.c_ion = c.Z * n_i * e4 * c.dt / (4.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
   h.ln_iex = log(I_ex / kMec2);
+  {  // delta rays: restricted loss prefactor (half of eq. stop_ion's), Moller depth
+    const double re = kE * kE / (4.0 * kPi * kEps0 * kMec2);
+    const double hwp = kHbar * sqrt(c.Z * n_i * kE * kE / (kEps0 * kMe));
+    h.d_cut = c.delta_cut / kMec2;
+    h.c_rst = 0.5 * h.c_ion;
+    h.d_lnI2 = 2.0 * log(I_ex / kMec2);
+    h.d_dens0 = 2.0 * log(hwp / I_ex) - 1.0;
+    h.k_mol = n_i * 2.0 * kPi * re * re * c.Z * kC * c.dt;
+    h.spawn_cap = (c.physics & HYB_PHYS_DELTA) ? c.max_particles : 0;
+  }
   h.k_brem = c.brem_boost * n_i * cz * kC * c.dt;
   h.k_sub = n_i * cz * kC * c.dt;
   h.inv_boost = 1.0 / c.brem_boost;
@@ -292,7 +319,16 @@ static void point_desc(hyb_run* r) {
     p.ux = b + L.off_part[k][4]; p.uy = b + L.off_part[k][5]; p.uz = b + L.off_part[k][6];
     p.wn = b + L.off_part[k][7]; p.tau = b + L.off_part[k][8];
     p.id = (uint32_t*)(b + L.off_part[k][9]);
+    p.taud = b + L.off_part[k][10];
   }
+  h.sp_cell = (uint32_t*)(b + L.off_sp_cell);
+  h.sp_pid = (uint32_t*)(b + L.off_sp_pid);
+  for (int f = 0; f < 7; ++f) h.sp_f[f] = b + L.off_sp_f[f];
+  h.sp_cnt = (unsigned*)(b + L.off_sp_cnt);
+  h.sp_start = (unsigned*)(b + L.off_sp_start);
+  h.sp_blk = (unsigned*)(b + L.off_sp_blk);
+  h.sp_grp = (unsigned*)(b + L.off_sp_grp);
+  h.sp_gpid = (unsigned*)(b + L.off_sp_gpid);
   h.tab_X = b + L.off_tabX;
   h.tab_SIG = b + L.off_tabSIG;
   h.tab_SUB = b + L.off_tabSUB;
@@ -619,6 +655,7 @@ static hyb_status ensure_single_plans(hyb_run* r) {
   r->L.runs = r->d_desc;
   r->L.nruns = 1;
   r->L.sort = r->h.sort_every > 0;
+  r->L.delta = (r->h.physics & PHYS_DELTA) != 0;
   return upload_plans(r, r->stream, ps, r->L, &r->d_maps, &r->maps_bytes, r->dev);
 }
 
@@ -847,12 +884,13 @@ hyb_status hyb_get_state(hyb_run* r, hyb_state* st) {
   const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
   const PartPtrs& P = r->h.p[ctr.cur];
   std::vector<uint32_t> cell(n), id(n);
-  std::vector<char> raw[8];
-  void* src[8] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau};
+  std::vector<char> raw[9];
+  void* src[9] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau, P.taud};
+  const int nf = (c.physics & HYB_PHYS_DELTA) ? 9 : 8;
   if (n) {
     HIPCHK(r, hipMemcpy(cell.data(), P.cell, n * 4, hipMemcpyDeviceToHost));
     HIPCHK(r, hipMemcpy(id.data(), P.id, n * 4, hipMemcpyDeviceToHost));
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < nf; ++f) {
       raw[f].resize(n * ts);
       HIPCHK(r, hipMemcpy(raw[f].data(), src[f], n * ts, hipMemcpyDeviceToHost));
     }
@@ -864,6 +902,7 @@ hyb_status hyb_get_state(hyb_run* r, hyb_state* st) {
   for (size_t i = 0; i < n; ++i) alive += cell[i] != kDead;
   st->step = ctr.step;
   st->next_id = r->next_id;
+  st->delta_next = ctr.delta_next;
   if ((int64_t)alive > st->capacity) {
     st->n = (int64_t)alive;
     return fail(r, HYB_ENOSPACE, "state buffers too small");
@@ -885,6 +924,7 @@ hyb_status hyb_get_state(hyb_run* r, hyb_state* st) {
     }
     if (st->w) st->w[k] = val(6, i) * r->h.w_ref;
     if (st->tau) st->tau[k] = val(7, i);
+    if (st->tau_d) st->tau_d[k] = nf == 9 ? val(8, i) : 0.0;
     if (st->id) st->id[k] = id[i];
     ++k;
   }
@@ -925,6 +965,9 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   const size_t n = (size_t)st->n;
   if (n && (!st->pos || !st->mom || !st->w || !st->tau || !st->id))
     return fail(r, HYB_EINVAL, "particle arrays missing");
+  const bool delta = (c.physics & HYB_PHYS_DELTA) != 0;
+  if (n && delta && !st->tau_d) return fail(r, HYB_EINVAL, "delta rays need tau_d");
+  if (st->delta_next < 0 || st->delta_next >= (int64_t)kDeltaIdBit) return fail(r, HYB_EINVAL, "delta_next out of range");
   {
     // electrons the sources will still inject from st->step on must fit too
     int64_t later = 0;
@@ -952,8 +995,9 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   }
   const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
   std::vector<uint32_t> cell(n);
-  std::vector<double> f[8];
-  for (int k = 0; k < 8; ++k) f[k].resize(n);
+  const int nf = delta ? 9 : 8;
+  std::vector<double> f[9];
+  for (int k = 0; k < nf; ++k) f[k].resize(n);
   const int lo[3] = {r->h.ix_lo, 0, 0}, hi[3] = {r->h.ix_hi, c.ny, c.nz};
   for (size_t i = 0; i < n; ++i) {
     int ci[3];
@@ -972,11 +1016,12 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
     for (int d = 0; d < 3; ++d) f[3 + d][i] = st->mom[3 * i + d] / (kMe * kC);
     f[6][i] = st->w[i] / r->w_ref;
     f[7][i] = st->tau[i];
-    for (int k = 3; k < 8; ++k)
+    if (delta) f[8][i] = st->tau_d[i];
+    for (int k = 3; k < nf; ++k)
       if (!std::isfinite(f[k][i])) return fail(r, HYB_ENUMERIC, "non-finite particle value");
   }
   const PartPtrs& P = r->h.p[0];
-  void* dst[8] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau};
+  void* dst[9] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau, P.taud};
   auto put_typed = [&](void* d, const double* v, size_t cnt) -> hipError_t {
     if (ts == 8) return hipMemcpy(d, v, cnt * 8, hipMemcpyHostToDevice);
     std::vector<float> fl(v, v + cnt);
@@ -985,7 +1030,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   if (n) {
     HIPCHK(r, hipMemcpy(P.cell, cell.data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemcpy(P.id, st->id, n * 4, hipMemcpyHostToDevice));
-    for (int k = 0; k < 8; ++k) HIPCHK(r, put_typed(dst[k], f[k].data(), n));
+    for (int k = 0; k < nf; ++k) HIPCHK(r, put_typed(dst[k], f[k].data(), n));
   }
   const size_t nodes = (size_t)r->h.nodes, cells = (size_t)r->h.cells;
   for (int d = 0; d < 3; ++d) {
@@ -998,6 +1043,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   if (st->eta) HIPCHK(r, hipMemcpy(r->h.eta, st->eta, cells * 8, hipMemcpyHostToDevice));
   if (st->Te || st->Ti) HIPCHK(r, refresh_fsig(r));
   HIPCHK(r, hipMemset(r->h.ion_heat, 0, cells * 8));
+  if (delta) HIPCHK(r, hipMemset(r->h.sp_cnt, 0, (size_t)r->h.ntiles * 4));
   HIPCHK(r, hipMemset(r->h.acc_led, 0, 16 * 8));
   HIPCHK(r, hipMemset(r->h.acc_hist, 0, hist_stride(c) * kHistCopies * 8));
   Counters ctr{};
@@ -1005,6 +1051,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   ctr.step = st->step;
   ctr.cur = 0;
   ctr.active = 1;
+  ctr.delta_next = st->delta_next;
   HIPCHK(r, hipMemcpy(r->h.ctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice));
   r->host_step = st->step;
   if (st->next_id > r->next_id) r->next_id = st->next_id;
@@ -1068,8 +1115,10 @@ static hyb_status eng_rebuild(hyb_engine* e, int p) {
   if (nres == 0) return HYB_OK;
   e->L[p].runs = e->d_descs[p];
   e->L[p].nruns = e->max_runs;
-  for (int s = 0; s < e->max_runs; ++s)
+  for (int s = 0; s < e->max_runs; ++s) {
     if (e->slots[p][s] && e->slots[p][s]->h.sort_every > 0) e->L[p].sort = true;
+    if (e->slots[p][s] && (e->slots[p][s]->h.physics & PHYS_DELTA)) e->L[p].delta = true;
+  }
   hyb_run tmp;
   hyb_status st = upload_plans(&tmp, e->stream, ps, e->L[p], &e->d_maps[p], &e->maps_bytes[p], e->dev);
   if (st != HYB_OK) return eng_fail(e, st, tmp.err);

@@ -35,12 +35,17 @@ constexpr double kHeatScale = 1099511627776.0;      // 2^40
 
 enum { L_INJECTED = 0, L_FIELD_LOSS, L_FIELD_GAIN, L_ION, L_STOPPED, L_RAD_D, L_RAD_S,
        L_ESCAPED, L_REFLUX, L_PHOTON_THR, L_RESIDUAL, L_N };
-enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_N };
+enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_DELTA, C_DELTA_LOST, C_N };
 
 enum : uint32_t {
   PHYS_FIELDS = 1u << 0, PHYS_ION = 1u << 1, PHYS_BREM = 1u << 2, PHYS_SCATTER = 1u << 3,
-  PHYS_EVOLVE_E = 1u << 4, PHYS_EVOLVE_B = 1u << 5, PHYS_HEAT = 1u << 6, PHYS_FSIGMA = 1u << 7
+  PHYS_EVOLVE_E = 1u << 4, PHYS_EVOLVE_B = 1u << 5, PHYS_HEAT = 1u << 6, PHYS_FSIGMA = 1u << 7,
+  PHYS_DELTA = 1u << 8
 };
+
+// delta rays: ids DELTA_ID_BIT + n; candidates of the energy sampler
+constexpr uint32_t kDeltaIdBit = 0x80000000u;
+constexpr int kDeltaTries = 32;
 
 constexpr uint32_t kDead = 0xFFFFFFFFu;
 constexpr int kMaxSources = 8;
@@ -79,6 +84,8 @@ struct Counters {
   int active;             // engine: 1 while the run still has steps to do
   long long steps_left;   // engine: steps still to do
   long long n_sorted;     // alive particles after the last compaction
+  long long n_spawn;      // delta rays recorded this step (may exceed the record buffer)
+  long long delta_next;   // delta rays numbered so far
 };
 
 // Structure-of-arrays particle storage: packed cell, offsets in the cell,
@@ -89,6 +96,7 @@ struct PartPtrs {
   void* ux; void* uy; void* uz;
   void* wn; void* tau;
   uint32_t* id;
+  void* taud;             // optical depth to the next delta ray (runs with delta rays)
 };
 
 // Material of the background solid (App. A), with the combinations of
@@ -139,6 +147,24 @@ struct RunDesc {
   // solid (heat update, FP64)
   Solid solid;
   double eta_fixed;
+  // delta rays (m c^2 units)
+  double d_cut;       // cut
+  double c_rst;       // restricted loss per step: c_rst * L / beta
+  double d_lnI2;      // 2 ln(I / m c^2)
+  double d_dens0;     // density effect: max(0, d_dens0 + ln (beta gamma)^2)
+  double k_mol;       // Moller depth per step: k_mol * J(x_c, gamma) / (beta (gamma - 1))
+  // this step's delta rays, recorded by the particle kernel (record order is
+  // the order of the atomics) and appended after the step's sort in the
+  // order (tile of the birth cell, parent id)
+  long long spawn_cap;
+  uint32_t* sp_cell;        // [spawn_cap] packed birth cell
+  uint32_t* sp_pid;         // [spawn_cap] parent id
+  void* sp_f[7];            // [spawn_cap] ox oy oz ux uy uz wn (run precision)
+  unsigned* sp_cnt;         // [ntiles] records per birth tile (cleared by the grouping)
+  unsigned* sp_start;       // [ntiles] exclusive scan of sp_cnt
+  unsigned* sp_blk;         // [scan_nblk] block sums of the scan
+  unsigned* sp_grp;         // [spawn_cap] record index, grouped by tile
+  unsigned* sp_gpid;        // [spawn_cap] parent id, grouped by tile
   // arrays
   void* E[3]; void* B[3];
   long long* J[3];
@@ -227,7 +253,14 @@ __host__ __device__ __forceinline__ Uni4<T> draws(uint32_t id, uint32_t seed, lo
   return Uni4<T>{uni<T>(r.x), uni<T>(r.y), uni<T>(r.z), uni<T>(r.w)};
 }
 
-enum : uint32_t { SLOT_COLLIDE = 0, SLOT_PHOTON = 1, SLOT_REFLUX0 = 2, SLOT_INJ_A = 8, SLOT_INJ_B = 9 };
+// Slots of the per-step draws: collisions; photon angles and new depth;
+// reflux on x, y, z; injection; a delta ray's azimuth and new depth; the
+// depths of a newborn delta ray (keyed by its own id); the sampler's
+// candidates, two per slot from SLOT_DELTA_TRY on.
+enum : uint32_t {
+  SLOT_COLLIDE = 0, SLOT_PHOTON = 1, SLOT_REFLUX0 = 2, SLOT_INJ_A = 8, SLOT_INJ_B = 9,
+  SLOT_DELTA_K = 12, SLOT_BIRTH = 13, SLOT_DELTA_TRY = 16
+};
 
 // ---- math in the run's precision ------------------------------------------
 // Descriptor pointers are generic.  Kernels cast them to the global address
@@ -249,17 +282,19 @@ __device__ __forceinline__ unsigned atomic_add_u32(unsigned* p, unsigned v) {
 template <typename T>
 struct PartG {
   gptr<uint32_t> cell, id;
-  gptr<T> ox, oy, oz, ux, uy, uz, wn, tau;
+  gptr<T> ox, oy, oz, ux, uy, uz, wn, tau, taud;
 };
 template <typename T>
 __device__ __forceinline__ PartG<T> part_g(const PartPtrs& P) {
   return PartG<T>{G(P.cell), G(P.id), G((T*)P.ox), G((T*)P.oy), G((T*)P.oz),
-                  G((T*)P.ux), G((T*)P.uy), G((T*)P.uz), G((T*)P.wn), G((T*)P.tau)};
+                  G((T*)P.ux), G((T*)P.uy), G((T*)P.uz), G((T*)P.wn), G((T*)P.tau), G((T*)P.taud)};
 }
 
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
 __device__ __forceinline__ double m_log(double x) { return log(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }

@@ -23,6 +23,7 @@ struct LaunchSet {
   Plan zero, inject, particle, grid, cells, fin, adv;
   Plan scan, scan1;   // tile-count scan: one block per kScanTile tiles; one block per run
   bool sort = false;                                  // some run sorts its particles
+  bool delta = false;                                 // some run has delta rays
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
 };
 

@@ -42,9 +42,10 @@ __device__ __forceinline__ long long inject_count(const RunDesc& R, long long st
 }
 
 // Block-wide sum of per-thread integer accumulators, then one atomic per
-// non-zero term: ledger terms to `led`, event counts to `evt`.
-// `extra`, if given, holds block-wide LDS sums of the same terms.
-template <int NL, int NC>
+// non-zero term: ledger terms to `led`, event counts to `evt`.  The
+// registers hold the NL ledger terms and the first NC event counts; `extra`,
+// if given, holds block-wide LDS sums of all NT terms in the same order.
+template <int NL, int NC, int NT = NL + NC>
 __device__ __forceinline__ void block_flush(const long long (&v)[NL + NC], long long* __restrict__ led,
                                             long long* __restrict__ evt, const long long* extra = nullptr) {
   __shared__ long long sm[kWaves][NL + NC];
@@ -57,10 +58,11 @@ __device__ __forceinline__ void block_flush(const long long (&v)[NL + NC], long 
     if (lane == 0) sm[wave][i] = x;
   }
   __syncthreads();
-  if (threadIdx.x < NL + NC) {
+  if (threadIdx.x < NT) {
     long long s = 0;
+    if (threadIdx.x < NL + NC)
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += sm[w][threadIdx.x];
+      for (int w = 0; w < kWaves; ++w) s += sm[w][threadIdx.x];
     if (extra) s += extra[threadIdx.x];
     if (s != 0) {
       long long* dst = threadIdx.x < NL ? &led[threadIdx.x] : &evt[threadIdx.x - NL];
@@ -153,6 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     P.wn[slot] = wn;
     P.tau[slot] = tau;
     P.id[slot] = id;
+    if (R.physics & PHYS_DELTA) P.taud[slot] = -m_log((T)1 - b.c);
     const T u2 = ux * ux + uy * uy + uz * uz;
     acc[L_INJECTED] += to_fixed(kinetic(u2, m_sqrt((T)1 + u2)) * wn * (T)kLedScale);
     acc[L_N + C_INJECTED] += 1;
@@ -556,6 +559,38 @@ __device__ __forceinline__ ChunkRange chunk_range(const BlockMap& bm, long long 
 }
 
 // ---------------------------------------------------------------------------
+// delta rays (App. B): restricted loss below the cut, Moller scatter above
+// ---------------------------------------------------------------------------
+// Restricted continuous loss over the step [m c^2] of an electron of
+// kinetic energy t, Lorentz factor g, u^2 = (beta gamma)^2: c_rst L / beta,
+// L = ln(2 (g + 1)) - 2 ln(I) + F^-(t, D) - delta, D = min(cut, t / 2),
+// F^- = -1 - beta^2 + ln((t - D) D) + t / (t - D) + (D^2/2 + (2t + 1) ln(1 - D/t)) / g^2,
+// delta = max(0, d_dens0 + ln u^2); L clamped at zero.
+template <typename T>
+__device__ __forceinline__ T restricted_loss(const RunDesc& R, T t, T g, T u2) {
+  const T ig = (T)1 / g;
+  const T b2 = u2 * ig * ig;
+  const T hc = (T)0.5 * t;
+  const T D = (T)R.d_cut < hc ? (T)R.d_cut : hc;
+  const T Fm = (T)-1 - b2 + m_log((t - D) * D) + t / (t - D) +
+               ((T)0.5 * D * D + ((T)2 * t + (T)1) * m_log1p(-D / t)) * ig * ig;
+  T dens = (T)R.d_dens0 + m_log(u2);
+  dens = dens > (T)0 ? dens : (T)0;
+  T L = m_log((T)2 * (g + (T)1)) - (T)R.d_lnI2 + Fm - dens;
+  L = L > (T)0 ? L : (T)0;
+  return (T)R.c_rst * L / m_sqrt(b2);
+}
+
+// x^2 times the bracket of the Moller cross-section d sigma / dx, with
+// a = (2g - 1)/g^2, b = ((g - 1)/g)^2; convex on (0, 1/2]
+template <typename T>
+__device__ __forceinline__ T moller_g(T x, T a, T b) {
+  const T y = (T)1 - x;
+  const T xx = x * x;
+  return b * xx + (T)1 - a * x + xx / (y * y) - a * xx / y;
+}
+
+// ---------------------------------------------------------------------------
 // the particle step: gather, Boris, deposit, move, ionisation,
 // bremsstrahlung, Davies scatter, boundaries, low-energy removal
 // ---------------------------------------------------------------------------
@@ -564,7 +599,8 @@ __device__ __forceinline__ ChunkRange chunk_range(const BlockMap& bm, long long 
 // occupancy pays for a few spills: 2 in FP64 (256 registers), 4 in FP32.
 template <typename T> struct PartOcc { static constexpr int waves = 2; };
 template <> struct PartOcc<float> { static constexpr int waves = 4; };
-template <typename T>
+// D: the variant with delta rays (own optical depth, spawning).
+template <typename T, bool D>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<T>::waves))) void k_particle(const RunDesc* __restrict__ runs,
                                                      const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
@@ -578,9 +614,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   const PartG<T> P = part_g<T>(R.p[ctr->cur]);
   const bool count = sort_step(R.sort_every, step);
   __shared__ ChunkLds<T> S;
-  long long acc[L_N + C_N];
+  long long acc[L_N];   // ledger terms; event counts and rare terms go to S.led
 #pragma unroll
-  for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
+  for (int i = 0; i < L_N; ++i) acc[i] = 0;
 
   const int nx = R.nx, ny = R.ny, nz = R.nz;
   const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
@@ -618,7 +654,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     }
     int ci = 0, cj = 0, ck = 0, my_tile = -1;
     // the electron's state is in flight while the chunk's homes are reduced
-    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0;
+    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0, taud = 0;
     uint32_t id = 0;
     if (cell != kDead) {
       ci = cell_i(cell); cj = cell_j(cell); ck = cell_k(cell);
@@ -626,6 +662,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       ox = P.ox[i]; oy = P.oy[i]; oz = P.oz[i];
       ux = P.ux[i]; uy = P.uy[i]; uz = P.uz[i];
       wn = P.wn[i]; tau = P.tau[i]; id = P.id[i];
+      if constexpr (D) {   // a batch may mix runs with and without delta rays
+        if (phys & PHYS_DELTA) taud = P.taud[i];
+      }
     }
     {
       int lo = cell != kDead ? my_tile : kNoTile, hi = my_tile;
@@ -754,14 +793,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         ox -= fx; oy -= fy; oz -= fz;
       }
 
-      // --- ionisation, eq. (stop_ion) ---
+      // --- ionisation, eq. (stop_ion); with delta rays the restricted loss ---
       T eps2 = eps1;
       long long heat = 0;
       if ((phys & PHYS_ION) && u2 > (T)0) {
-        const T beta = m_sqrt(u2) * ig;
-        T L = m_log(eps1) - (T)R.ln_iex + (T)0.5 * m_log(g + (T)1) + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
-        L = L > (T)0 ? L : (T)0;
-        T dE = (T)R.c_ion * L / beta;
+        T dE;
+        if (D && (phys & PHYS_DELTA)) {
+          dE = restricted_loss(R, eps1, g, u2);
+        } else {
+          const T beta = m_sqrt(u2) * ig;
+          T L = m_log(eps1) - (T)R.ln_iex + (T)0.5 * m_log(g + (T)1) + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
+          L = L > (T)0 ? L : (T)0;
+          dE = (T)R.c_ion * L / beta;
+        }
         dE = dE < eps1 ? dE : eps1;
         const T sc = umag_of(eps1 - dE) / m_sqrt(u2);
         ux *= sc; uy *= sc; uz *= sc;
@@ -771,6 +815,85 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         const T ion = (eps1 - eps2) * wn;
         acc[L_ION] += to_fixed(ion * ledS);
         heat += to_fixed(ion * (T)kHeatScale);
+      }
+
+      // --- delta rays: Moller scatter above the cut, own optical depth, one
+      // per step at most; born at x^n with the parent's weight ---
+      if constexpr (D) {
+        if ((phys & PHYS_DELTA) && u2 > (T)0) {
+          const T dcut = (T)R.d_cut;
+          const bool open = eps2 > (T)2 * dcut;
+          const T gi2 = (T)1 / (g * g);
+          const T a = ((T)2 * g - (T)1) * gi2, b = eps2 * eps2 * gi2;
+          const T xc = dcut / eps2;
+          if (open) {
+            const T J = b * ((T)0.5 - xc) + (T)1 / xc - (T)1 / ((T)1 - xc) - a * m_log(((T)1 - xc) / xc);
+            taud -= (T)R.k_mol * J * g / (m_sqrt(u2) * eps2);
+          }
+          if (open && taud < (T)0) {
+            // energy fraction by rejection from 1/x^2 on [x_c, 1/2]
+            const T gmax = fmax(moller_g(xc, a, b), moller_g((T)0.5, a, b));
+            const T span = (T)1 - (T)2 * xc;
+            T x = xc;
+#pragma unroll 1
+            for (int k = 0; k < kDeltaTries / 2; ++k) {
+              const Uni4<T> u = draws<T>(id, R.seed, step, SLOT_DELTA_TRY + k);
+              const T c0 = xc / ((T)1 - u.a * span);
+              if (u.b * gmax <= moller_g(c0, a, b)) { x = c0; break; }
+              x = xc / ((T)1 - u.c * span);   // kept if accepted or if it is the last candidate
+              if (u.d * gmax <= moller_g(x, a, b)) break;
+            }
+            const T ed = x * eps2;
+            const Uni4<T> uk = draws<T>(id, R.seed, step, SLOT_DELTA_K);
+            // two-body kinematics on a free electron at rest
+            T cth = m_sqrt(ed * (eps2 + (T)2) / (eps2 * (ed + (T)2)));
+            cth = cth < (T)1 ? cth : (T)1;
+            const T um = m_sqrt(u2);
+            T dx_ = ux, dy_ = uy, dz_ = uz;
+            rotate(dx_, dy_, dz_, m_acos(cth), uk.a);
+            const T sd = umag_of(ed) / um;
+            dx_ *= sd; dy_ *= sd; dz_ *= sd;
+            T qx = ux - dx_, qy = uy - dy_, qz = uz - dz_;
+            const T sq = umag_of(eps2 - ed) / m_sqrt(qx * qx + qy * qy + qz * qz);
+            ux = qx * sq; uy = qy * sq; uz = qz * sq;
+            taud = -m_log((T)1 - uk.b);
+            u2 = ux * ux + uy * uy + uz * uz;
+            g = m_sqrt((T)1 + u2);
+            const T eps_p = kinetic(u2, g);
+            lds_add(&S.led[L_N + C_DELTA], 1LL);
+            T resid = eps2 - eps_p - ed;
+            bool local = ed < (T)R.e_min;
+            if (!local) {
+              const unsigned long long a_ = __hip_atomic_fetch_add(
+                  (__attribute__((address_space(1))) unsigned long long*)&ctr->n_spawn, 1ull,
+                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if ((long long)a_ < R.spawn_cap) {
+                // the record: birth place x^n (still in this electron's slot)
+                G(R.sp_cell)[a_] = cell;
+                G(R.sp_pid)[a_] = id;
+                G((T*)R.sp_f[0])[a_] = P.ox[i];
+                G((T*)R.sp_f[1])[a_] = P.oy[i];
+                G((T*)R.sp_f[2])[a_] = P.oz[i];
+                G((T*)R.sp_f[3])[a_] = dx_;
+                G((T*)R.sp_f[4])[a_] = dy_;
+                G((T*)R.sp_f[5])[a_] = dz_;
+                G((T*)R.sp_f[6])[a_] = wn;
+                atomic_add_u32(&R.sp_cnt[my_tile], 1u);
+                const T d2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
+                resid += ed - kinetic(d2, m_sqrt((T)1 + d2));
+              } else {
+                local = true;
+                lds_add(&S.led[L_N + C_DELTA_LOST], 1LL);
+              }
+            }
+            if (local) {   // stops where it is born
+              lds_add(&S.led[L_STOPPED], to_fixed(ed * wn * ledS));
+              heat += to_fixed(ed * wn * (T)kHeatScale);
+            }
+            lds_add(&S.led[L_RESIDUAL], to_fixed(resid * wn * ledS));
+            eps2 = eps_p;
+          }
+        }
       }
 
       // --- bremsstrahlung: optical depth, one emission per step at most ---
@@ -876,6 +999,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         P.ox[i] = ox; P.oy[i] = oy; P.oz[i] = oz;
         P.ux[i] = ux; P.uy[i] = uy; P.uz[i] = uz;
         P.tau[i] = tau;
+        if constexpr (D) {
+          if (phys & PHYS_DELTA) P.taud[i] = taud;
+        }
         if (count) {   // destination tile for the sort that ends this step
           const int tx = ci >> 2, ty = cj >> 2, tz = ck >> 2;
           dest_bin = nb_bin(hm, tx, ty, tz);
@@ -923,44 +1049,58 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   }
   if (base_at >= 0) G(R.chunk_base)[base_at] = base_val;
   if (far_at >= 0) G(R.far_off)[far_at] = far_val;
-  block_flush<L_N, C_N>(acc, R.acc_led, R.events, S.led);
+  block_flush<L_N, 0, L_N + C_N>(acc, R.acc_led, R.events, S.led);
 }
 
 // ---------------------------------------------------------------------------
 // tile sort: scan of the destination counts, then scatter of the electrons
-// into the other particle buffer in tile order (dead electrons dropped)
+// into the other particle buffer in tile order (dead electrons dropped).
+// The same three scan kernels also number the step's delta rays by birth
+// tile (which = 1).
 // ---------------------------------------------------------------------------
+struct ScanSet { gptr<unsigned> cnt, start, blk; bool on; };
+
+__device__ __forceinline__ ScanSet scan_set(const RunDesc& R, int which) {
+  const auto ctr = G(R.ctr);
+  if (which == 0)
+    return ScanSet{G(R.tile_cnt), G(R.tile_start), G(R.scan_blk),
+                   ctr->active && sort_step(R.sort_every, ctr->step)};
+  return ScanSet{G(R.sp_cnt), G(R.sp_start), G(R.sp_blk), ctr->active && (R.physics & PHYS_DELTA) != 0};
+}
+
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const RunDesc* __restrict__ runs,
-                                                        const BlockMap* __restrict__ bmap) {
+                                                        const BlockMap* __restrict__ bmap, int which) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!G(R.ctr)->active || !sort_step(R.sort_every, G(R.ctr)->step)) return;
+  const ScanSet Q = scan_set(R, which);
+  if (!Q.on) return;
   __shared__ unsigned sm[kBlock];
   const int t0 = bm.lb * kScanTile;
   unsigned s = 0;
-  for (int t = t0 + threadIdx.x; t < t0 + kScanTile && t < R.ntiles; t += kBlock) s += G(R.tile_cnt)[t];
+  for (int t = t0 + threadIdx.x; t < t0 + kScanTile && t < R.ntiles; t += kBlock) s += Q.cnt[t];
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) G(R.scan_blk)[bm.lb] = sm[0];
+  if (threadIdx.x == 0) Q.blk[bm.lb] = sm[0];
 }
 
 // exclusive scan of the block sums (one workgroup per run)
 __global__ __launch_bounds__(kBlock) void k_scan_blocks(const RunDesc* __restrict__ runs,
-                                                        const BlockMap* __restrict__ bmap) {
+                                                        const BlockMap* __restrict__ bmap, int which) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!G(R.ctr)->active || !sort_step(R.sort_every, G(R.ctr)->step)) return;
+  const ScanSet Q = scan_set(R, which);
+  if (!Q.on) return;
   __shared__ unsigned sm[kBlock];
   __shared__ unsigned carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int base = 0; base < R.scan_nblk; base += kBlock) {
     const int t = base + threadIdx.x;
-    const unsigned v = t < R.scan_nblk ? G(R.scan_blk)[t] : 0u;
+    const unsigned v = t < R.scan_nblk ? Q.blk[t] : 0u;
     sm[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < kBlock; o <<= 1) {   // inclusive Hillis-Steele scan
@@ -969,20 +1109,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_blocks(const RunDesc* __restric
       sm[threadIdx.x] += a;
       __syncthreads();
     }
-    if (t < R.scan_nblk) G(R.scan_blk)[t] = carry + sm[threadIdx.x] - v;
+    if (t < R.scan_nblk) Q.blk[t] = carry + sm[threadIdx.x] - v;
     __syncthreads();
     if (threadIdx.x == kBlock - 1) carry += sm[kBlock - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0) G(R.ctr)->n_sorted = carry;
+  if (threadIdx.x == 0 && which == 0) G(R.ctr)->n_sorted = carry;
 }
 
 // tile starts and scatter cursors
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict__ runs,
-                                                       const BlockMap* __restrict__ bmap) {
+                                                       const BlockMap* __restrict__ bmap, int which) {
   const BlockMap bm = bmap[blockIdx.x];
   const RunDesc& R = runs[bm.run];
-  if (!G(R.ctr)->active || !sort_step(R.sort_every, G(R.ctr)->step)) return;
+  const ScanSet Q = scan_set(R, which);
+  if (!Q.on) return;
   __shared__ unsigned sm[kBlock];
   constexpr int per = kScanTile / kBlock;   // tiles per thread
   const int t0 = bm.lb * kScanTile + threadIdx.x * per;
@@ -990,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
   unsigned s = 0;
 #pragma unroll
   for (int q = 0; q < per; ++q) {
-    v[q] = t0 + q < R.ntiles ? G(R.tile_cnt)[t0 + q] : 0u;
+    v[q] = t0 + q < R.ntiles ? Q.cnt[t0 + q] : 0u;
     s += v[q];
   }
   sm[threadIdx.x] = s;
@@ -1001,12 +1142,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
     sm[threadIdx.x] += a;
     __syncthreads();
   }
-  unsigned run = G(R.scan_blk)[bm.lb] + sm[threadIdx.x] - s;
+  unsigned run = Q.blk[bm.lb] + sm[threadIdx.x] - s;
 #pragma unroll
   for (int q = 0; q < per; ++q) {
-    if (t0 + q < R.ntiles) {
-      G(R.tile_start)[t0 + q] = run;
-    }
+    if (t0 + q < R.ntiles) Q.start[t0 + q] = run;
     run += v[q];
   }
 }
@@ -1015,7 +1154,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
 // (dead electrons dropped).  The particle kernel fixed every electron's slot
 // when it counted the destinations; here each chunk ranks its electrons
 // inside their bins and copies them.
-template <typename T>
+template <typename T, bool D>
 __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ runs,
                                                     const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
@@ -1038,7 +1177,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
     const long long i = ch * kBlock + threadIdx.x;
     const uint32_t cell = i < n ? A.cell[i] : kDead;
     const Home hm = make_home(R, __builtin_amdgcn_readfirstlane(G(R.chunk_home)[ch]));
-    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0;
+    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0, taud = 0;
     uint32_t id = 0;
     int t = -1, b = -1;
     unsigned off = 0;
@@ -1046,6 +1185,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
       ox = A.ox[i]; oy = A.oy[i]; oz = A.oz[i];
       ux = A.ux[i]; uy = A.uy[i]; uz = A.uz[i];
       wn = A.wn[i]; tau = A.tau[i]; id = A.id[i];
+      if constexpr (D) {
+        if (R.physics & PHYS_DELTA) taud = A.taud[i];
+      }
       const int tx = cell_i(cell) >> 2, ty = cell_j(cell) >> 2, tz = cell_k(cell) >> 2;
       t = tx + R.ntx * (ty + R.nty * tz);
       b = nb_bin(hm, tx, ty, tz);
@@ -1058,8 +1200,91 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
       B.ox[slot] = ox; B.oy[slot] = oy; B.oz[slot] = oz;
       B.ux[slot] = ux; B.uy[slot] = uy; B.uz[slot] = uz;
       B.wn[slot] = wn; B.tau[slot] = tau; B.id[slot] = id;
+      if constexpr (D) {
+        if (R.physics & PHYS_DELTA) B.taud[slot] = taud;
+      }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// delta rays join the run: records grouped by birth tile, ranked by parent
+// id inside the tile, appended after the step's survivors
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_spawn_group(const RunDesc* __restrict__ runs,
+                                                        const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  const auto ctr = G(R.ctr);
+  if (!ctr->active || !(R.physics & PHYS_DELTA)) return;
+  const long long ns = ctr->n_spawn < R.spawn_cap ? ctr->n_spawn : R.spawn_cap;
+  for (long long a = (long long)bm.lb * kBlock + threadIdx.x; a < ns; a += (long long)bm.nb * kBlock) {
+    const uint32_t c = G(R.sp_cell)[a];
+    const int t = tile_of(R, cell_i(c), cell_j(c), cell_k(c));
+    // counting down leaves the tile counts cleared for the next step
+    const unsigned k = __hip_atomic_fetch_sub(G(R.sp_cnt) + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long pos = (long long)G(R.sp_start)[t] + k - 1;
+    if (pos >= 0 && pos < ns) {   // counts and records agree; the bound is a guard
+      G(R.sp_grp)[pos] = (unsigned)a;
+      G(R.sp_gpid)[pos] = G(R.sp_pid)[a];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spawn_append(const RunDesc* __restrict__ runs,
+                                                         const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  const auto ctr = G(R.ctr);
+  if (!ctr->active || !(R.physics & PHYS_DELTA)) return;
+  const long long ns = ctr->n_spawn < R.spawn_cap ? ctr->n_spawn : R.spawn_cap;
+  if (ns == 0) return;
+  const long long step = ctr->step;
+  // the buffer and count the next step starts from (as the end of the step sets them)
+  const bool sorted = sort_step(R.sort_every, step);
+  long long n0 = ctr->n_total + inject_count(R, step);
+  n0 = sorted ? ctr->n_sorted : (n0 < R.capacity ? n0 : R.capacity);
+  const PartG<T> P = part_g<T>(R.p[sorted ? ctr->cur ^ 1 : ctr->cur]);
+  const long long id0 = ctr->delta_next;
+  long long acc[L_N + C_N];
+#pragma unroll
+  for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
+  const gptr<const unsigned> gpid = G((const unsigned*)R.sp_gpid);
+  for (long long g = (long long)bm.lb * kBlock + threadIdx.x; g < ns; g += (long long)bm.nb * kBlock) {
+    const unsigned a = G(R.sp_grp)[g];
+    if (a >= ns) continue;   // every grouped slot holds a record; the bound is a guard
+    const uint32_t c = G(R.sp_cell)[a];
+    const int t = tile_of(R, cell_i(c), cell_j(c), cell_k(c));
+    const long long st = G(R.sp_start)[t];
+    const long long en = t + 1 < R.ntiles ? (long long)G(R.sp_start)[t + 1] : ns;
+    const unsigned me = gpid[g];
+    long long r = st;
+    for (long long j = st; j < en; ++j) r += gpid[j] < me ? 1 : 0;
+    const uint32_t id = kDeltaIdBit + (uint32_t)(id0 + r);
+    const T ux = G((const T*)R.sp_f[3])[a], uy = G((const T*)R.sp_f[4])[a], uz = G((const T*)R.sp_f[5])[a];
+    const T wn = G((const T*)R.sp_f[6])[a];
+    const long long slot = n0 + r;
+    if (slot < R.capacity) {
+      const Uni4<T> u = draws<T>(id, R.seed, step, SLOT_BIRTH);
+      P.cell[slot] = c;
+      P.ox[slot] = G((const T*)R.sp_f[0])[a];
+      P.oy[slot] = G((const T*)R.sp_f[1])[a];
+      P.oz[slot] = G((const T*)R.sp_f[2])[a];
+      P.ux[slot] = ux; P.uy[slot] = uy; P.uz[slot] = uz;
+      P.wn[slot] = wn;
+      P.tau[slot] = -m_log((T)1 - u.a);
+      P.taud[slot] = -m_log((T)1 - u.b);
+      P.id[slot] = id;
+    } else {   // no free slot: the delta ray stops in its birth cell
+      const T u2 = ux * ux + uy * uy + uz * uz;
+      const T e = kinetic(u2, m_sqrt((T)1 + u2)) * wn;
+      acc[L_STOPPED] += to_fixed(e * (T)kLedScale);
+      acc[L_N + C_DELTA_LOST] += 1;
+      atomic_add_i64(&R.ion_heat[cell_i(c) + R.nx * (cell_j(c) + R.ny * cell_k(c))], to_fixed(e * (T)kHeatScale));
+    }
+  }
+  block_flush<L_N, C_N>(acc, R.acc_led, R.events);
 }
 
 // ---------------------------------------------------------------------------
@@ -1267,6 +1492,13 @@ __global__ void k_advance(const RunDesc* __restrict__ runs, const BlockMap* __re
     const long long n = c->n_total + inject_count(R, c->step);
     c->n_total = n < R.capacity ? n : R.capacity;
   }
+  if (R.physics & PHYS_DELTA) {   // the step's delta rays were appended
+    const long long ns = c->n_spawn < R.spawn_cap ? c->n_spawn : R.spawn_cap;
+    const long long n = c->n_total + ns;
+    c->n_total = n < R.capacity ? n : R.capacity;
+    c->delta_next += ns;
+    c->n_spawn = 0;
+  }
   c->step += 1;
   if (c->steps_left > 0) {
     c->steps_left -= 1;
@@ -1314,13 +1546,22 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
   hipLaunchKernelGGL(k_zero_step, dim3(L.zero.nb), dim3(kBlock), 0, s, L.runs, L.zero.map);
   hipLaunchKernelGGL(k_inject<T>, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
   if (L.ev_start) (void)hipEventRecord(L.ev_start, s);
-  hipLaunchKernelGGL(k_particle<T>, dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+  if (L.delta) hipLaunchKernelGGL((k_particle<T, true>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+  else hipLaunchKernelGGL((k_particle<T, false>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
   if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
   if (L.sort) {
-    hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map, 0);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
+    if (L.delta) hipLaunchKernelGGL((k_scatter<T, true>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+    else hipLaunchKernelGGL((k_scatter<T, false>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+  }
+  if (L.delta) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 1);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map, 1);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 1);
+    hipLaunchKernelGGL(k_spawn_group, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
+    hipLaunchKernelGGL(k_spawn_append<T>, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
   }
   for (int k = 0; k < max_sub; ++k) {
     hipLaunchKernelGGL(k_ohm<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);

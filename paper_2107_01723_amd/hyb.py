@@ -20,7 +20,10 @@ HYB_OK, HYB_EINVAL, HYB_ENOMEM, HYB_ENOSPACE, HYB_EDEVICE, HYB_ESTATE, HYB_ENUME
 FP64, FP32_MIXED = 0, 1
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
                "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr", "residual")
-COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped")
+COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped", "n_delta",
+                "n_delta_lost")
+PHYS_DELTA = 1 << 8
+DELTA_ID_BIT = 0x80000000
 
 ABI_FUNCTIONS = (
     "hyb_init", "hyb_inject", "hyb_inject_envelope", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
@@ -64,6 +67,7 @@ class Config(C.Structure):
         ("eta_fixed", C.c_double),
         ("n_sub", C.c_int32),
         ("sort_every", C.c_int32),
+        ("delta_cut", C.c_double),
     ]
 
 
@@ -102,7 +106,7 @@ class TallyOut(C.Structure):
         ("series", C.POINTER(C.c_double)),
         ("flow", C.c_double * 4), ("ledger", C.c_double * 11),
         ("kinetic", C.c_double), ("conversion", C.c_double),
-        ("counters", C.c_int64 * 5), ("n_alive", C.c_int64), ("step", C.c_int64),
+        ("counters", C.c_int64 * 7), ("n_alive", C.c_int64), ("step", C.c_int64),
     ]
 
 
@@ -116,6 +120,7 @@ class State(C.Structure):
         ("Te", C.POINTER(C.c_double)), ("Ti", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double)),
         ("ion_heat", C.POINTER(C.c_double)),
         ("step", C.c_int64), ("next_id", C.c_int64),
+        ("tau_d", C.POINTER(C.c_double)), ("delta_next", C.c_int64),
     ]
 
 
@@ -186,10 +191,14 @@ def check_abi():
     return mine
 
 
+# config keys a dictionary may leave out, with their defaults
+CONFIG_DEFAULTS = {"delta_cut": 1e3 * 1.602176634e-19}
+
+
 def make_config(d: dict) -> Config:
     c = Config()
     for name, _ in Config._fields_:
-        setattr(c, name, d[name])
+        setattr(c, name, d[name] if name in d else CONFIG_DEFAULTS[name])
     return c
 
 
@@ -347,12 +356,12 @@ class Run:
         cells = c["nx"] * c["ny"] * c["nz"]
         cap = int(capacity if capacity is not None else c["max_particles"])
         a = dict(pos=np.zeros(3 * cap), mom=np.zeros(3 * cap), w=np.zeros(cap), tau=np.zeros(cap),
-                 id=np.zeros(cap, dtype=np.uint32), E=np.zeros(3 * nodes), B=np.zeros(3 * nodes),
+                 tau_d=np.zeros(cap), id=np.zeros(cap, dtype=np.uint32), E=np.zeros(3 * nodes), B=np.zeros(3 * nodes),
                  J=np.zeros(3 * nodes), Te=np.zeros(cells), Ti=np.zeros(cells), eta=np.zeros(cells),
                  ion_heat=np.zeros(cells))
         s = State()
         s.capacity = cap
-        for k in ("pos", "mom", "w", "tau", "E", "B", "J", "Te", "Ti", "eta", "ion_heat"):
+        for k in ("pos", "mom", "w", "tau", "tau_d", "E", "B", "J", "Te", "Ti", "eta", "ion_heat"):
             setattr(s, k, _dptr(a[k]))
         s.id = a["id"].ctypes.data_as(C.POINTER(C.c_uint32))
         self._check(self.L.hyb_get_state(self.h, C.byref(s)), "hyb_get_state")
@@ -367,14 +376,15 @@ class Run:
             return v.reshape(cshp).transpose(2, 1, 0).copy()
 
         return dict(pos=a["pos"][: 3 * n].reshape(n, 3), p=a["mom"][: 3 * n].reshape(n, 3),
-                    w=a["w"][:n], tau=a["tau"][:n], ids=a["id"][:n],
+                    w=a["w"][:n], tau=a["tau"][:n], tau_d=a["tau_d"][:n], ids=a["id"][:n],
                     E=fld(a["E"]), B=fld(a["B"]), j=fld(a["J"]), Te=cel(a["Te"]), Ti=cel(a["Ti"]),
                     eta=cel(a["eta"]), ion_heat=cel(a["ion_heat"]), step=int(s.step),
-                    next_id=int(s.next_id))
+                    next_id=int(s.next_id), delta_next=int(s.delta_next))
 
     def set_state(self, st: dict):
-        """st: pos (n,3) m, p (n,3) kg m/s, w, tau, ids; optional E, B (3 arrays
-        [i,j,k]), Te, Ti, eta ([i,j,k]); step, next_id."""
+        """st: pos (n,3) m, p (n,3) kg m/s, w, tau, ids; tau_d with delta rays;
+        optional E, B (3 arrays [i,j,k]), Te, Ti, eta ([i,j,k]); step, next_id,
+        delta_next."""
         n = len(st["ids"])
         keep = []
 
@@ -391,6 +401,7 @@ class Run:
         ids = arr(st["ids"], np.uint32)
         s.pos, s.mom, s.w, s.tau = _dptr(pos), _dptr(mom), _dptr(w), _dptr(tau)
         s.id = ids.ctypes.data_as(C.POINTER(C.c_uint32))
+        s.tau_d = _dptr(arr(st["tau_d"])) if st.get("tau_d") is not None else None
 
         def fld(t):
             return arr(np.concatenate([np.asarray(x).transpose(2, 1, 0).ravel() for x in t]))
@@ -406,6 +417,7 @@ class Run:
         s.ion_heat = None
         s.step = int(st.get("step", 0))
         s.next_id = int(st.get("next_id", 0))
+        s.delta_next = int(st.get("delta_next", 0))
         self._check(self.L.hyb_set_state(self.h, C.byref(s)), "hyb_set_state")
 
     def close(self):

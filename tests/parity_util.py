@@ -50,6 +50,9 @@ def particle_errors(got, ref, dx):
         tau=np.abs(gt - rt) / np.maximum(1.0, np.abs(rt)),
         w=np.abs(got["w"][gsel][gi] - ref["w"][rsel][ri]) / ref["w"][rsel][ri],
     )
+    if "tau_d" in got and "tau_d" in ref:
+        gd, rd = got["tau_d"][gsel][gi], ref["tau_d"][rsel][ri]
+        e["tau_d"] = np.abs(gd - rd) / np.maximum(1.0, np.abs(rd))
     return e, only
 
 

@@ -120,3 +120,35 @@ def test_serving_loop_small_scan(P):
     assert out["p99_s"] >= out["p50_s"] > 0
     for i, res in out["results"].items():
         assert res["step"] == reqs[i]["steps"]
+
+
+def test_delta_run_alone_equals_mixed(P):
+    """A run with delta rays batched with runs without them (same precision,
+    so one launch serves both kinds): every run bitwise as alone, the delta
+    rays and their optical depths included."""
+    reqs = _reqs()
+    d = W.base_config(nx=24, ny=16, nz=16, x_lo=2e-6, x_hi=22e-6, precision=W.FP64, seed=4,
+                      brem_boost=10.0, physics=W.PHYS_ALL | W.PHYS_DELTA, sort_every=2,
+                      max_particles=20000, series_len=64)
+    sd = [W.source(n_macro=1500, y0=8e-6, z0=8e-6, r_fwhm=4e-6, T_hot=2 * W.MEV)]
+    mix = [reqs[2], (d, sd, 40), reqs[0]]
+    alone = [_alone(P, *r) for r in mix]
+    assert alone[1][0]["counters"]["n_delta"] > 100
+    eng = P.Engine(max_runs=8)
+    runs = {k: eng.admit(*r) for k, r in enumerate(mix)}
+    finished = {}
+    for _ in range(200):
+        eng.step(3)
+        for r in eng.poll():
+            k = [k for k, v in runs.items() if v is r][0]
+            finished[k] = (r.tally(), r.get_state())
+            eng.retire(r)
+        if len(finished) == 3:
+            break
+    assert len(finished) == 3
+    for k in range(3):
+        _same(*alone[k], *finished[k])
+    o1, o2 = np.argsort(alone[1][1]["ids"]), np.argsort(finished[1][1]["ids"])
+    assert np.array_equal(alone[1][1]["tau_d"][o1], finished[1][1]["tau_d"][o2])
+    assert alone[1][0]["counters"] == finished[1][0]["counters"]
+    eng.close()

@@ -372,3 +372,81 @@ def test_envelope_injection(P, precision, tol):
         assert len(only) < 0.01 * len(err["ids"])
         assert err["w"].max() < 1e-6
     run.close()
+
+
+DELTA_PHYS = (W.PHYS_ALL & ~W.PHYS_FIELDS) | W.PHYS_DELTA
+
+
+@pytest.mark.parametrize("sort_every", [0, 3])
+def test_delta_rays_fp64(P, sort_every):
+    """Delta rays and the restricted ionisation loss (App. B) through 40 steps
+    of injection, collisions on and field feedback off (electrons
+    independent), with and without the tile sort: every electron, the delta
+    rays by their ids, both optical depths, the counts and the ledger."""
+    cfg, srcs, _ = small_config(6000, brem_boost=10.0, physics=DELTA_PHYS, sort_every=sort_every,
+                                max_particles=60000)
+    ora = OracleRun(cfg)
+    ora.add_source(srcs[0])
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    ora.run(40)
+    run.step(40)
+    t = run.tally()
+    st, ref = run.get_state(), ora.state()
+    nd = int(np.sum(ref["ids"] >= OR.DELTA_ID_BIT))
+    print(f"  delta rays emitted {ora.counters['n_delta']}, alive {nd}, next {ora.delta_next}", flush=True)
+    assert t["counters"]["n_delta"] == ora.counters["n_delta"] > 1000
+    assert t["counters"]["n_delta_lost"] == 0
+    assert nd > 100 and st["delta_next"] == ora.delta_next
+    err, only = particle_errors(st, ref, cfg["dx"])
+    assert not only, only[:10]
+    for k in ("p", "pos", "tau", "tau_d", "w"):
+        assert err[k].max() < 1e-10, (k, err[k].max())
+    for k in ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped"):
+        assert t["counters"][k] == ora.counters[k], k
+    for k in ("injected", "ionisation", "rad_discrete", "reflux", "stopped", "escaped", "photon_thr"):
+        assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-8, abs=1e-12 * ora.ledger["injected"]), k
+    led = t["ledger"]
+    out = (t["kinetic"] + led["field_loss"] - led["field_gain"] + led["ionisation"] + led["stopped"]
+           + led["rad_discrete"] + led["rad_subcut"] + led["escaped"] + led["reflux"] + led["residual"])
+    # closure to the fixed-point resolution of the accumulators (~1e-11 here)
+    assert abs(led["injected"] - out) < 1e-9 * led["injected"]
+    run.close()
+
+
+def test_delta_rays_fp32_one_step(P):
+    """FP32-mixed, one step from the oracle's state at step 40: the electrons
+    present before the step by id, and this step's delta rays matched to the
+    oracle's by birth place (their parents' start-of-step positions) and
+    momentum; discrete decisions that flip in FP32 are counted (<= 0.5 %)."""
+    cfg, srcs, _ = small_config(6000, precision=W.FP32_MIXED, brem_boost=10.0, physics=DELTA_PHYS,
+                                max_particles=60000)
+    ora = oracle_at(cfg, srcs, 40)
+    d0, nd0 = ora.delta_next, ora.counters["n_delta"]
+    run = gpu_from_oracle(P, cfg, srcs, ora)
+    ora.step()
+    run.step(1)
+    st, ref = run.get_state(), ora.state()
+    new_g = st["ids"] >= OR.DELTA_ID_BIT + d0
+    new_r = ref["ids"] >= OR.DELTA_ID_BIT + d0
+    old = lambda s, m: {k: (v[~m] if k in ("pos", "p", "w", "tau", "tau_d", "ids") else v) for k, v in s.items()}
+    err, only = particle_errors(old(st, new_g), old(ref, new_r), cfg["dx"])
+    bad = (err["p"] > 1e-5) | (err["pos"] > 1e-5) | (err["tau"] > 1e-5) | (err["tau_d"] > 1e-5)
+    nflip = int(np.sum(bad)) + len(only)
+    # this step's delta rays: nearest birth place
+    gp, rp = st["pos"][new_g], ref["pos"][new_r]
+    gm, rm = st["p"][new_g], ref["p"][new_r]
+    print(f"  delta rays this step: gpu {len(gp)}, oracle {len(rp)}; old-electron flips {nflip}", flush=True)
+    assert len(rp) > 20
+    matched = 0
+    for x, q in zip(gp, gm):
+        dx = np.max(np.abs(rp - x), axis=1) / cfg["dx"]
+        j = int(np.argmin(dx))
+        if dx[j] < 1e-5 and np.linalg.norm(rm[j] - q) <= 1e-5 * np.linalg.norm(rm[j]):
+            matched += 1
+    n_all = len(err["ids"]) + len(rp)
+    assert nflip + (len(rp) - matched) + abs(len(gp) - len(rp)) <= 0.005 * n_all
+    t = run.tally()
+    nd = ora.counters["n_delta"] - nd0
+    assert t["counters"]["n_delta"] == pytest.approx(nd, abs=max(2, 0.005 * nd))
+    run.close()
