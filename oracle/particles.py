@@ -184,11 +184,23 @@ def box_muller(u0, u1):
     return np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * math.pi * u1)
 
 
-def photon_polar(gamma, r):
-    """Photon polar angle about the electron direction (stand-in for the Tsai
-    sampler, which the paper cites without printing): inverse CDF of
-    dN/dOmega ~ (1 + gamma^2 theta^2)^-2, theta = sqrt(r/(1-r))/gamma, capped at pi."""
-    return np.minimum(np.sqrt(r / (1.0 - r)) / gamma, math.pi)
+TSAI_A = 0.625      # rate of the first Gamma(2) component of the Tsai-based mixture
+TSAI_D = 27.0       # relative weight of the second component (rate 3 TSAI_A)
+
+
+def photon_polar(gamma, r, r2):
+    """Photon polar angle about the electron direction (App. B: a direction
+    drawn from the Tsai differential cross-section).  The published
+    approximation of the Tsai angular distribution: theta = u / gamma with u
+    of density proportional to u exp(-a u) + d u exp(-3 a u), a = 0.625,
+    d = 27 -- a mixture of Gamma(2) laws of rates a (weight 9/(9+d)) and 3a
+    (weight d/(9+d)), each drawn as -ln(r1 r2)/rate.  The uniform r picks the
+    component and, rescaled onto (0, 1), serves as r1; theta is capped at pi."""
+    p1 = 9.0 / (9.0 + TSAI_D)
+    first = r < p1
+    r1 = np.where(first, r / p1, (r - p1) / (1.0 - p1))
+    rate = np.where(first, TSAI_A, 3.0 * TSAI_A)
+    return np.minimum(-np.log(r1 * r2) / rate / gamma, math.pi)
 
 
 # --------------------------------------------------------------------------

@@ -329,7 +329,7 @@ class OracleRun:
             u_p = P.uniforms(ids, c["seed"], n, P.SLOT_PHOTON)
             tau = np.where(emit, -np.log(1.0 - u_p[2]), tau)
             if np.any(emit):
-                th = PT.photon_polar(g2[emit], u_p[0][emit])
+                th = PT.photon_polar(g2[emit], u_p[0][emit], u_p[3][emit])
                 ph = 2.0 * math.pi * u_p[1][emit]
                 d = PT.rotate(p_pre[emit], th, ph)
                 d = d / np.sqrt(np.sum(d * d, axis=-1))[:, None]

@@ -496,8 +496,13 @@ __device__ __forceinline__ T photon_tally(const RunDesc& R, ChunkLds<T>& S, T wn
   const T kph = S.ph[0][t], um = S.ph[4][t], g = S.ph[5][t];
   T dxp = S.ph[1][t], dyp = S.ph[2][t], dzp = S.ph[3][t];
   const Uni4<T> pd = draws<T>(id, R.seed, step, SLOT_PHOTON);
-  // photon direction about the electron direction
-  T th = m_sqrt(pd.a / ((T)1 - pd.a)) / g;
+  // photon direction about the electron direction: theta = u / gamma, u from
+  // the Tsai-based mixture of Gamma(2) laws of rates a = 0.625 (weight 1/4)
+  // and 3a (weight 3/4), -ln(r1 r2) / rate; draw a picks the law and, rescaled
+  // onto (0, 1), serves as r1
+  const bool first = pd.a < (T)0.25;
+  const T r1 = first ? pd.a / (T)0.25 : (pd.a - (T)0.25) / (T)0.75;
+  T th = -m_log(r1 * pd.d) / ((first ? (T)0.625 : (T)1.875) * g);
   th = th < (T)kPi ? th : (T)kPi;
   rotate(dxp, dyp, dzp, th, pd.b);
   T cx = dxp / um;

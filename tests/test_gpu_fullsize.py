@@ -41,7 +41,7 @@ def _closure(t):
 
 def _subset(st, ids):
     sel = np.isin(st["ids"], ids)
-    return {k: (st[k][sel] if k in ("pos", "p", "w", "tau", "ids") else st[k]) for k in st}
+    return {k: (st[k][sel] if k in ("pos", "p", "w", "tau", "tau_d", "ids") else st[k]) for k in st}
 
 
 @pytest.mark.parametrize("precision,n_pre,tol", [(W.FP64, 30, 1e-10), (W.FP64, 60, 1e-10),

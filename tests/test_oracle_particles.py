@@ -168,17 +168,20 @@ def test_davies_scatter_statistics():
 
 
 def test_photon_polar_angle_distribution():
-    """theta = sqrt(r/(1-r))/gamma follows dN/dOmega ~ (1 + gamma^2 theta^2)^-2
-    in the small-angle limit: compare with the quadrature of that density."""
+    """gamma theta follows the Tsai-based mixture 1/4 Gamma(2, a) + 3/4
+    Gamma(2, 3a), a = 0.625: Kolmogorov-Smirnov against the closed-form CDF
+    1 - exp(-k u)(1 + k u) of each component, and the mean 2/a (1/4 + 1/4)."""
     gam = 40.0
+    n = 100000
     rng = np.random.default_rng(5)
-    th = PT.photon_polar(np.full(100000, gam), rng.random(100000))
-    dens = lambda t: t / (1 + gam ** 2 * t ** 2) ** 2
-    norm = integrate.quad(dens, 0, 50 / gam)[0]
-    cdf = lambda t: np.array([integrate.quad(dens, 0, x)[0] for x in np.atleast_1d(t)]) / norm
-    probe = np.array([0.3, 1.0, 3.0]) / gam
-    emp = [np.mean(th <= t) for t in probe]
-    assert np.allclose(emp, cdf(probe), atol=0.006)
+    th = PT.photon_polar(np.full(n, gam), rng.random(n), rng.random(n))
+    u = th * gam
+    a = 0.625
+    G = lambda x, k: 1.0 - np.exp(-k * x) * (1.0 + k * x)
+    assert stats.kstest(u, lambda x: 0.25 * G(x, a) + 0.75 * G(x, 3 * a)).pvalue > 1e-3
+    assert np.mean(u) == pytest.approx(1.6, rel=0.01)
+    # the cap at pi for slow electrons
+    assert PT.photon_polar(np.array([1.0]), np.array([0.9]), np.array([1e-6]))[0] == pytest.approx(math.pi)
 
 
 def test_optical_depth_emission_probability():
