@@ -6,7 +6,7 @@ paper reflux, 64x90 tally), synthetic inputs from `workloads`.  Warmup steps
 cover the 1 ps injection, so the timed steps carry the full particle load.
 The same workload is also timed in FP32-mixed precision.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--serve] [--opt-in]
 
 Prints one JSON line.  `value` is FP64 macro-electron steps per second
 (alive electrons x steps / wall time of the timed steps, inputs resident in
@@ -16,6 +16,11 @@ its mean duration, measured with HIP events on the run's stream; its
 WRITE_SIZE counters gave for the same kernel (per electron, from the summary
 under profiles/, times this run's mean alive count), or null when that
 summary was taken on other kernel sources.
+
+`--opt-in` also times the same FP64 workload with each opt-in process of
+the paper switched on (delta rays with the restricted loss; the eq. F_sigma
+enhancement) and reports them under `opt_in`; the headline numbers are those
+of the default physics.
 """
 from __future__ import annotations
 
@@ -93,7 +98,9 @@ def time_run(P, cfg, srcs, steps, warmup, label):
     res = dict(label=label, wall_s=wall, ms_per_step=1e3 * wall / steps,
                particle_steps_per_s=alive * steps / wall, alive_mean=alive,
                kernel_ms=kms / max(nlaunch, 1), kernel_launches=nlaunch,
-               conversion=t1["conversion"], n_alive_end=t1["n_alive"])
+               conversion=t1["conversion"], n_alive_end=t1["n_alive"],
+               n_delta=t1["counters"]["n_delta"] - t0["counters"]["n_delta"],
+               n_delta_lost=t1["counters"]["n_delta_lost"])
     pb = particle_bytes(cfg["precision"])
     achieved = pb * alive / (res["kernel_ms"] * 1e-3) / 1e9
     bpe = counted_bytes_per_electron(label)
@@ -141,6 +148,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", action="store_true", help="also run the 64-run serving scan")
     ap.add_argument("--particles", type=int, default=0, help="override the macro-electron count")
+    ap.add_argument("--opt-in", action="store_true",
+                    help="also time the workload with delta rays and with eq. F_sigma (FP64)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 512 MiB with torch (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -178,6 +187,18 @@ def main():
         r32 = time_run(P, c32, srcs, a.steps, a.warmup, "fp32_mixed")
         print(f"# fp32-mixed: {r32['ms_per_step']:.3f} ms/step, particle kernel {r32['kernel_ms']:.3f} ms",
               file=sys.stderr, flush=True)
+    opt_in = {}
+    if a.opt_in:
+        for name, bit, extra in (("delta_rays", W.PHYS_DELTA, 1.5), ("f_sigma", W.PHYS_FSIGMA, 1.0)):
+            c = dict(cfg, physics=cfg["physics"] | bit, max_particles=int(cfg["max_particles"] * extra))
+            r = time_run(P, c, srcs, a.steps, a.warmup, "fp64_" + name)
+            opt_in[name] = {"value": round(r["particle_steps_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                            "particle_kernel_ms": round(r["kernel_ms"], 4), "alive_mean": r["alive_mean"],
+                            "roofline": r["roofline"], "ledger_closure": r["ledger_closure"]}
+            if bit == W.PHYS_DELTA:
+                opt_in[name].update(delta_rays_timed=r["n_delta"], delta_rays_lost=r["n_delta_lost"])
+            print(f"# fp64 + {name}: {r['ms_per_step']:.3f} ms/step, particle kernel {r['kernel_ms']:.3f} ms",
+                  file=sys.stderr, flush=True)
     serving = None
     if a.serve:
         from paper_2107_01723_amd import serve
@@ -215,6 +236,8 @@ def main():
                               "particle_kernel_ms": round(r32["kernel_ms"], 4),
                               "roofline": r32["roofline"], "ledger_closure": r32["ledger_closure"]}
         line["mixed_over_fp64"] = round(r32["particle_steps_per_s"] / r64["particle_steps_per_s"], 3)
+    if opt_in:
+        line["opt_in"] = opt_in
     if serving:
         line["serving"] = serving
     if cpu:

@@ -260,6 +260,7 @@ static void fill_desc(hyb_run* r) {
     h.c_rst = 0.5 * h.c_ion;
     h.d_lnI2 = 2.0 * log(I_ex / kMec2);
     h.d_dens0 = 2.0 * log(hwp / I_ex) - 1.0;
+    h.d_u2min = exp(-h.d_dens0);
     h.k_mol = n_i * 2.0 * kPi * re * re * c.Z * kC * c.dt;
     h.spawn_cap = (c.physics & HYB_PHYS_DELTA) ? c.max_particles : 0;
   }

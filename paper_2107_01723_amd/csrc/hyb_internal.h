@@ -152,6 +152,7 @@ struct RunDesc {
   double c_rst;       // restricted loss per step: c_rst * L / beta
   double d_lnI2;      // 2 ln(I / m c^2)
   double d_dens0;     // density effect: max(0, d_dens0 + ln (beta gamma)^2)
+  double d_u2min;     // (beta gamma)^2 where the density effect starts: exp(-d_dens0)
   double k_mol;       // Moller depth per step: k_mol * J(x_c, gamma) / (beta (gamma - 1))
   // this step's delta rays, recorded by the particle kernel (record order is
   // the order of the atomics) and appended after the step's sort in the

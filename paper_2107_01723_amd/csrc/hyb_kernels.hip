@@ -577,11 +577,11 @@ __device__ __forceinline__ T restricted_loss(const RunDesc& R, T t, T g, T u2) {
   const T b2 = u2 * ig * ig;
   const T hc = (T)0.5 * t;
   const T D = (T)R.d_cut < hc ? (T)R.d_cut : hc;
-  const T Fm = (T)-1 - b2 + m_log((t - D) * D) + t / (t - D) +
-               ((T)0.5 * D * D + ((T)2 * t + (T)1) * m_log1p(-D / t)) * ig * ig;
-  T dens = (T)R.d_dens0 + m_log(u2);
-  dens = dens > (T)0 ? dens : (T)0;
-  T L = m_log((T)2 * (g + (T)1)) - (T)R.d_lnI2 + Fm - dens;
+  // ln(2 (g + 1)) + ln((t - D) D) as one logarithm
+  T L = m_log((T)2 * (g + (T)1) * (t - D) * D) - (T)R.d_lnI2 - (T)1 - b2 + t / (t - D) +
+        ((T)0.5 * D * D + ((T)2 * t + (T)1) * m_log1p(-D / t)) * ig * ig;
+  // the density effect is zero below (beta gamma)^2 = exp(-d_dens0)
+  if (u2 > (T)R.d_u2min) L -= (T)R.d_dens0 + m_log(u2);
   L = L > (T)0 ? L : (T)0;
   return (T)R.c_rst * L / m_sqrt(b2);
 }
@@ -869,9 +869,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
             T resid = eps2 - eps_p - ed;
             bool local = ed < (T)R.e_min;
             if (!local) {
-              const unsigned long long a_ = __hip_atomic_fetch_add(
-                  (__attribute__((address_space(1))) unsigned long long*)&ctr->n_spawn, 1ull,
-                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              // record slots: one atomic per wave on the run's counter (the
+              // lanes here are the wave's spawning electrons)
+              const int lane = threadIdx.x & 63;
+              const unsigned long long act = __ballot(1);
+              const int lead = __ffsll((long long)act) - 1;
+              unsigned long long base = 0;
+              if (lane == lead)
+                base = __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)&ctr->n_spawn,
+                                              (unsigned long long)__popcll(act), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+              base = ((unsigned long long)(unsigned)__shfl((int)(base >> 32), lead, 64) << 32) |
+                     (unsigned)__shfl((int)(unsigned)base, lead, 64);
+              const unsigned long long a_ = base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull));
               if ((long long)a_ < R.spawn_cap) {
                 // the record: birth place x^n (still in this electron's slot)
                 G(R.sp_cell)[a_] = cell;
@@ -883,7 +893,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
                 G((T*)R.sp_f[4])[a_] = dy_;
                 G((T*)R.sp_f[5])[a_] = dz_;
                 G((T*)R.sp_f[6])[a_] = wn;
-                atomic_add_u32(&R.sp_cnt[my_tile], 1u);
+                // birth-tile counts: one atomic per distinct tile of the wave's records
+                unsigned long long todo = __ballot(1);
+                while (todo) {
+                  const int l2 = __ffsll((long long)todo) - 1;
+                  const int t2 = __shfl(my_tile, l2, 64);
+                  const unsigned long long m = __ballot(my_tile == t2) & todo;
+                  if (lane == l2) atomic_add_u32(&R.sp_cnt[t2], (unsigned)__popcll(m));
+                  todo &= ~m;
+                }
                 const T d2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
                 resid += ed - kinetic(d2, m_sqrt((T)1 + d2));
               } else {
