@@ -81,6 +81,15 @@ enum {
   HYB_PHYS_DELTA = 1 << 8
 };
 
+/* Boundary kind of each axis (hyb_config.bc_x, bc_y, bc_z); the x faces are
+ * the slab's, the y and z faces the domain walls. */
+enum {
+  HYB_BC_REFLUX = 0,   /* escape above kappa_esc a0 m c^2, else reflux (Sec. II.A) */
+  HYB_BC_OPEN = 1,     /* every electron that leaves escapes (ledger term ESCAPED) */
+  HYB_BC_MIRROR = 2    /* specular reflection without loss or turn; for a laterally
+                          uniform beam the same as periodic walls (App. C) */
+};
+
 /* ids of delta rays have this bit set; injected electrons' ids stay below it */
 #define HYB_DELTA_ID_BIT 0x80000000u
 
@@ -150,6 +159,7 @@ typedef struct hyb_config {
   int32_t n_sub;            /* field sub-cycles per step; 0 = from the stability scan */
   int32_t sort_every;       /* cell-sort and compact particles every this many steps; 0 = never */
   double delta_cut;         /* delta-ray cut [J] (App. B: 1 keV), > 0 with HYB_PHYS_DELTA */
+  int32_t bc_x, bc_y, bc_z; /* HYB_BC_* per axis (HYB_BC_REFLUX is the paper's) */
 } hyb_config;
 
 /* An injection source (App. B, Sec. II.B): n_macro electrons spread evenly
@@ -184,6 +194,17 @@ typedef struct hyb_envelope {
   double max_half_angle;    /* cone cap [rad] (the paper: 20 deg) */
   double eta_l2e;           /* laser-to-electron efficiency */
 } hyb_envelope;
+
+/* A mono-energetic beam at normal incidence (the depth-dose benchmark of
+ * App. C): at the step of t_start, per_cell macro-electrons in every face
+ * cell of the slab's front (all ny x nz cells), uniform over the cell's face,
+ * with kinetic energy `energy` along +x and `weight` real electrons each. */
+typedef struct hyb_beam {
+  int32_t per_cell;
+  double t_start;           /* [s] */
+  double energy;            /* [J] */
+  double weight;            /* real electrons per macro-electron, > 0 */
+} hyb_beam;
 
 typedef void* (*hyb_alloc_fn)(size_t bytes, void* user);
 typedef void (*hyb_free_fn)(void* ptr, void* user);
@@ -273,6 +294,13 @@ hyb_status hyb_inject(hyb_run* run, const hyb_source* src);
  * hyb_inject. */
 hyb_status hyb_inject_envelope(hyb_run* run, const hyb_envelope* env);
 
+/* Schedule a hyb_beam; it counts as a source (at most 8 per run) and ids
+ * continue the run's counter in (face cell k-major, electron) order.
+ * HYB_EINVAL for bad parameters or a weight beyond the accumulator limit of
+ * hyb_inject; HYB_ENOSPACE when the schedule exceeds max_particles;
+ * HYB_ESTATE when the run already started past t_start. */
+hyb_status hyb_inject_beam(hyb_run* run, const hyb_beam* beam);
+
 /* Enqueue nsteps full hybrid-PIC steps (inject, push and collide, deposit,
  * Ohm + Faraday sub-cycles, heating, tallies; optional cell sort). */
 hyb_status hyb_step(hyb_run* run, int32_t nsteps);
@@ -321,8 +349,8 @@ const char* hyb_last_error(const hyb_run* run);
 const char* hyb_status_string(hyb_status s);
 
 /* sizeof of the ABI structs, for bindings to check their layouts:
- * config, source, device, tally_out, state, run_info, envelope. */
-void hyb_abi_sizes(int64_t sizes[7]);
+ * config, source, device, tally_out, state, run_info, envelope, beam. */
+void hyb_abi_sizes(int64_t sizes[8]);
 
 /* ---------------- serving engine (continuous batching) -------------------
  * Independent runs share one device.  Each engine tick advances every

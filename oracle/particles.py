@@ -254,6 +254,26 @@ def inject(src, first_id, count, step, seed, ix_lo, dx, I0):
     return pos, p, w, tau, ids.astype(np.uint32)
 
 
+def inject_beam(beam, first_id, step, seed, ix_lo, ny, nz):
+    """A mono-energetic beam at normal incidence: per_cell electrons in each
+    face cell (j, k) of the slab's front, k-major, uniform over the cell's
+    face; kinetic energy `energy`, momentum along +x, weight `weight`,
+    optical depth -ln(1 - u).  Returns X (cell units), p, w, tau, ids."""
+    per = int(beam["per_cell"])
+    n = per * ny * nz
+    ids = (np.arange(n, dtype=np.uint64) + np.uint64(first_id)).astype(np.uint64)
+    a0_, a1, _, _ = P.uniforms(ids, seed, step, P.SLOT_INJECT_A)
+    _, b1, _, _ = P.uniforms(ids, seed, step, P.SLOT_INJECT_B)
+    cell = np.arange(n) // per
+    jj, kk = (cell % ny).astype(np.float64), (cell // ny).astype(np.float64)
+    pos = np.stack([np.full(n, float(ix_lo)), jj + a0_, kk + a1], axis=-1)
+    p = np.zeros((n, 3))
+    p[:, 0] = momentum_of_energy(np.full(n, float(beam["energy"])))
+    tau = -np.log(1.0 - b1)
+    w = np.full(n, float(beam["weight"]))
+    return pos, p, w, tau, ids.astype(np.uint32)
+
+
 # ---------------------------------------------------------------------------
 # the paper's injection envelope (Sec. II.B, eq. N_cell, App. B)
 # ---------------------------------------------------------------------------

@@ -18,7 +18,8 @@ the reading both implementations follow):
      optionally both enhanced by eq. F_sigma of the cell at x^n, from the
      temperatures at the start of the step
   7. Davies elastic scatter (App. B)
-  8. boundaries x, y, z: escape or reflux (Sec. II.A)
+  8. boundaries x, y, z: escape or reflux (Sec. II.A); per axis also open
+     (every electron leaving escapes) or a lossless mirror
   9. removal below e_min, remaining energy -> the cell's heat
  10. n_sub sub-cycles of Ohm + Faraday (App. A)
  11. Ohmic + ionisation heating, electron-ion exchange, resistivity (App. A)
@@ -51,6 +52,7 @@ PHYS_EVOLVE_B = 1 << 5
 PHYS_HEAT = 1 << 6
 PHYS_FSIGMA = 1 << 7
 PHYS_DELTA = 1 << 8
+BC_REFLUX, BC_OPEN, BC_MIRROR = 0, 1, 2
 DELTA_ID_BIT = 0x80000000    # delta rays take ids DELTA_ID_BIT + 0, 1, ...
 
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
@@ -150,8 +152,27 @@ class OracleRun:
         self.next_id += s["_per_step"] * s["_ns"]
         self.sources.append(s)
 
+    def add_beam(self, beam: dict):
+        """Schedule a mono-energetic beam at normal incidence (the depth-dose
+        benchmark of App. C): per_cell electrons in every face cell of the
+        slab's front at the step of t_start; ids in (cell k-major, electron)
+        order."""
+        s = dict(beam)
+        s["_kind"] = "beam"
+        s["_s0"] = int(math.floor(s["t_start"] / self.dt + 0.5))
+        s["_id0"] = self.next_id
+        s["_n"] = int(s["per_cell"]) * self.ny * self.nz
+        self.next_id += s["_n"]
+        self.sources.append(s)
+
     def _inject(self, n):
         for s in self.sources:
+            if s.get("_kind") == "beam":
+                if n == s["_s0"]:
+                    pos, p, w, tau, ids = PT.inject_beam(s, s["_id0"], n, self.cfg["seed"], self.ix_lo,
+                                                         self.ny, self.nz)
+                    self._append(pos, p, w, tau, ids, n)
+                continue
             if s.get("_kind") == "envelope":
                 i = n - s["_s0"]
                 if 0 <= i < s["_ns"] and s["_per_step"] > 0:
@@ -370,7 +391,16 @@ class OracleRun:
             out = below | above
             if not np.any(out):
                 continue
-            esc = out & (eps_cur > self.eps_esc)
+            mode = int(c.get("bc_" + "xyz"[d], BC_REFLUX))
+            if mode == BC_MIRROR:
+                # specular: mirror the position about the face, flip the normal momentum
+                x = pos[:, d]
+                x = np.where(below, 2.0 * lo - x, x)
+                x = np.where(above, 2.0 * hi - x, x)
+                pos[:, d] = np.where(out, np.clip(x, lo, np.nextafter(hi, -np.inf)), x)
+                p[out, d] = -p[out, d]
+                continue
+            esc = out & (eps_cur > self.eps_esc) if mode == BC_REFLUX else out
             L["escaped"] += float(np.sum(w[esc] * eps_cur[esc]))
             self.counters["n_escaped"] += int(np.sum(esc))
             alive &= ~esc

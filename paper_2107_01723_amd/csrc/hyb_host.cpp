@@ -206,6 +206,8 @@ static std::string validate(const hyb_config& c) {
   if (c.eta_fixed < 0) return "eta_fixed must be >= 0";
   if (c.n_sub < 0 || c.n_sub > 1000) return "n_sub out of range";
   if (c.sort_every < 0) return "sort_every must be >= 0";
+  for (int b : {c.bc_x, c.bc_y, c.bc_z})
+    if (b != HYB_BC_REFLUX && b != HYB_BC_OPEN && b != HYB_BC_MIRROR) return "unknown boundary kind";
   return "";
 }
 
@@ -274,6 +276,7 @@ static void fill_desc(hyb_run* r) {
   h.reflux_ke_mode = c.reflux_ke_frac > 0 ? 1 : 0;
   h.keep_frac = 1.0 - c.reflux_ke_frac;
   h.sigma_dth = c.sigma_dtheta;
+  h.bc[0] = c.bc_x; h.bc[1] = c.bc_y; h.bc[2] = c.bc_z;
   h.e_min = c.e_min / kMec2;
   h.tab_nT = c.table_nT;
   h.tab_nr = c.table_nr;
@@ -634,6 +637,36 @@ static hyb_status add_envelope(hyb_run* r, const hyb_envelope* e) {
   return HYB_OK;
 }
 
+static hyb_status add_beam(hyb_run* r, const hyb_beam* b) {
+  const hyb_config& c = r->cfg;
+  if (!b) return fail(r, HYB_EINVAL, "null beam");
+  if ((int)r->srcs.size() >= kMaxSources) return fail(r, HYB_EINVAL, "too many sources");
+  if (b->per_cell < 1 || !(b->energy > 0) || !(b->weight > 0) || !(b->t_start >= 0))
+    return fail(r, HYB_EINVAL, "bad beam parameters");
+  const long long s0 = (long long)floor(b->t_start / c.dt + 0.5);
+  if (s0 < r->host_step) return fail(r, HYB_ESTATE, "source starts before the current step");
+  const long long n = (long long)b->per_cell * c.ny * c.nz;
+  if (r->scheduled + n > c.max_particles) return fail(r, HYB_ENOSPACE, "sources exceed max_particles");
+  if (!r->w_locked && r->host_step == 0) r->w_ref = std::max(r->w_ref, b->weight);
+  const double wref = r->w_ref > 0 ? r->w_ref : b->weight;
+  const double wmax = c.precision == HYB_FP64 ? 64.0 : 2.0;
+  if (b->weight / wref > wmax) return fail(r, HYB_EINVAL, "source weight too large for the accumulator scale");
+  SourceDesc d{};
+  d.kind = 2;
+  d.s0 = s0;
+  d.ns = 1;
+  d.base = n;
+  d.rem = 0;
+  d.id0 = r->next_id;
+  d.per_cell = b->per_cell;
+  d.t_hot = b->energy / kMec2;
+  d.wn = b->weight;   // absolute here; divided by w_ref when uploaded
+  r->srcs.push_back(d);
+  r->next_id += n;
+  r->scheduled += n;
+  return HYB_OK;
+}
+
 static hyb_status upload_sources(hyb_run* r) {
   if (r->w_ref <= 0) r->w_ref = 1.0;
   set_units(r->h, r->w_ref);
@@ -717,7 +750,7 @@ const char* hyb_status_string(hyb_status s) {
 
 const char* hyb_last_error(const hyb_run* run) { return run ? run->err.c_str() : g_err.c_str(); }
 
-void hyb_abi_sizes(int64_t sizes[7]) {
+void hyb_abi_sizes(int64_t sizes[8]) {
   sizes[0] = sizeof(hyb_config);
   sizes[1] = sizeof(hyb_source);
   sizes[2] = sizeof(hyb_device);
@@ -725,6 +758,7 @@ void hyb_abi_sizes(int64_t sizes[7]) {
   sizes[4] = sizeof(hyb_state);
   sizes[5] = sizeof(hyb_run_info);
   sizes[6] = sizeof(hyb_envelope);
+  sizes[7] = sizeof(hyb_beam);
 }
 
 hyb_status hyb_footprint(const hyb_config* cfg, int64_t* bytes) {
@@ -762,6 +796,14 @@ hyb_status hyb_inject_envelope(hyb_run* r, const hyb_envelope* env) {
   if (!r) return HYB_EINVAL;
   if (r->eng) return fail(r, HYB_ESTATE, "engine runs take their sources at admission");
   hyb_status st = add_envelope(r, env);
+  if (st != HYB_OK) return st;
+  return upload_sources(r);
+}
+
+hyb_status hyb_inject_beam(hyb_run* r, const hyb_beam* beam) {
+  if (!r) return HYB_EINVAL;
+  if (r->eng) return fail(r, HYB_ESTATE, "engine runs take their sources at admission");
+  hyb_status st = add_beam(r, beam);
   if (st != HYB_OK) return st;
   return upload_sources(r);
 }

@@ -67,7 +67,8 @@ struct SourceDesc {
   double t_hot;           // [m c^2]
   double one_minus_cos;   // 1 - cos(half angle); envelope: of the cap
   double wn;              // weight / w_ref; envelope: where f = g = 1
-  // envelope injection (kind 1): per_cell electrons in each listed face cell
+  // envelope injection (kind 1): per_cell electrons in each listed face cell;
+  // beam (kind 2): per_cell electrons in every face cell, energy t_hot along +x
   int kind, per_cell;
   const int* cells;       // injecting face cells, j | k << 16, k-major
   double tp, tf;          // peak time and fwhm [steps]; step n is at n + 1/2
@@ -131,6 +132,7 @@ struct RunDesc {
   // boundaries
   double eps_esc, du_tnsa, keep_frac, sigma_dth, e_min;
   int reflux_ke_mode;
+  int bc[3];          // boundary kind per axis: 0 reflux, 1 open, 2 mirror
   // tables (precision of the run)
   int tab_nT, tab_nr;
   double tab_ln_kcut, tab_s_scale, tab_kcut;

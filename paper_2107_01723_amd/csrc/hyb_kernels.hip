@@ -125,6 +125,14 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
       const T th_moore = m_atan(m_sqrt((T)2 / eps));
       omc = (T)1 - m_cos(th_moore < (T)S->cap ? th_moore : (T)S->cap);
       wn = (T)S->wn * sq;
+    } else if (S->kind == 2) {
+      // mono-energetic beam along +x, every face cell, uniform over the cell
+      const long long cidx = (t - off) / S->per_cell;
+      cy = (int)(cidx % R.ny); oy = a.a;
+      cz = (int)(cidx / R.ny); oz = a.b;
+      eps = (T)S->t_hot;
+      omc = (T)0;
+      wn = (T)S->wn;
     } else {
       const T r = m_sqrt((T)-2 * (T)S->sig2 * m_log((T)1 - (T)0.5 * a.a));
       T sps, cps;
@@ -226,12 +234,12 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   const bool below = c < lo;
   const bool above = c >= hi;
   if (!(below || above)) return true;
-  if (eps > (T)R.eps_esc) {
+  const int mode = R.bc[axis];   // 0 reflux, 1 open, 2 mirror
+  if (mode == 1 || (mode == 0 && eps > (T)R.eps_esc)) {
     lds_add(&led[L_ESCAPED], to_fixed(eps * wn * (T)kLedScale));
     lds_add(&led[L_N + C_ESCAPED], 1LL);
     return false;
   }
-  lds_add(&led[L_N + C_REFLUX], 1LL);
   // mirror about the face, then clamp into [lo, hi)
   int c2 = (below ? 2 * lo : 2 * hi) - c - 1;
   T o2 = (T)1 - o;
@@ -243,6 +251,8 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   if (axis == 0) ux = -ux;
   else if (axis == 1) uy = -uy;
   else uz = -uz;
+  if (mode == 2) return true;   // specular wall: nothing else changes
+  lds_add(&led[L_N + C_REFLUX], 1LL);
   // energy or momentum loss
   const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
   T scale;

@@ -26,7 +26,7 @@ PHYS_DELTA = 1 << 8
 DELTA_ID_BIT = 0x80000000
 
 ABI_FUNCTIONS = (
-    "hyb_init", "hyb_inject", "hyb_inject_envelope", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
+    "hyb_init", "hyb_inject", "hyb_inject_envelope", "hyb_inject_beam", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
     "hyb_run_info_get", "hyb_table_get", "hyb_timing_enable", "hyb_timing_get", "hyb_use_graph",
     "hyb_footprint", "hyb_free", "hyb_last_error", "hyb_status_string", "hyb_abi_sizes",
     "hyb_engine_create", "hyb_engine_admit", "hyb_engine_step", "hyb_engine_poll",
@@ -68,6 +68,7 @@ class Config(C.Structure):
         ("n_sub", C.c_int32),
         ("sort_every", C.c_int32),
         ("delta_cut", C.c_double),
+        ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("bc_z", C.c_int32),
     ]
 
 
@@ -89,6 +90,11 @@ class Envelope(C.Structure):
         ("g_min", C.c_double), ("f_min", C.c_double),
         ("max_half_angle", C.c_double), ("eta_l2e", C.c_double),
     ]
+
+
+class Beam(C.Structure):
+    _fields_ = [("per_cell", C.c_int32), ("t_start", C.c_double), ("energy", C.c_double),
+                ("weight", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -151,6 +157,7 @@ def lib():
         "hyb_init": (C.c_int, [P(Config), P(Device), P(vp)]),
         "hyb_inject": (C.c_int, [vp, P(Source)]),
         "hyb_inject_envelope": (C.c_int, [vp, P(Envelope)]),
+        "hyb_inject_beam": (C.c_int, [vp, P(Beam)]),
         "hyb_step": (C.c_int, [vp, C.c_int32]),
         "hyb_tally": (C.c_int, [vp, P(TallyOut)]),
         "hyb_get_state": (C.c_int, [vp, P(State)]),
@@ -183,16 +190,16 @@ def lib():
 
 def check_abi():
     """Compare the ctypes struct sizes with the library's."""
-    a = (C.c_int64 * 7)()
+    a = (C.c_int64 * 8)()
     lib().hyb_abi_sizes(a)
-    mine = [C.sizeof(t) for t in (Config, Source, Device, TallyOut, State, RunInfo, Envelope)]
+    mine = [C.sizeof(t) for t in (Config, Source, Device, TallyOut, State, RunInfo, Envelope, Beam)]
     if list(a) != mine:
         raise RuntimeError(f"ABI struct sizes differ: library {list(a)} binding {mine}")
     return mine
 
 
 # config keys a dictionary may leave out, with their defaults
-CONFIG_DEFAULTS = {"delta_cut": 1e3 * 1.602176634e-19}
+CONFIG_DEFAULTS = {"delta_cut": 1e3 * 1.602176634e-19, "bc_x": 0, "bc_y": 0, "bc_z": 0}
 
 
 def make_config(d: dict) -> Config:
@@ -303,6 +310,13 @@ class Run:
     def inject_envelope(self, env: dict):
         """The paper's envelope injection (hyb_inject_envelope)."""
         self._check(self.L.hyb_inject_envelope(self.h, C.byref(make_envelope(env))), "hyb_inject_envelope")
+
+    def inject_beam(self, beam: dict):
+        """A mono-energetic normal-incidence beam (hyb_inject_beam)."""
+        b = Beam()
+        for name, _ in Beam._fields_:
+            setattr(b, name, beam[name])
+        self._check(self.L.hyb_inject_beam(self.h, C.byref(b)), "hyb_inject_beam")
 
     def step(self, n: int = 1):
         self._check(self.L.hyb_step(self.h, int(n)), "hyb_step")

@@ -450,3 +450,46 @@ def test_delta_rays_fp32_one_step(P):
     nd = ora.counters["n_delta"] - nd0
     assert t["counters"]["n_delta"] == pytest.approx(nd, abs=max(2, 0.005 * nd))
     run.close()
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_depth_dose_benchmark_setup(P, precision):
+    """The depth-dose benchmark setup of App. C through its 2 ps: 0.5 MeV
+    electrons at normal incidence on tantalum (hyb_inject_beam), open in x,
+    mirror walls in y and z, ionisation, Davies scatter and heating.  FP64:
+    every electron, every cell's temperature, the counts and the ledger;
+    FP32-mixed: the depth-dose profile (temperature rise summed over each x
+    layer), the counts and the ledger within FP32 tolerances."""
+    cfg, beam, steps = W.config_depth_dose()
+    cfg["precision"] = precision
+    ora = OracleRun(cfg)
+    ora.add_beam(beam)
+    run = P.Run(cfg)
+    run.inject_beam(beam)
+    ora.run(steps)
+    run.step(steps)
+    t, st, ref = run.tally(), run.get_state(), ora.state()
+    prof_g = (st["Te"] - cfg["T0"]).sum(axis=(1, 2))
+    prof_r = (ref["Te"] - cfg["T0"]).sum(axis=(1, 2))
+    l1 = np.sum(np.abs(prof_g - prof_r)) / np.sum(np.abs(prof_r))
+    print(f"  escaped {t['counters']['n_escaped']} / {ora.counters['n_escaped']}, stopped "
+          f"{t['counters']['n_stopped']} / {ora.counters['n_stopped']}, dose peak at "
+          f"{np.argmax(prof_r) * cfg['dx'] * 1e6:.1f} um, profile L1 {l1:.2e}", flush=True)
+    assert ora.counters["n_escaped"] > 500 and ora.counters["n_stopped"] > 500
+    if precision == W.FP64:
+        assert t["counters"]["n_escaped"] == ora.counters["n_escaped"]
+        assert t["counters"]["n_stopped"] == ora.counters["n_stopped"]
+        assert rel(st["Te"], ref["Te"]) < 1e-10
+        # the rises are small against T0 (1 eV): Te's own FP64 rounding is
+        # ~1e-9 of a rise in the deep layers
+        assert l1 < 1e-8
+        for k in ("injected", "ionisation", "stopped", "escaped"):
+            assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-9), k
+    else:
+        # a few discrete decisions (escape through the front, removal) flip in FP32
+        assert abs(t["counters"]["n_escaped"] - ora.counters["n_escaped"]) <= 0.01 * 3200
+        assert l1 < 2e-2
+        for k in ("injected", "ionisation", "escaped"):
+            assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=2e-2), k
+    assert t["counters"]["n_reflux"] == 0
+    run.close()

@@ -28,6 +28,7 @@ MATERIALS = {
     "Al": dict(Z=13.0, A=26.9815, rho=2700.0),
     "Cu": dict(Z=29.0, A=63.546, rho=8960.0),
     "Au": dict(Z=79.0, A=196.967, rho=19300.0),
+    "Ta": dict(Z=73.0, A=180.948, rho=16650.0),
 }
 
 # physics toggle bits (mirrors the HYB_PHYS_* bits of the C ABI)
@@ -45,6 +46,11 @@ PHYS_ALL = (PHYS_FIELDS | PHYS_ION | PHYS_BREM | PHYS_SCATTER |
 
 FP64 = 0
 FP32_MIXED = 1
+
+# boundary kinds per axis (x: the slab faces; y, z: the domain walls)
+BC_REFLUX = 0    # escape above kappa_esc a0 m c^2, else reflux (Sec. II.A)
+BC_OPEN = 1      # every electron that leaves escapes
+BC_MIRROR = 2    # specular reflection, no loss (a laterally uniform beam: periodic)
 
 TABLE_CSBH = 0   # complete-screening Bethe-Heitler spectral shape
 TABLE_FLAT = 1   # flat k dsigma/dk
@@ -81,6 +87,7 @@ def base_config(**over) -> dict:
         eta_fixed=0.0,
         n_sub=0,                      # 0 -> automatic from the stability scan
         sort_every=0,
+        bc_x=BC_REFLUX, bc_y=BC_REFLUX, bc_z=BC_REFLUX,
     )
     for k, v in over.items():
         if k not in cfg:
@@ -168,6 +175,35 @@ def config_huge() -> tuple[dict, list[dict], int]:
                  z0=128e-6, r_fwhm=2e-6, T_hot=10.8 * MEV,
                  half_angle=math.radians(30.0))
     return cfg, [src], 10000
+
+
+def beam(**over) -> dict:
+    """A mono-energetic beam at normal incidence: per_cell macro-electrons of
+    the given weight in every face cell of the slab's front, at the step of
+    t_start."""
+    b = dict(per_cell=50, t_start=0.0, energy=0.5 * MEV, weight=1.0)
+    for k, v in over.items():
+        if k not in b:
+            raise KeyError(f"unknown beam key {k}")
+        b[k] = v
+    return b
+
+
+def config_depth_dose() -> tuple[dict, dict, int]:
+    """The paper's depth-dose benchmark setup (App. C): 0.5 MeV electrons at
+    normal incidence on tantalum, 256 x 8 x 8 cells over 150 um in x, 50
+    unit-weight macro-electrons per front-face cell in the first step, 2 ps;
+    open in x, laterally mirror walls (for a laterally uniform beam the same
+    as the periodic walls the paper uses); ionisation, Davies scatter and
+    heating (currents of unit-weight electrons give negligible fields).
+    Cells are cubic here (150/256 um), so the lateral extent is 4.7 um.
+    Returns (config, beam, steps)."""
+    nx = 256
+    dx = 150e-6 / nx
+    cfg = base_config(nx=nx, ny=8, nz=8, dx=dx, dt=5e-15, material="Ta", x_lo=0.0, x_hi=nx * dx,
+                      physics=PHYS_ION | PHYS_SCATTER | PHYS_HEAT, bc_x=BC_OPEN, bc_y=BC_MIRROR,
+                      bc_z=BC_MIRROR, max_particles=4096, series_len=4)
+    return cfg, beam(), 400
 
 
 def scale_particles(cfg: dict, srcs: list[dict], n_macro: int) -> tuple[dict, list[dict]]:
