@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", action="store_true", help="also run the 64-run serving scan")
     ap.add_argument("--particles", type=int, default=0, help="override the macro-electron count")
+    ap.add_argument("--model", action="store_true",
+                    help="also time the energy-partition model over the intensity-Z plane")
     ap.add_argument("--opt-in", action="store_true",
                     help="also time the workload with delta rays and with eq. F_sigma (FP64)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -199,6 +201,21 @@ def main():
                 opt_in[name].update(delta_rays_timed=r["n_delta"], delta_rays_lost=r["n_delta_lost"])
             print(f"# fp64 + {name}: {r['ms_per_step']:.3f} ms/step, particle kernel {r['kernel_ms']:.3f} ms",
                   file=sys.stderr, flush=True)
+    model = None
+    if a.model:
+        import numpy as np
+        import torch
+        m = W.model_inputs()
+        I, Z = W.model_scan_grid()
+        P.model_scan(m, I[:64], Z[:64])          # warm-up (module load)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = P.model_scan(m, I, Z)
+        wall = time.perf_counter() - t0
+        model = {"points": len(I), "rk4_steps_per_electron": m["nsteps"], "wall_ms": round(1e3 * wall, 3),
+                 "electron_steps_per_s": round(3 * len(I) * m["nsteps"] / wall, 1),
+                 "eta_e_gamma_range": [float(np.min(f[1])), float(np.max(f[1]))]}
+        print(f"# model: {len(I)} points in {1e3 * wall:.2f} ms", file=sys.stderr, flush=True)
     serving = None
     if a.serve:
         from paper_2107_01723_amd import serve
@@ -238,6 +255,8 @@ def main():
         line["mixed_over_fp64"] = round(r32["particle_steps_per_s"] / r64["particle_steps_per_s"], 3)
     if opt_in:
         line["opt_in"] = opt_in
+    if model:
+        line["model"] = model
     if serving:
         line["serving"] = serving
     if cpu:

@@ -206,6 +206,27 @@ typedef struct hyb_beam {
   double weight;            /* real electrons per macro-electron, > 0 */
 } hyb_beam;
 
+/* Inputs of the paper's energy-partition model (Sec. III.B): the injection
+ * condensed into three macro-electrons (kinetic energy below e_th, from
+ * e_th to the escape energy kappa_esc a0 m c^2, above it) integrated
+ * through the continuous stopping powers of bremsstrahlung (eq. stop_brem),
+ * ionisation (eq. stop_ion, I = 11 eV Z), reflux (eq. stop_tnsa) and the
+ * resistive field (eq. stop_field). */
+typedef struct hyb_model {
+  double wavelength;        /* laser wavelength [m] (eq. a0) */
+  double eta_l2e;           /* laser-to-electron efficiency */
+  double r_fwhm, t_fwhm;    /* injection envelope [m], [s] */
+  double fg_mean;           /* <fg> over the injecting cells and steps (0.41) */
+  double sqrt_fg_mean;      /* <sqrt fg> (0.61): <eps_k> = a0 m c^2 <sqrt fg> */
+  double kappa_esc, kappa_tnsa;
+  double e_th;              /* X-ray threshold [J] (1 MeV) */
+  double Lx, Ly, Lz;        /* target size [m]; the escaping electron runs to Lx */
+  double theta_c;           /* half-angle of the current cone in eq. stop_field [rad] */
+  double eta_mean;          /* typical resistivity <eta> [Ohm m] */
+  double n_i;               /* ion density [m^-3] (the paper: 6e28) */
+  int32_t nsteps;           /* fourth-order Runge-Kutta steps per macro-electron */
+} hyb_model;
+
 typedef void* (*hyb_alloc_fn)(size_t bytes, void* user);
 typedef void (*hyb_free_fn)(void* ptr, void* user);
 
@@ -348,9 +369,27 @@ void hyb_free(hyb_run* run);
 const char* hyb_last_error(const hyb_run* run);
 const char* hyb_status_string(hyb_status s);
 
+/* The energy-partition model of Sec. III.B at n scan points (host arrays
+ * I0 [W/m^2] and Z, n each), one GPU thread per macro-electron.  out
+ * (host, caller-owned, 6 n doubles, point-major) receives the fractions of
+ * the injected hot-electron energy lost to: bremsstrahlung (all photons),
+ * photons above e_th (eta_e->gamma, part of the first), ionisation,
+ * reflux, the field, and escape.  Integration: for each macro-electron,
+ * nsteps classical Runge-Kutta steps with u = ln(1 + eps / 1 keV) as the
+ * independent variable from its energy down to zero, the state being the
+ * path and the energy given to each mechanism; the escaping electron stops
+ * where its path reaches Lx (state interpolated linearly between the two
+ * steps around the crossing) and what it has not lost escapes.  dev may be
+ * NULL (device 0, default stream).  Device buffers come from dev's
+ * allocator (hipMalloc otherwise) and are freed before return.
+ * Synchronous.  HYB_EINVAL for bad inputs (non-positive sizes or
+ * intensities, Z < 1, nsteps outside [1, 1e6]); HYB_ENOMEM; HYB_EDEVICE. */
+hyb_status hyb_model_scan(const hyb_model* m, const double* I0, const double* Z, int64_t n,
+                          double* out, const hyb_device* dev);
+
 /* sizeof of the ABI structs, for bindings to check their layouts:
- * config, source, device, tally_out, state, run_info, envelope, beam. */
-void hyb_abi_sizes(int64_t sizes[8]);
+ * config, source, device, tally_out, state, run_info, envelope, beam, model. */
+void hyb_abi_sizes(int64_t sizes[9]);
 
 /* ---------------- serving engine (continuous batching) -------------------
  * Independent runs share one device.  Each engine tick advances every

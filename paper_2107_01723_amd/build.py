@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhyb.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["hyb_kernels.hip", "hyb_host.cpp", "hyb_tables.cpp"]
+SOURCES = ["hyb_kernels.hip", "hyb_model.hip", "hyb_host.cpp", "hyb_tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

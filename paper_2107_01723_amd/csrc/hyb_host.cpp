@@ -750,7 +750,46 @@ const char* hyb_status_string(hyb_status s) {
 
 const char* hyb_last_error(const hyb_run* run) { return run ? run->err.c_str() : g_err.c_str(); }
 
-void hyb_abi_sizes(int64_t sizes[8]) {
+hyb_status hyb_model_scan(const hyb_model* m, const double* I0, const double* Z, int64_t n, double* out,
+                          const hyb_device* dev) {
+  if (!m) return fail(nullptr, HYB_EINVAL, "null model");
+  if (n < 0 || n > (1LL << 28)) return fail(nullptr, HYB_EINVAL, "n out of range");
+  if (n == 0) return HYB_OK;
+  if (!I0 || !Z || !out) return fail(nullptr, HYB_EINVAL, "null array");
+  if (!(m->wavelength > 0) || !(m->eta_l2e > 0) || !(m->r_fwhm > 0) || !(m->t_fwhm > 0) ||
+      !(m->fg_mean > 0) || m->fg_mean > 1 || !(m->sqrt_fg_mean > 0) || m->sqrt_fg_mean > 1 ||
+      !(m->kappa_esc > 0) || !(m->kappa_tnsa >= 0) || !(m->e_th > 0) || !(m->Lx > 0) || !(m->Ly > 0) ||
+      !(m->Lz > 0) || !(m->theta_c >= 0) || !(m->theta_c < 0.5 * kPi) || !(m->eta_mean >= 0) ||
+      !(m->n_i > 0) || m->nsteps < 1 || m->nsteps > 1000000)
+    return fail(nullptr, HYB_EINVAL, "bad model inputs");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(I0[i] > 0) || !std::isfinite(I0[i]) || !(Z[i] >= 1) || !(Z[i] < 200))
+      return fail(nullptr, HYB_EINVAL, "scan point outside I0 > 0, 1 <= Z < 200");
+  hyb_device d{};
+  if (dev) d = *dev;
+  HIPCHK(nullptr, hipSetDevice(d.device));
+  hipStream_t s = (hipStream_t)d.stream;
+  const size_t bytes = (size_t)n * 8 * sizeof(double);
+  double* buf = (double*)dev_alloc(d, bytes);
+  if (!buf) return fail(nullptr, HYB_ENOMEM, "device allocation failed");
+  double* dI = buf;
+  double* dZ = buf + n;
+  double* dout = buf + 2 * n;
+  hipError_t e = hipMemcpyAsync(dI, I0, n * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dZ, Z, n * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    launch_model(*m, dI, dZ, n, dout, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 6 * n * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(s);
+  dev_free(d, buf);
+  if (e != hipSuccess) return fail(nullptr, HYB_EDEVICE, std::string("hyb_model_scan: ") + hipGetErrorString(e));
+  return HYB_OK;
+}
+
+void hyb_abi_sizes(int64_t sizes[9]) {
   sizes[0] = sizeof(hyb_config);
   sizes[1] = sizeof(hyb_source);
   sizes[2] = sizeof(hyb_device);
@@ -759,6 +798,7 @@ void hyb_abi_sizes(int64_t sizes[8]) {
   sizes[5] = sizeof(hyb_run_info);
   sizes[6] = sizeof(hyb_envelope);
   sizes[7] = sizeof(hyb_beam);
+  sizes[8] = sizeof(hyb_model);
 }
 
 hyb_status hyb_footprint(const hyb_config* cfg, int64_t* bytes) {

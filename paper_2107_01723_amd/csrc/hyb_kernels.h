@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "hyb.h"
 #include "hyb_internal.h"
 
 namespace hyb {
@@ -29,5 +30,8 @@ struct LaunchSet {
 
 void launch_step(const LaunchSet& L, hipStream_t s, int precision, int max_sub);
 void launch_kinetic(const RunDesc* runs, int run, int nblocks, hipStream_t s, int precision);
+// the energy-partition model at n scan points (device arrays; out 6 n doubles)
+void launch_model(const hyb_model& m, const double* I0, const double* Z, long long n, double* out,
+                  hipStream_t s);
 
 }  // namespace hyb

@@ -28,7 +28,7 @@ DELTA_ID_BIT = 0x80000000
 ABI_FUNCTIONS = (
     "hyb_init", "hyb_inject", "hyb_inject_envelope", "hyb_inject_beam", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
     "hyb_run_info_get", "hyb_table_get", "hyb_timing_enable", "hyb_timing_get", "hyb_use_graph",
-    "hyb_footprint", "hyb_free", "hyb_last_error", "hyb_status_string", "hyb_abi_sizes",
+    "hyb_footprint", "hyb_free", "hyb_last_error", "hyb_status_string", "hyb_abi_sizes", "hyb_model_scan",
     "hyb_engine_create", "hyb_engine_admit", "hyb_engine_step", "hyb_engine_poll",
     "hyb_engine_retire", "hyb_engine_stats", "hyb_engine_free",
 )
@@ -97,6 +97,15 @@ class Beam(C.Structure):
                 ("weight", C.c_double)]
 
 
+class Model(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("wavelength", "eta_l2e", "r_fwhm", "t_fwhm", "fg_mean",
+                                           "sqrt_fg_mean", "kappa_esc", "kappa_tnsa", "e_th", "Lx", "Ly",
+                                           "Lz", "theta_c", "eta_mean", "n_i")] + [("nsteps", C.c_int32)]
+
+
+MODEL_KEYS = ("brem", "photon_thr", "ionisation", "reflux", "field", "escaped")
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -158,6 +167,7 @@ def lib():
         "hyb_inject": (C.c_int, [vp, P(Source)]),
         "hyb_inject_envelope": (C.c_int, [vp, P(Envelope)]),
         "hyb_inject_beam": (C.c_int, [vp, P(Beam)]),
+        "hyb_model_scan": (C.c_int, [P(Model), P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double), vp]),
         "hyb_step": (C.c_int, [vp, C.c_int32]),
         "hyb_tally": (C.c_int, [vp, P(TallyOut)]),
         "hyb_get_state": (C.c_int, [vp, P(State)]),
@@ -190,9 +200,9 @@ def lib():
 
 def check_abi():
     """Compare the ctypes struct sizes with the library's."""
-    a = (C.c_int64 * 8)()
+    a = (C.c_int64 * 9)()
     lib().hyb_abi_sizes(a)
-    mine = [C.sizeof(t) for t in (Config, Source, Device, TallyOut, State, RunInfo, Envelope, Beam)]
+    mine = [C.sizeof(t) for t in (Config, Source, Device, TallyOut, State, RunInfo, Envelope, Beam, Model)]
     if list(a) != mine:
         raise RuntimeError(f"ABI struct sizes differ: library {list(a)} binding {mine}")
     return mine
@@ -233,6 +243,26 @@ def footprint(cfg: dict) -> int:
 
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def model_scan(m: dict, I0, Z, device: int = 0, stream=None):
+    """The energy-partition model of Sec. III.B at the scan points (I0
+    [W/m^2], Z) through hyb_model_scan.  Returns an array [6, n] of energy
+    fractions in the order of MODEL_KEYS."""
+    I0 = np.ascontiguousarray(np.asarray(I0, dtype=np.float64).ravel())
+    Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).ravel())
+    if I0.shape != Z.shape:
+        raise ValueError("I0 and Z differ in length")
+    mod = Model()
+    for name, _ in Model._fields_:
+        setattr(mod, name, m[name])
+    out = np.zeros(6 * len(I0))
+    dev, mem, _ = _device(device, stream, True)
+    st = lib().hyb_model_scan(C.byref(mod), _dptr(I0), _dptr(Z), len(I0), _dptr(out), C.byref(dev))
+    del mem
+    if st != HYB_OK:
+        raise HybError(st, "hyb_model_scan: " + lib().hyb_last_error(None).decode())
+    return out.reshape(len(I0), 6).T.copy()
 
 
 class _TorchMemory:

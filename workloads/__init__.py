@@ -206,6 +206,32 @@ def config_depth_dose() -> tuple[dict, dict, int]:
     return cfg, beam(), 400
 
 
+def model_inputs(**over) -> dict:
+    """Inputs of the paper's energy-partition model (Sec. III.B): 100 um
+    cube, 5 um / 40 fs envelope with <fg> 0.41 and <sqrt fg> 0.61,
+    eta_l->e 0.3, kappa_esc 2, kappa_tnsa 2.7e-3, 1 MeV threshold, current
+    cone 20 deg, <eta> 1e-6 Ohm m, n_i 6e28 m^-3, 1 um light; 4000
+    integration steps per macro-electron."""
+    m = dict(wavelength=1e-6, eta_l2e=0.3, r_fwhm=5e-6, t_fwhm=40e-15, fg_mean=0.41, sqrt_fg_mean=0.61,
+             kappa_esc=2.0, kappa_tnsa=2.7e-3, e_th=1.0 * MEV, Lx=100e-6, Ly=100e-6, Lz=100e-6,
+             theta_c=math.radians(20.0), eta_mean=1e-6, n_i=6e28, nsteps=4000)
+    for k, v in over.items():
+        if k not in m:
+            raise KeyError(f"unknown model key {k}")
+        m[k] = v
+    return m
+
+
+def model_scan_grid(n_int: int = 41, z_values=None) -> tuple[np.ndarray, np.ndarray]:
+    """The intensity-Z plane of the model's heatmap: n_int log-spaced
+    intensities over 1e20-1e22 W/cm^2 (in W/m^2) times atomic numbers
+    (default 1..92); returns flat (I0, Z) arrays."""
+    z = np.arange(1, 93, dtype=np.float64) if z_values is None else np.asarray(z_values, dtype=np.float64)
+    i0 = intensity_wcm2(np.logspace(20.0, 22.0, n_int))
+    I, Z = np.meshgrid(i0, z, indexing="ij")
+    return I.ravel(), Z.ravel()
+
+
 def scale_particles(cfg: dict, srcs: list[dict], n_macro: int) -> tuple[dict, list[dict]]:
     """Same workload with fewer macro-electrons (same physics per electron:
     the default weight rule keeps the injected energy fixed)."""
