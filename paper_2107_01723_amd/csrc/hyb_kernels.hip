@@ -659,6 +659,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   unsigned base_val = 0, far_val = 0;
   long long base_at = -1, far_at = -1;
   int carry_js = -1, carry_tile = -1;   // LDS region slot carried over, and its tile
+  int f_tile0 = -1, f_tile1 = -1;       // tiles whose field halos the two LDS slots hold
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
     const long long i = ch * kBlock + threadIdx.x;
@@ -711,23 +712,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         while (js_hi == js_lo || js_hi == carry_js) ++js_hi;
       }
     }
+    // LDS field-halo slot of each home (fields do not change during the launch)
+    int fs_lo = -1, fs_hi = -1;
     if (phys & PHYS_FIELDS) {
-      // the field halos of the two homes, staged in LDS (rows of 6 nodes along
-      // x are contiguous in HBM); nodes outside the grid are never gathered
-      const int nreg = hm.ok ? (hm2.ok && thi != tlo ? 2 : 1) : 0;
+      // a home whose halo a slot already holds keeps it; a new one takes the
+      // other home's free slot, else the slot of the smaller (older) tile
+      if (hm.ok) fs_lo = f_tile0 == tlo ? 0 : (f_tile1 == tlo ? 1 : -1);
+      if (two) fs_hi = f_tile0 == thi ? 0 : (f_tile1 == thi ? 1 : -1);
+      const bool need_lo = hm.ok && fs_lo < 0;
+      if (need_lo) fs_lo = fs_hi >= 0 ? 1 - fs_hi : (f_tile0 <= f_tile1 ? 0 : 1);
+      const bool need_hi = two && fs_hi < 0;
+      if (need_hi) fs_hi = 1 - fs_lo;
+      const int nst = (need_lo ? 1 : 0) + (need_hi ? 1 : 0);
+      if (nst) {
+        // the new halos, staged in LDS: the six field loads of a node are
+        // issued together (rows of 6 nodes along x are contiguous in HBM);
+        // nodes outside the grid are never gathered
 #pragma unroll 1
-      for (int f = 0; f < 6; ++f) {
-        const gptr<const T> src = f == 0 ? E0 : f == 1 ? E1 : f == 2 ? E2 : f == 3 ? B0 : f == 4 ? B1 : B2;
-        for (int t = threadIdx.x; t < nreg * kHaloN; t += kBlock) {
-          const int r = t >= kHaloN, l = t - r * kHaloN;
-          const int i = (r ? hm2.bx : hm.bx) + l % kHalo, j = (r ? hm2.by : hm.by) + (l / kHalo) % kHalo;
-          const int k = (r ? hm2.bz : hm.bz) + l / (kHalo * kHalo);
-          T v = (T)0;
-          if (i >= 0 && j >= 0 && k >= 0 && i <= nx && j <= ny && k <= nz) v = src[i + sx * j + sxy * k];
-          S.F[r][f][l] = v;
+        for (int t = threadIdx.x; t < nst * kHaloN; t += kBlock) {
+          const bool is_lo = need_lo && t < kHaloN;
+          const int l = t >= kHaloN ? t - kHaloN : t;
+          const int i = (is_lo ? hm.bx : hm2.bx) + l % kHalo;
+          const int j = (is_lo ? hm.by : hm2.by) + (l / kHalo) % kHalo;
+          const int k = (is_lo ? hm.bz : hm2.bz) + l / (kHalo * kHalo);
+          const bool in = i >= 0 && j >= 0 && k >= 0 && i <= nx && j <= ny && k <= nz;
+          const long long o = in ? i + (long long)sx * j + (long long)sxy * k : 0;
+          T v[6];
+          v[0] = in ? E0[o] : (T)0;
+          v[1] = in ? E1[o] : (T)0;
+          v[2] = in ? E2[o] : (T)0;
+          v[3] = in ? B0[o] : (T)0;
+          v[4] = in ? B1[o] : (T)0;
+          v[5] = in ? B2[o] : (T)0;
+          T* d = &S.F[is_lo ? fs_lo : fs_hi][0][l];
+#pragma unroll
+          for (int f = 0; f < 6; ++f) d[f * kHaloN] = v[f];
         }
+        if (need_lo) { if (fs_lo == 0) f_tile0 = tlo; else f_tile1 = tlo; }
+        if (need_hi) { if (fs_hi == 0) f_tile0 = thi; else f_tile1 = thi; }
+        __syncthreads();
       }
-      __syncthreads();
     }
     // offsets returned by the previous chunk's atomics: waiting for them here
     // costs nothing, this chunk's loads (issued later) have landed
@@ -754,7 +778,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       if (phys & PHYS_FIELDS) {
         T Ex, Ey, Ez, Bx, By, Bz;
         if (reg >= 0) {   // from the home halo staged in LDS
-          const T* F = &S.F[reg][0][0];
+          const T* F = &S.F[reg == 0 ? fs_lo : fs_hi][0][0];
           Ex = gather8_lds(F, rbx, rby, rbz, sxa, nya, nza);
           Ey = gather8_lds(F + kHaloN, rbx, rby, rbz, nxa, sya, nza);
           Ez = gather8_lds(F + 2 * kHaloN, rbx, rby, rbz, nxa, nya, sza);
