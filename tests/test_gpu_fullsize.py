@@ -125,3 +125,45 @@ def test_fullsize_fp32_256cube_properties(P):
     print(f"  closure {_closure(t):.2e}, alive {t['n_alive']}", flush=True)
     assert t["n_alive"] > 50_000_000
     _check_run_properties(t, None)
+
+
+def test_fullsize_fp64_delta_rays(P):
+    """The 2e7-electron FP64 workload with delta rays (about a million
+    records a step): 2000 electrons drawn at step 40 stepped once by the
+    oracle against the GPU's step of the whole population (the parents; a
+    delta ray's id depends on the whole step's records), then whole-run
+    properties: ledger closure, unique ids, no lost delta rays."""
+    cfg, srcs, _ = W.config_fp64_large()
+    cfg["physics"] |= W.PHYS_DELTA
+    cfg["max_particles"] = 30_000_000
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(40)
+    st0 = run.get_state()
+    run.step(1)
+    st1 = run.get_state()
+    t = run.tally()
+    run.close()
+    n0 = len(st0["ids"])
+    print(f"  step 40: {n0} electrons alive, {st0['delta_next']} delta rays so far, "
+          f"{t['counters']['n_delta']} emitted", flush=True)
+    assert st0["delta_next"] > 1_000_000
+    pick = np.random.default_rng(5).choice(n0, 2000, replace=False)
+    ids = st0["ids"][pick]
+    ora = OracleRun(cfg)
+    ora.set_state(dict(_subset(st0, ids), step=st0["step"], next_id=st0["next_id"],
+                       delta_next=st0["delta_next"]))
+    ora.step()
+    ref = ora.state()
+    born = ref["ids"] >= 0x80000000 + st0["delta_next"]
+    ref = {k: (v[~born] if k in ("pos", "p", "w", "tau", "tau_d", "ids") else v) for k, v in ref.items()}
+    got = _subset(st1, ids)
+    err, only = particle_errors(got, ref, cfg["dx"])
+    print(f"  compared {len(err['ids'])}: max|dp|={err['p'].max():.2e} max|dtau_d|={err['tau_d'].max():.2e} "
+          f"only-one-side={len(only)}", flush=True)
+    assert not only and len(err["ids"]) > 1800
+    for k in ("p", "pos", "tau", "tau_d", "w"):
+        assert err[k].max() < 1e-10, k
+    assert _closure(t) < 1e-6
+    assert t["counters"]["n_delta_lost"] == 0
+    assert len(np.unique(st1["ids"])) == len(st1["ids"])
