@@ -1208,9 +1208,20 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const RunDesc* __restrict
 }
 
 // Scatter of the electrons into the other particle buffer in tile order
-// (dead electrons dropped).  The particle kernel fixed every electron's slot
-// when it counted the destinations; here each chunk ranks its electrons
-// inside their bins and copies them.
+// (dead electrons dropped).  The particle kernel fixed where each chunk's
+// electrons bound for a tile go (tile start + the chunk's offset in it); here
+// each chunk ranks its electrons inside their destination bins, gathers them
+// in LDS in bin order, and writes every bin's run with consecutive threads,
+// so that a run reaches HBM as whole sectors rather than one piece per wave.
+// Electrons bound outside the chunk's bins (rare) are written directly.
+template <typename T> struct ScatterLds {
+  unsigned cnt[kNbN];          // electrons per bin, then (after the scan) bin starts
+  unsigned start[kNbN];
+  T f[9][kBlock];              // ox oy oz ux uy uz wn tau taud, in bin order
+  uint32_t cell[kBlock], id[kBlock];
+  unsigned char bin[kBlock];
+};
+
 template <typename T, bool D>
 __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ runs,
                                                     const BlockMap* __restrict__ bmap) {
@@ -1223,42 +1234,76 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const RunDesc* __restrict__ 
   n = n < R.capacity ? n : R.capacity;
   const PartG<T> A = part_g<T>(R.p[ctr->cur]);
   const PartG<T> B = part_g<T>(R.p[ctr->cur ^ 1]);
-  __shared__ unsigned cnt[2][kNbN];   // rank counters, alternating between chunks
-  if (threadIdx.x < kNbN) { cnt[0][threadIdx.x] = 0; cnt[1][threadIdx.x] = 0; }
+  const bool dl = D && (R.physics & PHYS_DELTA);
+  __shared__ ScatterLds<T> L;
   const ChunkRange cr = chunk_run(bm, n);
-  int p = 0;
-  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, p ^= 1) {
-    // the counters of the other parity were last used by the previous chunk
+  const int lane = threadIdx.x & 63;
+  for (long long ch = cr.beg; ch < cr.end; ch += cr.stride) {
+    // the previous chunk has finished reading the staged electrons
     __syncthreads();
-    if (threadIdx.x < kNbN) cnt[p ^ 1][threadIdx.x] = 0;
+    if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
     const long long i = ch * kBlock + threadIdx.x;
     const uint32_t cell = i < n ? A.cell[i] : kDead;
     const Home hm = make_home(R, __builtin_amdgcn_readfirstlane(G(R.chunk_home)[ch]));
-    T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0, taud = 0;
+    T v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t id = 0;
-    int t = -1, b = -1;
-    unsigned off = 0;
+    int b = -1;
+    long long far_slot = -1;
     if (cell != kDead) {
-      ox = A.ox[i]; oy = A.oy[i]; oz = A.oz[i];
-      ux = A.ux[i]; uy = A.uy[i]; uz = A.uz[i];
-      wn = A.wn[i]; tau = A.tau[i]; id = A.id[i];
-      if constexpr (D) {
-        if (R.physics & PHYS_DELTA) taud = A.taud[i];
-      }
+      v[0] = A.ox[i]; v[1] = A.oy[i]; v[2] = A.oz[i];
+      v[3] = A.ux[i]; v[4] = A.uy[i]; v[5] = A.uz[i];
+      v[6] = A.wn[i]; v[7] = A.tau[i]; id = A.id[i];
+      if (dl) v[8] = A.taud[i];
       const int tx = cell_i(cell) >> 2, ty = cell_j(cell) >> 2, tz = cell_k(cell) >> 2;
-      t = tx + R.ntx * (ty + R.nty * tz);
       b = nb_bin(hm, tx, ty, tz);
-      off = G(R.tile_start)[t] + (b >= 0 ? G(R.chunk_base)[ch * kNbN + b] : G(R.far_off)[i]);
+      if (b < 0) far_slot = (long long)G(R.tile_start)[tx + R.ntx * (ty + R.nty * tz)] + G(R.far_off)[i];
     }
-    const unsigned rank = wave_rank(cnt[p], b);
-    const long long slot = (long long)off + (b >= 0 ? rank : 0u);
-    if (t >= 0 && slot < R.capacity) {   // counts and scatter agree; the bound is a guard
-      B.cell[slot] = cell;
-      B.ox[slot] = ox; B.oy[slot] = oy; B.oz[slot] = oz;
-      B.ux[slot] = ux; B.uy[slot] = uy; B.uz[slot] = uz;
-      B.wn[slot] = wn; B.tau[slot] = tau; B.id[slot] = id;
-      if constexpr (D) {
-        if (R.physics & PHYS_DELTA) B.taud[slot] = taud;
+    __syncthreads();   // counts cleared
+    const unsigned rank = wave_rank(L.cnt, b);
+    __syncthreads();   // counts complete
+    if (threadIdx.x < 64) {
+      // exclusive scan of the 125 bin counts: two bins per lane, then the wave
+      const int b0 = 2 * lane, b1 = 2 * lane + 1;
+      const unsigned c0 = b0 < kNbN ? L.cnt[b0] : 0u, c1 = b1 < kNbN ? L.cnt[b1] : 0u;
+      unsigned s = c0 + c1;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(s, o, 64);
+        if (lane >= o) s += u;
+      }
+      const unsigned ex = s - c0 - c1;
+      if (b0 < kNbN) L.start[b0] = ex;
+      if (b1 < kNbN) L.start[b1] = ex + c0;
+    }
+    __syncthreads();   // bin starts ready
+    if (b >= 0) {
+      const unsigned q = L.start[b] + rank;
+#pragma unroll
+      for (int f = 0; f < 9; ++f) L.f[f][q] = v[f];
+      L.cell[q] = cell;
+      L.id[q] = id;
+      L.bin[q] = (unsigned char)b;
+    } else if (far_slot >= 0 && far_slot < R.capacity) {   // outside the chunk's bins
+      B.cell[far_slot] = cell;
+      B.ox[far_slot] = v[0]; B.oy[far_slot] = v[1]; B.oz[far_slot] = v[2];
+      B.ux[far_slot] = v[3]; B.uy[far_slot] = v[4]; B.uz[far_slot] = v[5];
+      B.wn[far_slot] = v[6]; B.tau[far_slot] = v[7]; B.id[far_slot] = id;
+      if (dl) B.taud[far_slot] = v[8];
+    }
+    __syncthreads();   // electrons staged in bin order
+    const unsigned nbinned = L.start[kNbN - 1] + L.cnt[kNbN - 1];
+    const unsigned q = threadIdx.x;
+    if (q < nbinned) {
+      const int bq = L.bin[q];
+      const int tx = hm.tx + bq % kNb - 2, ty = hm.ty + (bq / kNb) % kNb - 2, tz = hm.tz + bq / (kNb * kNb) - 2;
+      const long long slot = (long long)G(R.tile_start)[tx + R.ntx * (ty + R.nty * tz)] +
+                             G(R.chunk_base)[ch * kNbN + bq] + (q - L.start[bq]);
+      if (slot < R.capacity) {   // counts and scatter agree; the bound is a guard
+        B.cell[slot] = L.cell[q];
+        B.ox[slot] = L.f[0][q]; B.oy[slot] = L.f[1][q]; B.oz[slot] = L.f[2][q];
+        B.ux[slot] = L.f[3][q]; B.uy[slot] = L.f[4][q]; B.uz[slot] = L.f[5][q];
+        B.wn[slot] = L.f[6][q]; B.tau[slot] = L.f[7][q]; B.id[slot] = L.id[q];
+        if (dl) B.taud[slot] = L.f[8][q];
       }
     }
   }
