@@ -493,3 +493,36 @@ def test_depth_dose_benchmark_setup(P, precision):
             assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=2e-2), k
     assert t["counters"]["n_reflux"] == 0
     run.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(W.FP64, 1e-12), (W.FP32_MIXED, 1e-6)])
+def test_checkpoint_resume(P, precision, tol):
+    """hyb_get_state / hyb_set_state as a checkpoint: 15 steps, the state
+    into a fresh run (sources scheduled again), 15 more steps -- the same
+    electrons (delta rays and their depths included), temperatures and
+    delta-ray numbering as 30 uninterrupted steps.  Positions cross the
+    boundary in metres, so they agree to rounding rather than bitwise."""
+    cfg, srcs, _ = small_config(4000, precision=precision, brem_boost=10.0, physics=DELTA_PHYS,
+                                sort_every=2, max_particles=60000)
+    ref_run = P.Run(cfg)
+    ref_run.inject(srcs[0])
+    ref_run.step(30)
+    ref = ref_run.get_state()
+    ref_run.close()
+    a = P.Run(cfg)
+    a.inject(srcs[0])
+    a.step(15)
+    mid = a.get_state()
+    a.close()
+    b = P.Run(cfg)
+    b.inject(srcs[0])
+    b.set_state(mid)
+    b.step(15)
+    got = b.get_state()
+    b.close()
+    assert got["step"] == ref["step"] == 30 and got["delta_next"] == ref["delta_next"] > 0
+    err, only = particle_errors(got, ref, cfg["dx"])
+    assert not only
+    for k in ("p", "pos", "tau", "tau_d", "w"):
+        assert err[k].max() < tol, (k, err[k].max())
+    assert rel(got["Te"], ref["Te"]) < tol
