@@ -160,6 +160,19 @@ typedef struct hyb_config {
   int32_t sort_every;       /* cell-sort and compact particles every this many steps; 0 = never */
   double delta_cut;         /* delta-ray cut [J] (App. B: 1 keV), > 0 with HYB_PHYS_DELTA */
   int32_t bc_x, bc_y, bc_z; /* HYB_BC_* per axis (HYB_BC_REFLUX is the paper's) */
+  /* compound solid (App. A: several single-element solids share the cells):
+   * n_extra further elements mixed into the slab with (Z, A, rho, I_ex) above.
+   * Electron processes sum over the elements; heating follows the paper's
+   * compound rule (n_e summed, 1/C averaged with weights Z n); each element's
+   * Z*, Coulomb logarithm and resistivity are taken as if it filled the cell
+   * at the total ion density, the resistivity is sum(x Z* eta)/sum(x Z*)
+   * over the ion shares x, and the electron-ion exchange rates add with the
+   * shares.  Not with HYB_PHYS_FSIGMA. */
+  int32_t n_extra;          /* 0..3 */
+  double extra_Z[3];        /* atomic numbers */
+  double extra_A[3];        /* molar masses [g/mol] */
+  double extra_rho[3];      /* partial mass densities [kg/m^3] */
+  double extra_I_ex[3];     /* mean excitation energies [J]; 0 -> 11 eV * Z */
 } hyb_config;
 
 /* An injection source (App. B, Sec. II.B): n_macro electrons spread evenly

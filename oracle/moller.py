@@ -93,6 +93,30 @@ def restricted_stopping(eps, Z, n_i, I_ex, e_cut):
     return out
 
 
+def restricted_stopping_mix(eps, elems, e_cut):
+    """The restricted stopping power of App. B summed over the elements of a
+    compound, each with its own Z n and I; the density effect is the
+    compound's: omega_p of all the electrons and ln I = sum(Z n ln I)/sum(Z n).
+    The total is clamped >= 0."""
+    eps = np.asarray(eps, dtype=np.float64)
+    out = np.zeros_like(eps)
+    ok = eps > 0.0
+    t = eps[ok] / K.MEC2
+    g = t + 1.0
+    b2 = 1.0 - 1.0 / (g * g)
+    D = np.minimum(e_cut / K.MEC2, 0.5 * t)
+    zn = sum(e["Z"] * e["n"] for e in elems)
+    lnI = sum(e["Z"] * e["n"] * math.log(e["I_ex"]) for e in elems) / zn
+    dens = density_effect(np.sqrt(b2) * g, zn, 1.0, math.exp(lnI))
+    base = np.log(2.0 * (g + 1.0)) + f_minus(t, D) - dens
+    S = 0.0
+    for e in elems:
+        pref = e["Z"] * e["n"] * K.E ** 4 / (8.0 * math.pi * K.EPS0 ** 2 * K.ME * b2 * K.C ** 2)
+        S = S + pref * (base - 2.0 * math.log(e["I_ex"] / K.MEC2))
+    out[ok] = np.maximum(S, 0.0)
+    return out
+
+
 def _bracket(x, g):
     a = (2.0 * g - 1.0) / (g * g)
     b = (g - 1.0) ** 2 / (g * g)

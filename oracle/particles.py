@@ -168,6 +168,31 @@ def stopping_ion(eps, p, Z, n_i, I_ex):
     return np.maximum(S, 0.0)
 
 
+def stopping_ion_mix(eps, p, elems):
+    """eq. (stop_ion) summed over the elements of a compound (App. A), each
+    with its own Z, n and I_ex; the total clamped >= 0."""
+    g = gamma_of(p)
+    v2 = np.sum(p * p, axis=-1) / (g * K.ME) ** 2
+    common = 0.5 * np.log(g + 1.0) + 0.909 / g ** 2 - 0.818 / g - 0.246
+    S = 0.0
+    for e in elems:
+        L = np.log(np.maximum(eps, 1e-300) / e["I_ex"]) + common
+        S = S + e["Z"] * e["n"] * K.E ** 4 / (4.0 * math.pi * K.EPS0 ** 2 * K.ME * v2) * L
+    return np.maximum(S, 0.0)
+
+
+def davies_sigma2_mix(p, elems, dt):
+    """The Davies variance summed over the elements of a compound (each
+    Z^2 n with its own screening logarithm), the total clamped >= 0."""
+    g = gamma_of(p)
+    pm = np.sqrt(np.sum(p * p, axis=-1))
+    s = 0.0
+    for e in elems:
+        lg = np.log(4.0 * K.EPS0 * K.H * pm / (e["Z"] ** (1.0 / 3.0) * K.ME * K.E ** 2))
+        s = s + e["Z"] * e["Z"] * e["n"] * lg
+    return (K.E ** 4 * g * K.ME / (2.0 * math.pi * K.EPS0 ** 2 * pm ** 3) * np.maximum(s, 0.0) * dt)
+
+
 def davies_sigma2(p, Z, n_i, dt):
     """Variance of the Davies deflection over dt (App. B):
     Z^2 e^4 n_i gamma m/(2 pi eps0^2 p^3) ln(4 eps0 h p/(Z^1/3 m e^2)) dt,

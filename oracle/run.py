@@ -71,10 +71,20 @@ class OracleRun:
         self.Z, self.A, self.rho = float(c["Z"]), float(c["A"]), float(c["rho"])
         self.n_i = S.ion_density(self.rho, self.A)
         self.I_ex = c["I_ex"] if c["I_ex"] > 0 else 11.0 * K.E * self.Z
+        # the solid's elements (App. A: several single-element solids make a
+        # compound); the first is (Z, A, rho, I_ex)
+        self.elems = [dict(S.element(self.Z, self.A, self.rho), I_ex=self.I_ex)]
+        for k in range(int(c.get("n_extra", 0))):
+            Zk = float(c["extra_Z"][k])
+            Ik = c["extra_I_ex"][k] if c["extra_I_ex"][k] > 0 else 11.0 * K.E * Zk
+            self.elems.append(dict(S.element(Zk, c["extra_A"][k], c["extra_rho"][k]), I_ex=Ik))
+        if len(self.elems) > 1 and int(c["physics"]) & PHYS_FSIGMA:
+            raise ValueError("eq. F_sigma is defined for single-element solids")
         self.a0 = PT.a0_of(c["I0"], c["wavelength"])
         self.eps_esc = c["kappa_esc"] * self.a0 * K.MEC2
         self.dp_tnsa = c["kappa_tnsa"] * self.a0 * K.ME * K.C
         self.cz = T.c_z(self.Z)
+        self.ncz = sum(e["n"] * T.c_z(e["Z"]) for e in self.elems)   # sum of n C_Z
         self.table = T.BremTable(c["k_cut"], c["table_emax"], int(c["table_nT"]),
                                  int(c["table_nr"]), int(c["table_shape"]))
         ix_lo = c["x_lo"] / self.dx
@@ -86,8 +96,8 @@ class OracleRun:
             raise ValueError("slab outside the grid")
         self.box_lo = np.array([float(self.ix_lo), 0.0, 0.0])          # cell units
         self.box_hi = np.array([float(self.ix_hi), float(self.ny), float(self.nz)])
-        self.n_sub = int(c["n_sub"]) if c["n_sub"] > 0 else S.n_sub_auto(
-            self.dt, self.dx, self.Z, self.A, self.rho, c["T0"], c["lambda1"], c["lambda2"])
+        self.n_sub = int(c["n_sub"]) if c["n_sub"] > 0 else S.n_sub_auto_mix(
+            self.dt, self.dx, self.elems, c["T0"], c["lambda1"], c["lambda2"])
         shape = (self.nx + 1, self.ny + 1, self.nz + 1)
         self.E = tuple(np.zeros(shape) for _ in range(3))
         self.B = tuple(np.zeros(shape) for _ in range(3))
@@ -127,7 +137,7 @@ class OracleRun:
         c = self.cfg
         if c["eta_fixed"] > 0.0:
             return np.full(np.shape(Te), float(c["eta_fixed"]))
-        eta, _, _ = S.resistivity(Te, Ti, self.Z, self.A, self.rho, c["lambda1"], c["lambda2"])
+        eta, _, _ = S.resistivity_mix(Te, Ti, self.elems, c["lambda1"], c["lambda2"])
         return eta
 
     def add_source(self, src: dict):
@@ -291,9 +301,9 @@ class OracleRun:
         # ionisation
         if phys & PHYS_ION:
             if phys & PHYS_DELTA:
-                Sion = M.restricted_stopping(eps1, self.Z, self.n_i, self.I_ex, self.e_cut)
+                Sion = M.restricted_stopping_mix(eps1, self.elems, self.e_cut)
             else:
-                Sion = PT.stopping_ion(eps1, p, self.Z, self.n_i, self.I_ex)
+                Sion = PT.stopping_ion_mix(eps1, p, self.elems)
             v = np.sqrt(np.sum(vel * vel, axis=-1))
             dE = np.minimum(Sion * v * dt, eps1)
             p = PT.with_energy(p, eps1 - dE)
@@ -307,7 +317,8 @@ class OracleRun:
         if phys & PHYS_DELTA:
             g2 = PT.gamma_of(p)
             beta = np.sqrt(np.sum(p * p, axis=-1)) / (g2 * K.ME * K.C)
-            taud = taud - self.n_i * M.moller_sigma(eps2, self.Z, self.e_cut) * beta * K.C * dt
+            sig_d = sum(e["n"] * M.moller_sigma(eps2, e["Z"], self.e_cut) for e in self.elems)
+            taud = taud - sig_d * beta * K.C * dt
             # no delta ray once eps <= 2 cut (the depth then stays put)
             ie = np.nonzero((taud < 0.0) & (eps2 > 2.0 * self.e_cut))[0]
             if len(ie):
@@ -339,9 +350,9 @@ class OracleRun:
             beta2 = np.sqrt(np.sum(p * p, axis=-1)) / (g2 * K.ME * K.C)
             # cross-sections of the cell at x^n, enhanced by eq. F_sigma if enabled
             fs = fsig[cell] if fsig is not None else 1.0
-            tau = tau - B_ * self.n_i * self.cz * fs * self.table.sigma(eps2) * beta2 * K.C * dt
+            tau = tau - B_ * self.ncz * fs * self.table.sigma(eps2) * beta2 * K.C * dt
             emit = tau < 0.0
-            sub = self.n_i * self.cz * fs * self.table.sub(eps2) * beta2 * K.C * dt
+            sub = self.ncz * fs * self.table.sub(eps2) * beta2 * K.C * dt
             if np.any(emit):
                 kph[emit] = self.table.sample_k(eps2[emit], u_c[3][emit])
             p_pre = p.copy()
@@ -371,7 +382,7 @@ class OracleRun:
             pm = np.sqrt(np.sum(p * p, axis=-1))
             moving = pm > 0.0
             if np.any(moving):
-                s2 = PT.davies_sigma2(p[moving], self.Z, self.n_i, dt)
+                s2 = PT.davies_sigma2_mix(p[moving], self.elems, dt)
                 dth = PT.box_muller(u_c[0][moving], u_c[1][moving]) * np.sqrt(s2)
                 p[moving] = PT.rotate(p[moving], dth, 2.0 * math.pi * u_c[2][moving])
                 # elastic: a change of the kinetic energy is rounding, booked apart
@@ -465,9 +476,9 @@ class OracleRun:
         if phys & PHYS_HEAT:
             s = self.solid
             j2 = F.cell_current_sq(self.j)
-            Te, Ti, eta = S.heat_update(self.Te[s], self.Ti[s], j2[s], self.ion_heat[s],
-                                        self.eta[s], dt, dx ** 3, self.Z, self.A, self.rho,
-                                        c["lambda1"], c["lambda2"])
+            Te, Ti, eta = S.heat_update_mix(self.Te[s], self.Ti[s], j2[s], self.ion_heat[s],
+                                            self.eta[s], dt, dx ** 3, self.elems,
+                                            c["lambda1"], c["lambda2"])
             self.Te[s], self.Ti[s] = Te, Ti
             if c["eta_fixed"] <= 0.0:
                 self.eta[s] = eta

@@ -162,3 +162,86 @@ def n_sub_auto(dt, dx, Z, A, rho, T0, lambda1, lambda2):
     eta, _, _ = resistivity(T, T, Z, A, rho, lambda1, lambda2)
     dt_max = 0.9 * K.MU0 * dx * dx / (6.0 * float(np.max(eta)))
     return max(1, int(math.ceil(dt / dt_max)))
+
+
+# ---------------------------------------------------------------------------
+# compound solids (App. A: several single-element solids in one cell)
+# ---------------------------------------------------------------------------
+# An element of a compound is a dict with Z, A [g/mol], rho (its partial mass
+# density [kg/m^3]) and n (its ion density [m^-3]).  The paper gives the rule
+# for the electron heating only: n_e = Z n_i of eq. Te_rise becomes the sum of
+# Z n over the solids, and 1/C is averaged with weights Z n.  Readings for
+# the rest, chosen so that two overlapping halves of one material behave as
+# that material (the paper's stated criterion for its heating rule):
+#   * each element's Z*, Coulomb logarithm, relaxation time and resistivity are
+#     evaluated as if the element filled the cell at the total ion density
+#     n_t = sum n (for Z*: at the mass density n_t A amu);
+#   * resistivity: the free electrons' collision rates add over the ion
+#     species in proportion to their shares x = n / n_t (Matthiessen), so
+#     eta = sum(x Z* eta_el) / sum(x Z*);
+#   * exchange: dTe/dt = (Ti - Te) sum(x a_el), and energy conservation
+#     between n_e* = n_t sum(x Z*) free electrons and n_t ions gives
+#     dTi/dt = (Te - Ti) sum(x a_el) sum(x Z*).
+# With one element all of these are the single-element formulas above.
+
+def element(Z, A, rho):
+    return dict(Z=float(Z), A=float(A), rho=float(rho), n=ion_density(rho, A))
+
+
+def heat_capacity_mix(Te, elems):
+    """<1/C> weighted by Z n (App. A compounds) and n_e = sum Z n: returns
+    (n_e, <1/C>)."""
+    ne = sum(e["Z"] * e["n"] for e in elems)
+    inv_c = sum(e["Z"] * e["n"] / heat_capacity(Te, e["Z"]) for e in elems) / ne
+    return ne, inv_c
+
+
+def _as_if_filled(e, n_t):
+    """The element as if it filled the cell at the total ion density."""
+    return dict(e, n=n_t, rho=n_t * e["A"] * K.AMU)
+
+
+def resistivity_mix(Te, Ti, elems, lambda1, lambda2):
+    """Compound resistivity (reading above).  Returns (eta, [Z*_el], [lnL_el])."""
+    n_t = sum(e["n"] for e in elems)
+    num, den = 0.0, 0.0
+    zs, lls = [], []
+    for e in elems:
+        f = _as_if_filled(e, n_t)
+        eta_e, Zs, lnL = resistivity(Te, Ti, f["Z"], f["A"], f["rho"], lambda1, lambda2)
+        x = e["n"] / n_t
+        num = num + x * Zs * eta_e
+        den = den + x * Zs
+        zs.append(Zs)
+        lls.append(lnL)
+    return num / den, zs, lls
+
+
+def heat_update_mix(Te, Ti, j2, ion_heat, eta, dt, dV, elems, lambda1, lambda2):
+    """heat_update for a compound: the heating of eq. Te_rise with the
+    paper's compound rule, exchange and resistivity by the readings above."""
+    n_t = sum(e["n"] for e in elems)
+    rho_eps = eta * j2 * dt + ion_heat / dV
+    ne, inv_c = heat_capacity_mix(Te, elems)
+    Te1 = Te + rho_eps * inv_c / (ne * K.KB)
+    a = 0.0
+    zbar = 0.0
+    for e in elems:
+        f = _as_if_filled(e, n_t)
+        Zs = zstar_more(f["Z"], f["A"], f["rho"], Te1)
+        lnL = coulomb_log(Te1, Ti, Zs, n_t)
+        a_e, _ = exchange_rates(Te1, Ti, Zs, lnL, n_t, f["A"] * K.AMU)
+        x = e["n"] / n_t
+        a = a + x * a_e
+        zbar = zbar + x * Zs
+    Te2, Ti2 = exchange_exact(Te1, Ti, a, a * zbar, dt)
+    eta2, _, _ = resistivity_mix(Te2, Ti2, elems, lambda1, lambda2)
+    return Te2, Ti2, eta2
+
+
+def n_sub_auto_mix(dt, dx, elems, T0, lambda1, lambda2):
+    """n_sub_auto with the compound resistivity."""
+    T = np.logspace(math.log10(T0), 9.0, 400)
+    eta, _, _ = resistivity_mix(T, T, elems, lambda1, lambda2)
+    dt_max = 0.9 * K.MU0 * dx * dx / (6.0 * float(np.max(eta)))
+    return max(1, int(math.ceil(dt / dt_max)))

@@ -206,18 +206,52 @@ static std::string validate(const hyb_config& c) {
   if (c.eta_fixed < 0) return "eta_fixed must be >= 0";
   if (c.n_sub < 0 || c.n_sub > 1000) return "n_sub out of range";
   if (c.sort_every < 0) return "sort_every must be >= 0";
+  if (c.n_extra < 0 || c.n_extra > 3) return "n_extra must be in [0, 3]";
+  for (int k = 0; k < c.n_extra; ++k)
+    if (!(c.extra_Z[k] >= 1) || !(c.extra_A[k] > 0) || !(c.extra_rho[k] > 0) || c.extra_I_ex[k] < 0)
+      return "bad compound element";
+  if (c.n_extra > 0 && (c.physics & HYB_PHYS_FSIGMA)) return "eq. F_sigma needs a single-element solid";
   for (int b : {c.bc_x, c.bc_y, c.bc_z})
     if (b != HYB_BC_REFLUX && b != HYB_BC_OPEN && b != HYB_BC_MIRROR) return "unknown boundary kind";
   return "";
 }
 
-static int n_sub_auto(const hyb_config& c, double n_i) {
-  const Solid sol = make_solid(c.Z, c.A, c.rho, n_i, c.lambda1, c.lambda2);
+// The solid's elements: the first is (Z, A, rho, I_ex), then the extras.
+struct Elem { double Z, A, rho, n, I; };
+static std::vector<Elem> elements(const hyb_config& c) {
+  std::vector<Elem> v;
+  v.push_back(Elem{c.Z, c.A, c.rho, c.rho / (c.A * kAmu), c.I_ex > 0 ? c.I_ex : 11.0 * kE * c.Z});
+  for (int k = 0; k < c.n_extra; ++k)
+    v.push_back(Elem{c.extra_Z[k], c.extra_A[k], c.extra_rho[k], c.extra_rho[k] / (c.extra_A[k] * kAmu),
+                     c.extra_I_ex[k] > 0 ? c.extra_I_ex[k] : 11.0 * kE * c.extra_Z[k]});
+  return v;
+}
+
+// The compound of the heat update: one element is the plain solid; several
+// are each taken as if they filled the cell at the total ion density.
+static Mix make_mix(const hyb_config& c) {
+  const std::vector<Elem> e = elements(c);
+  Mix m{};
+  m.n = (int)e.size();
+  double n_t = 0.0, ne = 0.0;
+  for (const Elem& x : e) { n_t += x.n; ne += x.Z * x.n; }
+  m.ne = ne;
+  for (int k = 0; k < m.n; ++k) {
+    m.w[k] = e[k].Z * e[k].n / ne;
+    m.x[k] = e[k].n / n_t;
+    m.el[k] = m.n == 1 ? make_solid(e[k].Z, e[k].A, e[k].rho, e[k].n, c.lambda1, c.lambda2)
+                       : make_solid(e[k].Z, e[k].A, n_t * e[k].A * kAmu, n_t, c.lambda1, c.lambda2);
+  }
+  return m;
+}
+
+static int n_sub_auto(const hyb_config& c) {
+  const Mix mix = make_mix(c);
   double eta_max = 0.0;
   const double a = log10(c.T0), b = 9.0;
   for (int i = 0; i < 400; ++i) {
     const double T = i == 399 ? 1e9 : pow(10.0, a + i * (b - a) / 399.0);
-    eta_max = fmax(eta_max, resistivity(sol, T, T));
+    eta_max = fmax(eta_max, resistivity_mix(mix, T, T));
   }
   const double dt_max = 0.9 * kMu0 * c.dx * c.dx / (6.0 * eta_max);
   return std::max(1, (int)ceil(c.dt / dt_max));
@@ -248,29 +282,42 @@ static void fill_desc(hyb_run* r) {
   const double I_ex = c.I_ex > 0 ? c.I_ex : 11.0 * kE * c.Z;
   const double a0 = 8.5e-6 * sqrt(c.I0 * c.wavelength * c.wavelength);
   const double cz = cz_of(c.Z);
-  h.n_sub = c.n_sub > 0 ? c.n_sub : n_sub_auto(c, n_i);
+  h.n_sub = c.n_sub > 0 ? c.n_sub : n_sub_auto(c);
   h.e_kick = -kE * c.dt / (2.0 * kMe * kC);
   h.b_rot = -kE * c.dt / (2.0 * kMe);
   h.cdt_dx = kC * c.dt / c.dx;
   const double e4 = kE * kE * kE * kE;
-  h.c_ion = c.Z * n_i * e4 * c.dt / (4.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
-  h.ln_iex = log(I_ex / kMec2);
+  // electron processes sum over the solid's elements: sums of Z n, Z^2 n and
+  // n C_Z, and the logarithms averaged with the weights of their terms
+  const std::vector<Elem> els = elements(c);
+  double zn = 0.0, zn_lnI = 0.0, z2n = 0.0, z2n_lnD = 0.0, ncz = 0.0;
+  for (const Elem& e : els) {
+    zn += e.Z * e.n;
+    zn_lnI += e.Z * e.n * log(e.I / kMec2);
+    z2n += e.Z * e.Z * e.n;
+    z2n_lnD += e.Z * e.Z * e.n * log(4.0 * kEps0 * kH * kC / (pow(e.Z, 1.0 / 3.0) * kE * kE));
+    ncz += e.n * cz_of(e.Z);
+  }
+  const bool single = els.size() == 1;
+  h.c_ion = (single ? c.Z * n_i : zn) * e4 * c.dt / (4.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
+  h.ln_iex = single ? log(I_ex / kMec2) : zn_lnI / zn;
   {  // delta rays: restricted loss prefactor (half of eq. stop_ion's), Moller depth
     const double re = kE * kE / (4.0 * kPi * kEps0 * kMec2);
-    const double hwp = kHbar * sqrt(c.Z * n_i * kE * kE / (kEps0 * kMe));
+    const double hwp = kHbar * sqrt((single ? c.Z * n_i : zn) * kE * kE / (kEps0 * kMe));
+    const double I_eff = single ? I_ex : exp(h.ln_iex) * kMec2;
     h.d_cut = c.delta_cut / kMec2;
     h.c_rst = 0.5 * h.c_ion;
-    h.d_lnI2 = 2.0 * log(I_ex / kMec2);
-    h.d_dens0 = 2.0 * log(hwp / I_ex) - 1.0;
+    h.d_lnI2 = 2.0 * h.ln_iex;
+    h.d_dens0 = 2.0 * log(hwp / I_eff) - 1.0;
     h.d_u2min = exp(-h.d_dens0);
-    h.k_mol = n_i * 2.0 * kPi * re * re * c.Z * kC * c.dt;
+    h.k_mol = (single ? n_i * c.Z : zn) * 2.0 * kPi * re * re * kC * c.dt;
     h.spawn_cap = (c.physics & HYB_PHYS_DELTA) ? c.max_particles : 0;
   }
-  h.k_brem = c.brem_boost * n_i * cz * kC * c.dt;
-  h.k_sub = n_i * cz * kC * c.dt;
+  h.k_brem = c.brem_boost * (single ? n_i * cz : ncz) * kC * c.dt;
+  h.k_sub = (single ? n_i * cz : ncz) * kC * c.dt;
   h.inv_boost = 1.0 / c.brem_boost;
-  h.c_dav = c.Z * c.Z * e4 * n_i * c.dt / (2.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
-  h.l_dav = 4.0 * kEps0 * kH * kC / (pow(c.Z, 1.0 / 3.0) * kE * kE);
+  h.c_dav = (single ? c.Z * c.Z * n_i : z2n) * e4 * c.dt / (2.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
+  h.l_dav = single ? 4.0 * kEps0 * kH * kC / (pow(c.Z, 1.0 / 3.0) * kE * kE) : exp(z2n_lnD / z2n);
   h.eps_esc = c.kappa_esc * a0;
   h.du_tnsa = c.kappa_tnsa * a0;
   h.reflux_ke_mode = c.reflux_ke_frac > 0 ? 1 : 0;
@@ -290,6 +337,7 @@ static void fill_desc(hyb_run* r) {
   h.e_bin_scale = c.tally_nE / log(c.tally_Ehi / c.tally_Elo);
   h.Ethr = c.tally_Ethr / kMec2;
   h.solid = make_solid(c.Z, c.A, c.rho, n_i, c.lambda1, c.lambda2);
+  h.mix = make_mix(c);
   h.eta_fixed = c.eta_fixed;
   h.sort_every = c.sort_every;
   h.ntx = (c.nx + kTile - 1) / kTile;
@@ -492,7 +540,7 @@ static hyb_status create_run(const hyb_config* cfg, const hyb_device* dev, hyb_r
   {
     std::vector<double> T(ncells, c.T0), eta(ncells, 0.0);
     const double e0 = c.eta_fixed > 0 ? c.eta_fixed
-                                      : resistivity(r->h.solid, c.T0, c.T0);
+                                      : resistivity_mix(r->h.mix, c.T0, c.T0);
     for (int k = 0; k < c.nz; ++k)
       for (int j = 0; j < c.ny; ++j)
         for (int i = r->h.ix_lo; i < r->h.ix_hi; ++i) eta[i + (size_t)c.nx * (j + (size_t)c.ny * k)] = e0;

@@ -114,6 +114,18 @@ struct Solid {
   double tc_c;    // electron-ion exchange: 1 / tau = tc_c lnL / (Te m_i + Ti m_e)^1.5
 };
 
+// A compound solid (App. A): its elements, each as if it filled the cell at
+// the total ion density n_t, with the weights of the heating rule and the
+// ion shares.  One element: the plain solid.
+constexpr int kMaxElems = 4;
+struct Mix {
+  int n;                    // elements
+  double ne;                // sum of Z n over the elements (eq. Te_rise)
+  double w[kMaxElems];      // Z n / ne: weights of 1 / C
+  double x[kMaxElems];      // n / n_t: shares of the ion density
+  Solid el[kMaxElems];
+};
+
 // Read-only description of one run (device memory; one per resident run).
 struct RunDesc {
   int nx, ny, nz, ix_lo, ix_hi;
@@ -146,8 +158,9 @@ struct RunDesc {
   double heat_unit;   // J per fixed unit of collisional heat
   double led_unit;    // J per fixed unit of the ledger
   double cnt_unit;    // photons per fixed unit of the number tally
-  // solid (heat update, FP64)
+  // solid (heat update, FP64): the first element, and the compound
   Solid solid;
+  Mix mix;
   double eta_fixed;
   // delta rays (m c^2 units)
   double d_cut;       // cut

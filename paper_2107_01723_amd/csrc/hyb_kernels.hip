@@ -1521,8 +1521,9 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const double jy = (double)(Jy[n] + Jy[n + 1] + Jy[n + sxy] + Jy[n + 1 + sxy]) * ju;
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
     double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = G(R.eta)[c], fs = 1.0;
-    heat_cell(sol, Te, Ti, eta, jx * jx + jy * jy + jz * jz, (double)G(R.ion_heat)[c] * R.heat_unit, R.dt, dV,
-              fixed, want_fs ? &fs : nullptr);
+    const double j2 = jx * jx + jy * jy + jz * jz, qh = (double)G(R.ion_heat)[c] * R.heat_unit;
+    if (R.mix.n == 1) heat_cell(sol, Te, Ti, eta, j2, qh, R.dt, dV, fixed, want_fs ? &fs : nullptr);
+    else heat_cell_mix(R.mix, Te, Ti, eta, j2, qh, R.dt, dV, fixed);
     if (want_fs) {
       if (R.precision == 0) G((double*)R.fsig)[c] = fs;
       else G((float*)R.fsig)[c] = (float)fs;

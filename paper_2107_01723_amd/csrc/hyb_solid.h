@@ -124,4 +124,54 @@ __host__ __device__ inline void heat_cell(const Solid& s, double& Te, double& Ti
   if (fs) *fs = f_sigma(s, Ti2, Zs2);
 }
 
+// Compound resistivity: sum(x Z* eta_el) / sum(x Z*), each element's
+// Lee-More resistivity as if it filled the cell at the total ion density
+// (the free electrons' collision rates add over the ion species).
+__host__ __device__ inline double resistivity_mix(const Mix& m, double Te, double Ti) {
+  if (m.n == 1) return resistivity(m.el[0], Te, Ti);
+  double num = 0.0, den = 0.0;
+  for (int k = 0; k < m.n; ++k) {
+    const double Zs = zstar(m.el[k], Te);
+    num += m.x[k] * Zs * resistivity_z(m.el[k], Te, Ti, Zs);
+    den += m.x[k] * Zs;
+  }
+  return num / den;
+}
+
+// One cell of a compound (App. A): heating with n_e summed over the
+// elements and 1/C averaged with weights Z n; electron-ion exchange with the
+// elements' rates added by ion share, the ions' rate scaled by the mean Z*
+// (energy conservation between free electrons and ions); the compound
+// resistivity.  One element: heat_cell.
+__host__ __device__ inline void heat_cell_mix(const Mix& m, double& Te, double& Ti, double& eta, double j2,
+                                              double ion_heat_J, double dt, double dV, bool fixed_eta,
+                                              double* fs = nullptr) {
+  if (m.n == 1) {
+    heat_cell(m.el[0], Te, Ti, eta, j2, ion_heat_J, dt, dV, fixed_eta, fs);
+    return;
+  }
+  const double rho_eps = eta * j2 * dt + ion_heat_J / dV;
+  double inv_c = 0.0;
+  for (int k = 0; k < m.n; ++k) inv_c += m.w[k] / heat_capacity(m.el[k], Te);
+  const double Te1 = Te + rho_eps * inv_c / (m.ne * kKb);
+  const double e4 = kE * kE * kE * kE;
+  double a = 0.0, zbar = 0.0;
+  for (int k = 0; k < m.n; ++k) {
+    const Solid& s = m.el[k];
+    const double Zs = zstar(s, Te1);
+    const double lnL = coulomb_log(s, Te1, Ti, Zs);
+    const double denom = Te1 * s.m_i + Ti * kMe;
+    const double inv_tc = s.tc_c * lnL / (denom * sqrt(denom));
+    a += m.x[k] * Zs * Zs * e4 * s.n_i * inv_tc;
+    zbar += m.x[k] * Zs;
+  }
+  const double b = a * zbar;
+  const double sum = a + b;
+  const double M = (b * Te1 + a * Ti) / sum;
+  const double D = (Te1 - Ti) * exp(-sum * dt);
+  Te = M + a / sum * D;
+  Ti = M - b / sum * D;
+  if (!fixed_eta) eta = resistivity_mix(m, Te, Ti);
+}
+
 }  // namespace hyb

@@ -69,6 +69,8 @@ class Config(C.Structure):
         ("sort_every", C.c_int32),
         ("delta_cut", C.c_double),
         ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("bc_z", C.c_int32),
+        ("n_extra", C.c_int32), ("extra_Z", C.c_double * 3), ("extra_A", C.c_double * 3),
+        ("extra_rho", C.c_double * 3), ("extra_I_ex", C.c_double * 3),
     ]
 
 
@@ -209,13 +211,18 @@ def check_abi():
 
 
 # config keys a dictionary may leave out, with their defaults
-CONFIG_DEFAULTS = {"delta_cut": 1e3 * 1.602176634e-19, "bc_x": 0, "bc_y": 0, "bc_z": 0}
+CONFIG_DEFAULTS = {"delta_cut": 1e3 * 1.602176634e-19, "bc_x": 0, "bc_y": 0, "bc_z": 0, "n_extra": 0,
+                   "extra_Z": (0.0, 0.0, 0.0), "extra_A": (0.0, 0.0, 0.0), "extra_rho": (0.0, 0.0, 0.0),
+                   "extra_I_ex": (0.0, 0.0, 0.0)}
 
 
 def make_config(d: dict) -> Config:
     c = Config()
-    for name, _ in Config._fields_:
-        setattr(c, name, d[name] if name in d else CONFIG_DEFAULTS[name])
+    for name, typ in Config._fields_:
+        v = d[name] if name in d else CONFIG_DEFAULTS[name]
+        if issubclass(typ, C.Array):
+            v = typ(*[float(x) for x in v])
+        setattr(c, name, v)
     return c
 
 

@@ -526,3 +526,72 @@ def test_checkpoint_resume(P, precision, tol):
     for k in ("p", "pos", "tau", "tau_d", "w"):
         assert err[k].max() < tol, (k, err[k].max())
     assert rel(got["Te"], ref["Te"]) < tol
+
+
+def _plastic_cfg(precision, **over):
+    cfg, srcs, _ = small_config(6000, precision=precision, brem_boost=10.0, **W.plastic(), **over)
+    return cfg, srcs
+
+
+def test_compound_plastic_whole_run_fp64(P):
+    """A CH plastic slab (App. A compound of carbon and hydrogen), 40 steps
+    with collisions, delta rays and heating, field feedback off: every
+    electron, the temperatures and resistivity of every cell, the ledger."""
+    cfg, srcs = _plastic_cfg(W.FP64, physics=(W.PHYS_ALL & ~W.PHYS_FIELDS) | W.PHYS_DELTA,
+                             max_particles=60000)
+    ora = oracle_at(cfg, srcs, 40)
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(40)
+    got, ref = run.get_state(), ora.state()
+    err, only = particle_errors(got, ref, cfg["dx"])
+    print(f"  alive {len(err['ids'])}, max|dp| {err['p'].max():.2e}, delta rays {ora.counters['n_delta']}",
+          flush=True)
+    assert not only
+    for k in ("p", "pos", "tau", "tau_d"):
+        assert err[k].max() < 1e-10, k
+    s = ora.solid
+    assert ref["Te"][s].max() > 1.5 * cfg["T0"]
+    for k in ("Te", "Ti", "eta"):
+        assert rel(got[k][s], ref[k][s]) < 1e-10, k
+    t = run.tally()
+    for k in ("injected", "ionisation", "rad_discrete", "reflux", "stopped", "escaped"):
+        assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-8, abs=1e-12 * ora.ledger["injected"]), k
+    run.close()
+
+
+def test_compound_plastic_one_step_fields_on(P):
+    """The CH slab with every process and the field feedback on: one step
+    from an identical state at step 30 -- electrons, E, B, Te, eta."""
+    cfg, srcs = _plastic_cfg(W.FP64, max_particles=20000)
+    ora = oracle_at(cfg, srcs, 30)
+    run = gpu_from_oracle(P, cfg, srcs, ora)
+    ora.step()
+    run.step(1)
+    got, ref = run.get_state(), ora.state()
+    err, only = particle_errors(got, ref, cfg["dx"])
+    assert not only
+    assert err["p"].max() < 1e-10 and err["pos"].max() < 1e-10
+    assert field_rel(got["E"], ref["E"]) < 1e-9 and field_rel(got["B"], ref["B"]) < 1e-9
+    s = ora.solid
+    assert rel(got["Te"][s], ref["Te"][s]) < 1e-10 and rel(got["eta"][s], ref["eta"][s]) < 1e-10
+    run.close()
+
+
+def test_compound_halves_equal_the_material_on_gpu(P):
+    """On the GPU too, gold as two half-density solids steps like gold (the
+    compound heat path against the single-element one), FP64 30 steps."""
+    base = dict(physics=W.PHYS_ALL & ~W.PHYS_FIELDS, max_particles=20000)
+    cfg_a, srcs, _ = small_config(3000, brem_boost=10.0, **base)
+    cfg_b = dict(cfg_a, rho=cfg_a["rho"] / 2, n_extra=1, extra_Z=(79.0, 0.0, 0.0),
+                 extra_A=(cfg_a["A"], 0.0, 0.0), extra_rho=(cfg_a["rho"] / 2, 0.0, 0.0))
+    out = []
+    for cfg in (cfg_a, cfg_b):
+        run = P.Run(cfg)
+        run.inject(srcs[0])
+        run.step(30)
+        out.append(run.get_state())
+        run.close()
+    err, only = particle_errors(out[1], out[0], cfg_a["dx"])
+    assert not only and err["p"].max() < 1e-11
+    assert rel(out[1]["Te"], out[0]["Te"]) < 1e-11 and rel(out[1]["eta"], out[0]["eta"]) < 1e-11

@@ -88,9 +88,13 @@ def base_config(**over) -> dict:
         n_sub=0,                      # 0 -> automatic from the stability scan
         sort_every=0,
         bc_x=BC_REFLUX, bc_y=BC_REFLUX, bc_z=BC_REFLUX,
+        # further elements mixed into the slab (App. A compounds): Z, molar
+        # mass [g/mol], partial mass density [kg/m^3], I_ex [J] (0 -> 11 eV Z)
+        n_extra=0, extra_Z=(0.0, 0.0, 0.0), extra_A=(0.0, 0.0, 0.0), extra_rho=(0.0, 0.0, 0.0),
+        extra_I_ex=(0.0, 0.0, 0.0),
     )
     for k, v in over.items():
-        if k not in cfg:
+        if k not in cfg and k not in ("Z", "A", "rho"):
             raise KeyError(f"unknown config key {k}")
         cfg[k] = v
     mat = MATERIALS[cfg["material"]]
@@ -175,6 +179,19 @@ def config_huge() -> tuple[dict, list[dict], int]:
                  z0=128e-6, r_fwhm=2e-6, T_hot=10.8 * MEV,
                  half_angle=math.radians(30.0))
     return cfg, [src], 10000
+
+
+def plastic(**over) -> dict:
+    """A CH plastic slab (polystyrene-like, 1.05 g/cm^3, C:H = 1:1) as a
+    compound of carbon (the first element) and hydrogen: the config keys of
+    base_config for it."""
+    n = 1050.0 / ((12.011 + 1.008) * 1.66053906660e-27)     # CH units per m^3
+    rho_c = n * 12.011 * 1.66053906660e-27
+    rho_h = n * 1.008 * 1.66053906660e-27
+    cfg = dict(material="Au", Z=6.0, A=12.011, rho=rho_c, n_extra=1, extra_Z=(1.0, 0.0, 0.0),
+               extra_A=(1.008, 0.0, 0.0), extra_rho=(rho_h, 0.0, 0.0), extra_I_ex=(0.0, 0.0, 0.0))
+    cfg.update(over)
+    return cfg
 
 
 def beam(**over) -> dict:
