@@ -19,8 +19,8 @@ summary was taken on other kernel sources.
 
 `--opt-in` also times the same FP64 workload with each opt-in process of
 the paper switched on (delta rays with the restricted loss; the eq. F_sigma
-enhancement) and reports them under `opt_in`; the headline numbers are those
-of the default physics.
+enhancement; the Urban-type elastic scatter in place of Davies) and reports
+them under `opt_in`; the headline numbers are those of the default physics.
 """
 from __future__ import annotations
 
@@ -191,7 +191,8 @@ def main():
               file=sys.stderr, flush=True)
     opt_in = {}
     if a.opt_in:
-        for name, bit, extra in (("delta_rays", W.PHYS_DELTA, 1.5), ("f_sigma", W.PHYS_FSIGMA, 1.0)):
+        for name, bit, extra in (("delta_rays", W.PHYS_DELTA, 1.5), ("f_sigma", W.PHYS_FSIGMA, 1.0),
+                                 ("urban_scatter", W.PHYS_URBAN, 1.0)):
             c = dict(cfg, physics=cfg["physics"] | bit, max_particles=int(cfg["max_particles"] * extra))
             r = time_run(P, c, srcs, a.steps, a.warmup, "fp64_" + name)
             opt_in[name] = {"value": round(r["particle_steps_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),

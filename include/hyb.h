@@ -78,7 +78,20 @@ enum {
    * (4x4x4-cell tile of the birth cell, x fastest; parent id); a delta ray
    * below e_min stops at once (ledger term STOPPED, the cell's heat).  Only
    * with HYB_PHYS_ION; not part of HYB_PHYS_ALL. */
-  HYB_PHYS_DELTA = 1 << 8
+  HYB_PHYS_DELTA = 1 << 8,
+  /* the paper's other elastic model (App. B, Urban's approach) in place of
+   * the Davies scatter: the polar angle of a step is drawn from model
+   * functions whose first two Legendre moments are those of Lewis theory,
+   * exp(-v dt / lambda_1) and exp(-v dt / lambda_2), no displacement within
+   * the step.  The transport mean free paths come from the screened
+   * Rutherford cross-section (nucleus and atomic electrons, Z (Z + 1)) with
+   * Moliere's screening angle, summed over the solid's elements; the model
+   * function is a core a exp(-a (1 - cos theta)) plus an isotropic part of
+   * weight w_i, (a, w_i) fixed by the two moments (w_i = 0 and the first
+   * moment alone where the pair needs w_i < 0).  Same draws as the Davies
+   * scatter (part, polar angle, azimuth).  Only with HYB_PHYS_SCATTER; not
+   * part of HYB_PHYS_ALL. */
+  HYB_PHYS_URBAN = 1 << 9
 };
 
 /* Boundary kind of each axis (hyb_config.bc_x, bc_y, bc_z); the x faces are

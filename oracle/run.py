@@ -17,7 +17,8 @@ the reading both implementations follow):
      emission per step, boosted cross-section (Sec. II.B); sub-cut loss;
      optionally both enhanced by eq. F_sigma of the cell at x^n, from the
      temperatures at the start of the step
-  7. Davies elastic scatter (App. B)
+  7. elastic scatter (App. B): Davies, or Urban-type model functions
+     matched to the Lewis moments
   8. boundaries x, y, z: escape or reflux (Sec. II.A); per axis also open
      (every electron leaving escapes) or a lossless mirror
   9. removal below e_min, remaining energy -> the cell's heat
@@ -42,6 +43,7 @@ from . import particles as PT
 from . import philox as P
 from . import solid as S
 from . import tables as T
+from . import urban as U
 
 PHYS_FIELDS = 1 << 0
 PHYS_ION = 1 << 1
@@ -52,6 +54,7 @@ PHYS_EVOLVE_B = 1 << 5
 PHYS_HEAT = 1 << 6
 PHYS_FSIGMA = 1 << 7
 PHYS_DELTA = 1 << 8
+PHYS_URBAN = 1 << 9
 BC_REFLUX, BC_OPEN, BC_MIRROR = 0, 1, 2
 DELTA_ID_BIT = 0x80000000    # delta rays take ids DELTA_ID_BIT + 0, 1, ...
 
@@ -78,6 +81,8 @@ class OracleRun:
             Zk = float(c["extra_Z"][k])
             Ik = c["extra_I_ex"][k] if c["extra_I_ex"][k] > 0 else 11.0 * K.E * Zk
             self.elems.append(dict(S.element(Zk, c["extra_A"][k], c["extra_rho"][k]), I_ex=Ik))
+        if int(c["physics"]) & PHYS_URBAN and not int(c["physics"]) & PHYS_SCATTER:
+            raise ValueError("the Urban-type model replaces the Davies scatter: set PHYS_SCATTER too")
         if len(self.elems) > 1 and int(c["physics"]) & PHYS_FSIGMA:
             raise ValueError("eq. F_sigma is defined for single-element solids")
         self.a0 = PT.a0_of(c["I0"], c["wavelength"])
@@ -377,14 +382,18 @@ class OracleRun:
         else:
             eps3 = eps2
 
-        # Davies elastic scatter
+        # elastic scatter: Davies, or the Urban-type model functions
         if phys & PHYS_SCATTER:
             pm = np.sqrt(np.sum(p * p, axis=-1))
             moving = pm > 0.0
             if np.any(moving):
-                s2 = PT.davies_sigma2_mix(p[moving], self.elems, dt)
-                dth = PT.box_muller(u_c[0][moving], u_c[1][moving]) * np.sqrt(s2)
-                p[moving] = PT.rotate(p[moving], dth, 2.0 * math.pi * u_c[2][moving])
+                if phys & PHYS_URBAN:
+                    p[moving] = U.scatter(p[moving], self.elems, dt, u_c[0][moving], u_c[1][moving],
+                                          u_c[2][moving])
+                else:
+                    s2 = PT.davies_sigma2_mix(p[moving], self.elems, dt)
+                    dth = PT.box_muller(u_c[0][moving], u_c[1][moving]) * np.sqrt(s2)
+                    p[moving] = PT.rotate(p[moving], dth, 2.0 * math.pi * u_c[2][moving])
                 # elastic: a change of the kinetic energy is rounding, booked apart
                 e_r = PT.kinetic(p)
                 L["residual"] += float(np.sum(w * (eps3 - e_r)))

@@ -198,7 +198,9 @@ static std::string validate(const hyb_config& c) {
   if (c.tally_nE < 1 || c.tally_ntheta < 1 || !(c.tally_Ehi > c.tally_Elo) || !(c.tally_Elo > 0)) return "bad tally bins";
   if (c.series_len < 0) return "series_len must be >= 0";
   if (c.max_particles < 1 || c.max_particles > 2000000000LL) return "max_particles out of range";
-  if ((c.physics & ~0x1FFu) != 0) return "unknown physics bits";
+  if ((c.physics & ~0x3FFu) != 0) return "unknown physics bits";
+  if ((c.physics & HYB_PHYS_URBAN) && !(c.physics & HYB_PHYS_SCATTER))
+    return "the Urban-type scatter replaces the Davies scatter: set HYB_PHYS_SCATTER too";
   if (c.physics & HYB_PHYS_DELTA) {
     if (!(c.physics & HYB_PHYS_ION)) return "delta rays need HYB_PHYS_ION";
     if (!(c.delta_cut > 0)) return "delta_cut must be positive";
@@ -318,6 +320,19 @@ static void fill_desc(hyb_run* r) {
   h.inv_boost = 1.0 / c.brem_boost;
   h.c_dav = (single ? c.Z * c.Z * n_i : z2n) * e4 * c.dt / (2.0 * kPi * kEps0 * kEps0 * kMe * kMe * kC * kC * kC);
   h.l_dav = single ? 4.0 * kEps0 * kH * kC / (pow(c.Z, 1.0 / 3.0) * kE * kE) : exp(z2n_lnD / z2n);
+  {  // Urban-type scatter: per element 2 pi Z (Z + 1) n r_e^2 c dt and Moliere's
+     // screening A = 1.13 (alpha Z^1/3 / (2 0.88534 u))^2 (1 + 3.76 (alpha Z)^2 / (1.13 beta^2))
+    const double re = kE * kE / (4.0 * kPi * kEps0 * kMec2);
+    const double alpha = kE * kE / (4.0 * kPi * kEps0 * kHbar * kC);
+    h.u_n = (int)els.size();
+    for (int j = 0; j < h.u_n; ++j) {
+      const double Z = els[j].Z;
+      const double t = alpha * cbrt(Z) / (2.0 * 0.88534);
+      h.u_k1[j] = 2.0 * kPi * Z * (Z + 1.0) * els[j].n * re * re * kC * c.dt;
+      h.u_ca[j] = 1.13 * t * t;
+      h.u_cb[j] = 3.76 * alpha * alpha * Z * Z / 1.13;
+    }
+  }
   h.eps_esc = c.kappa_esc * a0;
   h.du_tnsa = c.kappa_tnsa * a0;
   h.reflux_ke_mode = c.reflux_ke_frac > 0 ? 1 : 0;
@@ -738,6 +753,7 @@ static hyb_status ensure_single_plans(hyb_run* r) {
   r->L.nruns = 1;
   r->L.sort = r->h.sort_every > 0;
   r->L.delta = (r->h.physics & PHYS_DELTA) != 0;
+  r->L.urban = (r->h.physics & PHYS_URBAN) != 0;
   return upload_plans(r, r->stream, ps, r->L, &r->d_maps, &r->maps_bytes, r->dev);
 }
 
@@ -1249,6 +1265,7 @@ static hyb_status eng_rebuild(hyb_engine* e, int p) {
   for (int s = 0; s < e->max_runs; ++s) {
     if (e->slots[p][s] && e->slots[p][s]->h.sort_every > 0) e->L[p].sort = true;
     if (e->slots[p][s] && (e->slots[p][s]->h.physics & PHYS_DELTA)) e->L[p].delta = true;
+    if (e->slots[p][s] && (e->slots[p][s]->h.physics & PHYS_URBAN)) e->L[p].urban = true;
   }
   hyb_run tmp;
   hyb_status st = upload_plans(&tmp, e->stream, ps, e->L[p], &e->d_maps[p], &e->maps_bytes[p], e->dev);

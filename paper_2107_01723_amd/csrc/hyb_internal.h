@@ -40,7 +40,7 @@ enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_DELTA, C_DEL
 enum : uint32_t {
   PHYS_FIELDS = 1u << 0, PHYS_ION = 1u << 1, PHYS_BREM = 1u << 2, PHYS_SCATTER = 1u << 3,
   PHYS_EVOLVE_E = 1u << 4, PHYS_EVOLVE_B = 1u << 5, PHYS_HEAT = 1u << 6, PHYS_FSIGMA = 1u << 7,
-  PHYS_DELTA = 1u << 8
+  PHYS_DELTA = 1u << 8, PHYS_URBAN = 1u << 9
 };
 
 // delta rays: ids DELTA_ID_BIT + n; candidates of the energy sampler
@@ -141,6 +141,10 @@ struct RunDesc {
   double c_ion, ln_iex;
   double k_brem, k_sub, inv_boost;
   double c_dav, l_dav;
+  // Urban-type scatter, per element: v dt / lambda_1 = sum k1 B1(A) / (u^2 beta),
+  // A = ca (1 + cb / beta^2) / u^2 (Moliere), u = p / (m c)
+  int u_n;
+  double u_k1[kMaxElems], u_ca[kMaxElems], u_cb[kMaxElems];
   // boundaries
   double eps_esc, du_tnsa, keep_frac, sigma_dth, e_min;
   int reflux_ke_mode;
@@ -340,12 +344,12 @@ __device__ __forceinline__ T kinetic(T u2, T g) { return u2 / ((T)1 + g); }
 template <typename T>
 __device__ __forceinline__ T umag_of(T e) { return m_sqrt(e * (e + (T)2)); }
 
-// Turn direction of (ux,uy,uz) by dth at azimuth phi = 2 pi t, keeping |u|.
-// Basis: a = unit(uhat x e_m), e_m the axis of the smallest |uhat_i| (ties ->
-// lowest index), b = uhat x a; uhat' = cos dth uhat + sin dth (cos phi a +
-// sin phi b).
+// Turn direction of (ux,uy,uz) by the polar angle of cosine c and sine s at
+// azimuth phi = 2 pi t, keeping |u|.  Basis: a = unit(uhat x e_m), e_m the
+// axis of the smallest |uhat_i| (ties -> lowest index), b = uhat x a;
+// uhat' = c uhat + s (cos phi a + sin phi b).
 template <typename T>
-__device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T t) {
+__device__ __forceinline__ void rotate_cs(T& ux, T& uy, T& uz, T c, T s, T t) {
   const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
   const T inv = (T)1 / um;
   const T hx = ux * inv, hy = uy * inv, hz = uz * inv;
@@ -357,14 +361,21 @@ __device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T t) {
   const T an = (T)1 / m_sqrt(ax * ax + ay * ay + az * az);
   ax *= an; ay *= an; az *= an;
   const T bx = hy * az - hz * ay, by = hz * ax - hx * az, bz = hx * ay - hy * ax;
-  T c, s, cp, sp;
-  m_sincos(dth, s, c);
+  T cp, sp;
   m_sincos2pi(t, sp, cp);
   T dx = c * hx + s * (cp * ax + sp * bx);
   T dy = c * hy + s * (cp * ay + sp * by);
   T dz = c * hz + s * (cp * az + sp * bz);
   const T dn = um / m_sqrt(dx * dx + dy * dy + dz * dz);
   ux = dx * dn; uy = dy * dn; uz = dz * dn;
+}
+
+// The same turn by the polar angle dth.
+template <typename T>
+__device__ __forceinline__ void rotate(T& ux, T& uy, T& uz, T dth, T t) {
+  T c, s;
+  m_sincos(dth, s, c);
+  rotate_cs(ux, uy, uz, c, s, t);
 }
 
 // ---- bremsstrahlung table lookups ------------------------------------------

@@ -25,6 +25,7 @@ struct LaunchSet {
   Plan scan, scan1;   // tile-count scan: one block per kScanTile tiles; one block per run
   bool sort = false;                                  // some run sorts its particles
   bool delta = false;                                 // some run has delta rays
+  bool urban = false;                                 // some run has the Urban-type scatter
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
 };
 

@@ -606,18 +606,134 @@ __device__ __forceinline__ T moller_g(T x, T a, T b) {
 }
 
 // ---------------------------------------------------------------------------
+// Urban-type elastic scatter (App. B): model functions of the polar angle
+// whose first two Legendre moments are Lewis theory's
+// ---------------------------------------------------------------------------
+// L(a) = coth a - 1/a, C = 1 - L, S = L - a/3 and dL/da, in double: below
+// 1/2 the Taylor series sum 2^2n B_2n a^(2n-1) / (2n)! (twelve terms), above
+// C = 1/a - 2 / (e^2a - 1) (no cancellation as C -> 0).
+__device__ __forceinline__ void langevin_d(double a, double& L, double& C, double& S, double& dL) {
+  if (a < 0.5) {
+    const double q = a * a;
+    // coefficients of a^3, a^5, ..., a^23
+    const double c2 = -1.0 / 45.0, c3 = 2.0 / 945.0, c4 = -1.0 / 4725.0, c5 = 2.0 / 93555.0,
+                 c6 = -1382.0 / 638512875.0, c7 = 4.0 / 18243225.0, c8 = -3617.0 / 162820783125.0,
+                 c9 = 87734.0 / 38979295480125.0, c10 = -349222.0 / 1531329465290625.0,
+                 c11 = 310732.0 / 13447856940643125.0, c12 = -472728182.0 / 201919571963756521875.0;
+    const double p = c2 + q * (c3 + q * (c4 + q * (c5 + q * (c6 + q * (c7 + q * (c8 + q * (c9 +
+                     q * (c10 + q * (c11 + q * c12)))))))));
+    S = a * q * p;
+    L = a * (1.0 / 3.0) + S;
+    C = 1.0 - L;
+    dL = 1.0 / 3.0 + q * (3 * c2 + q * (5 * c3 + q * (7 * c4 + q * (9 * c5 + q * (11 * c6 +
+         q * (13 * c7 + q * (15 * c8 + q * (17 * c9 + q * (19 * c10 + q * (21 * c11 + q * 23 * c12))))))))));
+  } else {
+    const double e = expm1(2.0 * a);   // inf above a ~ 354: 2 / e -> 0
+    C = 1.0 / a - 2.0 / e;
+    L = 1.0 - C;
+    S = L - a * (1.0 / 3.0);
+    // 1 / sinh^2 a = 4 (e + 1) / e^2, negligible against 1/a^2 far out
+    dL = a < 40.0 ? 1.0 / (a * a) - 4.0 * (e + 1.0) / (e * e) : 1.0 / (a * a);
+  }
+}
+
+// Root in t = ln a of a residual that decreases in a, from t: Newton steps
+// kept inside the bracket, bisection where a step leaves it.  f(t, F, dF/dt).
+template <class Fn>
+__device__ __forceinline__ double urban_solve(Fn f, double t) {
+  double lo = -41.0, hi = 41.0;
+  t = t > lo ? (t < hi ? t : hi) : lo;
+#pragma unroll 1
+  for (int it = 0; it < 100; ++it) {
+    double F, dF;
+    f(t, F, dF);
+    if (F == 0.0) break;
+    if (F > 0.0) lo = t; else hi = t;
+    double tn = t - F / dF;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    const double step = fabs(tn - t);
+    t = tn;
+    if (step < 1e-15 * (fabs(t) > 1.0 ? fabs(t) : 1.0) || hi - lo < 1e-15) break;
+  }
+  return t;
+}
+
+// 1 - cos theta of one step's deflection of an electron of u^2 = (p/(m c))^2:
+// x_l = v dt / lambda_l summed over the elements from the screened Rutherford
+// law, sigma_1 = 8 pi k (ln(1 + 1/A) - 1/(1 + A)), sigma_2 = 24 pi k ((1 + 2A)
+// ln(1 + 1/A) - 2); the model function (1 - w_i) a e^(-a (1 - cos)) / (1 -
+// e^(-2a)) + w_i / 2 with 1/L(a) - 3/a = exp(x_1 - x_2) and w_i = 1 -
+// exp(-x_1) / L(a), or, where that w_i < 0, w_i = 0 and L(a) = exp(-x_1).
+// Quantities near 1 are carried as their distance from 1.
+// ua < w_i picks the isotropic part; ub gives the angle by the part's inverse CDF.
+__device__ __forceinline__ double urban_one_minus_cos(const RunDesc& R, double u2, double ua, double ub) {
+  const double b2 = u2 / (1.0 + u2);
+  double x1 = 0.0, x2 = 0.0;
+#pragma unroll 1
+  for (int j = 0; j < R.u_n; ++j) {
+    const double A = R.u_ca[j] * (1.0 + R.u_cb[j] / b2) / u2;
+    const double lg = log1p(1.0 / A);
+    x1 += R.u_k1[j] * (lg - 1.0 / (1.0 + A));
+    x2 += R.u_k1[j] * ((1.0 + 2.0 * A) * lg - 2.0);
+  }
+  const double iv = 1.0 / (u2 * sqrt(b2));
+  x1 *= iv;
+  x2 *= 3.0 * iv;
+  const double d = x2 - x1;
+  const double r = exp(-d), rho = -expm1(-d);
+  // psi(a) = 1 - (1/L - 3/a) against rho = 1 - r: large a as 3/a - c/(1 - c),
+  // c = 1 - L; small a as r - (1/L - 3/a) with 1/L - 3/a = -3 S / (a L)
+  auto moments = [&](double t, double& F, double& dF) {
+    const double a = exp(t);
+    double L, C, S, dL;
+    langevin_d(a, L, C, S, dL);
+    F = a < 0.5 ? r + 3.0 * S / (a * L) : 3.0 / a - C / L - rho;
+    dF = a * dL / (L * L) - 3.0 / a;
+  };
+  double t0;
+  if (rho < 0.5) {   // a > ~3: psi = e (2 - 3e) / (1 - e), e = 1/a, exact above a ~ 20
+    const double q = 2.0 + rho, disc = q * q - 12.0 * rho;
+    t0 = -log(2.0 * rho / (q + sqrt(disc > 0.0 ? disc : 0.0)));
+  } else {           // small a: 1/L - 3/a ~ a/5
+    t0 = log(5.0 * r);
+  }
+  double a = exp(urban_solve(moments, t0));
+  double L, C, S, dL;
+  langevin_d(a, L, C, S, dL);
+  const double om = -expm1(-x1);   // 1 - exp(-x1)
+  double wi = (om - C) / L;        // 1 - exp(-x1) / L
+  if (wi < 0.0) {    // the first moment alone: 1 - L(a) = 1 - exp(-x1)
+    auto first = [&](double t, double& F, double& dF) {
+      const double aa = exp(t);
+      double L1, C1, S1, dL1;
+      langevin_d(aa, L1, C1, S1, dL1);
+      F = C1 - om;
+      dF = -aa * dL1;
+    };
+    a = exp(urban_solve(first, om < 0.5 ? -log(om) : log(3.0 * (1.0 - om))));
+    wi = 0.0;
+  }
+  if (ua < wi) return 2.0 * (1.0 - ub);
+  return -log1p(-(1.0 - ub) * -expm1(-2.0 * a)) / a;
+}
+
+// ---------------------------------------------------------------------------
 // the particle step: gather, Boris, deposit, move, ionisation,
-// bremsstrahlung, Davies scatter, boundaries, low-energy removal
+// bremsstrahlung, elastic scatter, boundaries, low-energy removal
 // ---------------------------------------------------------------------------
 // Waves per SIMD the register allocation of the particle kernel is held to.
 // The kernel is latency bound (dependent HBM round trips per chunk), so
 // occupancy pays for a few spills: 2 in FP64 (256 registers), 4 in FP32.
 template <typename T> struct PartOcc { static constexpr int waves = 2; };
 template <> struct PartOcc<float> { static constexpr int waves = 4; };
-// D: the variant with delta rays (own optical depth, spawning).
-template <typename T, bool D>
+// Variants (V, bits): delta rays (own optical depth, spawning); the
+// Urban-type scatter.  Each adds registers that the plain step need not hold.
+enum : int { kVarDelta = 1, kVarUrban = 2 };
+template <typename T, int V>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<T>::waves))) void k_particle(const RunDesc* __restrict__ runs,
                                                      const BlockMap* __restrict__ bmap) {
+  constexpr bool D = (V & kVarDelta) != 0;
+  constexpr bool UR = (V & kVarUrban) != 0;
   const BlockMap bm = bmap[blockIdx.x];
   if (bm.nb < 8) return;   // alignment padding between runs
   const RunDesc& R = runs[bm.run];
@@ -1000,16 +1116,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         acc[L_RESIDUAL] += to_fixed((eps2 - eps3 - kb - sub_a) * wn * ledS);
       }
 
-      // --- Davies elastic scatter ---
+      // --- elastic scatter: Davies, or the Urban-type model functions ---
       if ((phys & PHYS_SCATTER) && u2 > (T)0) {
-        const T um = m_sqrt(u2);
-        T lg = m_log((T)R.l_dav * um);
-        lg = lg > (T)0 ? lg : (T)0;
-        const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
-        T sb, cb;
-        m_sincos2pi(cd.b, sb, cb);
-        const T gam = m_sqrt((T)-2 * m_log(cd.a)) * cb;
-        rotate(ux, uy, uz, gam * m_sqrt(s2), cd.c);
+        if (UR && (phys & PHYS_URBAN)) {
+          const double w = urban_one_minus_cos(R, (double)u2, (double)cd.a, (double)cd.b);
+          rotate_cs(ux, uy, uz, (T)(1.0 - w), (T)sqrt(w * (2.0 - w)), cd.c);
+        } else {
+          const T um = m_sqrt(u2);
+          T lg = m_log((T)R.l_dav * um);
+          lg = lg > (T)0 ? lg : (T)0;
+          const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
+          T sb, cb;
+          m_sincos2pi(cd.b, sb, cb);
+          const T gam = m_sqrt((T)-2 * m_log(cd.a)) * cb;
+          rotate(ux, uy, uz, gam * m_sqrt(s2), cd.c);
+        }
         // elastic: any change of the stored energy is rounding, booked apart
         u2 = ux * ux + uy * uy + uz * uz;
         g = m_sqrt((T)1 + u2);
@@ -1649,8 +1770,18 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
   hipLaunchKernelGGL(k_zero_step, dim3(L.zero.nb), dim3(kBlock), 0, s, L.runs, L.zero.map);
   hipLaunchKernelGGL(k_inject<T>, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
   if (L.ev_start) (void)hipEventRecord(L.ev_start, s);
-  if (L.delta) hipLaunchKernelGGL((k_particle<T, true>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
-  else hipLaunchKernelGGL((k_particle<T, false>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+  switch ((L.delta ? kVarDelta : 0) | (L.urban ? kVarUrban : 0)) {
+    case 0: hipLaunchKernelGGL((k_particle<T, 0>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map); break;
+    case kVarDelta:
+      hipLaunchKernelGGL((k_particle<T, kVarDelta>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+      break;
+    case kVarUrban:
+      hipLaunchKernelGGL((k_particle<T, kVarUrban>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
+      break;
+    default:
+      hipLaunchKernelGGL((k_particle<T, kVarDelta | kVarUrban>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs,
+                         L.particle.map);
+  }
   if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
   if (L.sort) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);

@@ -23,6 +23,7 @@ LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
 COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped", "n_delta",
                 "n_delta_lost")
 PHYS_DELTA = 1 << 8
+PHYS_URBAN = 1 << 9
 DELTA_ID_BIT = 0x80000000
 
 ABI_FUNCTIONS = (

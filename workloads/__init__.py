@@ -41,6 +41,7 @@ PHYS_EVOLVE_B = 1 << 5    # advance B with Faraday's law
 PHYS_HEAT = 1 << 6        # temperature and resistivity update
 PHYS_FSIGMA = 1 << 7       # eq. F_sigma enhancement of the brem cross-sections (opt-in)
 PHYS_DELTA = 1 << 8        # delta rays + restricted ionisation loss (opt-in)
+PHYS_URBAN = 1 << 9        # Urban-type elastic scatter instead of Davies (opt-in, with PHYS_SCATTER)
 PHYS_ALL = (PHYS_FIELDS | PHYS_ION | PHYS_BREM | PHYS_SCATTER |
             PHYS_EVOLVE_E | PHYS_EVOLVE_B | PHYS_HEAT)
 
@@ -206,7 +207,7 @@ def beam(**over) -> dict:
     return b
 
 
-def config_depth_dose() -> tuple[dict, dict, int]:
+def config_depth_dose(urban: bool = False) -> tuple[dict, dict, int]:
     """The paper's depth-dose benchmark setup (App. C): 0.5 MeV electrons at
     normal incidence on tantalum, 256 x 8 x 8 cells over 150 um in x, 50
     unit-weight macro-electrons per front-face cell in the first step, 2 ps;
@@ -214,11 +215,13 @@ def config_depth_dose() -> tuple[dict, dict, int]:
     as the periodic walls the paper uses); ionisation, Davies scatter and
     heating (currents of unit-weight electrons give negligible fields).
     Cells are cubic here (150/256 um), so the lateral extent is 4.7 um.
-    Returns (config, beam, steps)."""
+    urban: the paper's other elastic model (Urban-type model functions)
+    instead of Davies.  Returns (config, beam, steps)."""
     nx = 256
     dx = 150e-6 / nx
     cfg = base_config(nx=nx, ny=8, nz=8, dx=dx, dt=5e-15, material="Ta", x_lo=0.0, x_hi=nx * dx,
-                      physics=PHYS_ION | PHYS_SCATTER | PHYS_HEAT, bc_x=BC_OPEN, bc_y=BC_MIRROR,
+                      physics=PHYS_ION | PHYS_SCATTER | PHYS_HEAT | (PHYS_URBAN if urban else 0),
+                      bc_x=BC_OPEN, bc_y=BC_MIRROR,
                       bc_z=BC_MIRROR, max_particles=4096, series_len=4)
     return cfg, beam(), 400
 
