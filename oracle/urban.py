@@ -46,8 +46,10 @@ from __future__ import annotations
 
 import math
 
+from fractions import Fraction
+
 import numpy as np
-from scipy.special import bernoulli
+from mpmath import bernfrac
 
 from . import constants as K
 from . import particles as PT
@@ -55,10 +57,11 @@ from . import particles as PT
 TF = 0.88534              # Thomas-Fermi radius in units of a_0 Z^(-1/3)
 M_C1, M_C2 = 1.13, 3.76   # Moliere's screening constants
 
-# coth a - 1/a = sum_{n >= 1} 2^(2n) B_2n a^(2n-1) / (2n)!  (|a| < pi)
+# coth a - 1/a = sum_{n >= 1} 2^(2n) B_2n a^(2n-1) / (2n)!  (|a| < pi), with
+# the Bernoulli numbers as exact fractions
 _NSER = 20
-_B = bernoulli(2 * _NSER)
-_LCOEF = np.array([2.0 ** (2 * n) * _B[2 * n] / math.factorial(2 * n) for n in range(1, _NSER + 1)])
+_LCOEF = np.array([float(Fraction(2 ** (2 * n)) * Fraction(*bernfrac(2 * n)) / math.factorial(2 * n))
+                   for n in range(1, _NSER + 1)])
 _SMALL = 1.0              # below: the series, above: the closed form
 
 

@@ -639,6 +639,8 @@ __device__ __forceinline__ void langevin_d(double a, double& L, double& C, doubl
 
 // Root in t = ln a of a residual that decreases in a, from t: Newton steps
 // kept inside the bracket, bisection where a step leaves it.  f(t, F, dF/dt).
+// Newton converges quadratically, so a step below 1e-9 leaves an error of
+// order 1e-18 and ends the search.
 template <class Fn>
 __device__ __forceinline__ double urban_solve(Fn f, double t) {
   double lo = -41.0, hi = 41.0;
@@ -650,10 +652,11 @@ __device__ __forceinline__ double urban_solve(Fn f, double t) {
     if (F == 0.0) break;
     if (F > 0.0) lo = t; else hi = t;
     double tn = t - F / dF;
-    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    const bool newton = tn > lo && tn < hi;
+    if (!newton) tn = 0.5 * (lo + hi);
     const double step = fabs(tn - t);
     t = tn;
-    if (step < 1e-15 * (fabs(t) > 1.0 ? fabs(t) : 1.0) || hi - lo < 1e-15) break;
+    if ((newton && step < 1e-9 * (fabs(t) > 1.0 ? fabs(t) : 1.0)) || hi - lo < 1e-15) break;
   }
   return t;
 }
@@ -690,14 +693,14 @@ __device__ __forceinline__ double urban_one_minus_cos(const RunDesc& R, double u
     F = a < 0.5 ? r + 3.0 * S / (a * L) : 3.0 / a - C / L - rho;
     dF = a * dL / (L * L) - 3.0 / a;
   };
-  double t0;
-  if (rho < 0.5) {   // a > ~3: psi = e (2 - 3e) / (1 - e), e = 1/a, exact above a ~ 20
+  double a;
+  if (rho < 0.5) {   // a > ~3: psi = e (2 - 3e) / (1 - e), e = 1/a, exact above a = 20
     const double q = 2.0 + rho, disc = q * q - 12.0 * rho;
-    t0 = -log(2.0 * rho / (q + sqrt(disc > 0.0 ? disc : 0.0)));
+    a = (q + sqrt(disc > 0.0 ? disc : 0.0)) / (2.0 * rho);
+    if (a < 20.0) a = exp(urban_solve(moments, log(a)));
   } else {           // small a: 1/L - 3/a ~ a/5
-    t0 = log(5.0 * r);
+    a = exp(urban_solve(moments, log(5.0 * r)));
   }
-  double a = exp(urban_solve(moments, t0));
   double L, C, S, dL;
   langevin_d(a, L, C, S, dL);
   const double om = -expm1(-x1);   // 1 - exp(-x1)
@@ -710,7 +713,8 @@ __device__ __forceinline__ double urban_one_minus_cos(const RunDesc& R, double u
       F = C1 - om;
       dF = -aa * dL1;
     };
-    a = exp(urban_solve(first, om < 0.5 ? -log(om) : log(3.0 * (1.0 - om))));
+    // above a = 20, 1 - L(a) = 1/a exactly
+    a = om < 0.05 ? 1.0 / om : exp(urban_solve(first, om < 0.5 ? -log(om) : log(3.0 * (1.0 - om))));
     wi = 0.0;
   }
   if (ua < wi) return 2.0 * (1.0 - ub);

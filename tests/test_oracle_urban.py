@@ -115,15 +115,35 @@ def test_fallback_case():
     assert U.langevin(a)[0] == pytest.approx(math.exp(-x1[0]), rel=1e-12)
 
 
-def test_langevin_series_and_closed_form_agree():
-    """coth a - 1/a: the series below 1 against the closed form in extended
-    precision just above and below the switch, and its limits."""
-    a = np.array([0.5, 0.9, 0.999999, 1.0, 1.2])
-    al = a.astype(np.longdouble)
-    ref = (np.cosh(al) / np.sinh(al) - 1 / al).astype(np.float64)
-    assert np.allclose(U.langevin(a), ref, rtol=1e-15)
-    assert U.langevin(np.array([1e-6]))[0] == pytest.approx(1e-6 / 3, rel=1e-12)
+def test_langevin_against_high_precision():
+    """coth a - 1/a, and 1/L - 3/a where the series serves, against
+    40-digit arithmetic on both sides of the switch and far out."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    a = np.array([1e-6, 0.01, 0.3, 0.5, 0.9, 0.989128, 0.999999, 1.0, 1.2, 3.0, 30.0, 1e6])
+    ref = np.array([float(mp.coth(mp.mpf(x)) - 1 / mp.mpf(x)) for x in a])
+    assert np.allclose(U.langevin(a), ref, rtol=3e-16, atol=0)
+    small = a[a < 1.0]
+    ref_phi = np.array([float(1 / (mp.coth(mp.mpf(x)) - 1 / mp.mpf(x)) - 3 / mp.mpf(x)) for x in small])
+    assert np.allclose(U._phi_small(small), ref_phi, rtol=1e-15, atol=0)
     assert U.langevin(np.array([1e6]))[0] == pytest.approx(1 - 1e-6, rel=1e-15)
+
+
+def test_model_parameters_against_high_precision():
+    """The solved (a, w_i) of a few real steps against the same equations
+    solved in 40-digit arithmetic."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    c = _cases()[::7]
+    a, wi = U.model_params(c[:, 0], c[:, 1])
+    for (x1, x2), ai, wii in zip(c, a, wi):
+        L = lambda t: mp.coth(t) - 1 / t
+        if wii > 0.0:
+            am = mp.findroot(lambda t: 1 / L(t) - 3 / t - mp.exp(mp.mpf(x1) - mp.mpf(x2)), mp.mpf(ai))
+            assert float(1 - mp.exp(-mp.mpf(x1)) / L(am)) == pytest.approx(wii, rel=1e-11, abs=1e-15)
+        else:
+            am = mp.findroot(lambda t: L(t) - mp.exp(-mp.mpf(x1)), mp.mpf(ai))
+        assert ai == pytest.approx(float(am), rel=3e-14)
 
 
 def test_sampler_moments_and_cdf():
