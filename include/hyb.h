@@ -99,8 +99,13 @@ enum {
 enum {
   HYB_BC_REFLUX = 0,   /* escape above kappa_esc a0 m c^2, else reflux (Sec. II.A) */
   HYB_BC_OPEN = 1,     /* every electron that leaves escapes (ledger term ESCAPED) */
-  HYB_BC_MIRROR = 2    /* specular reflection without loss or turn; for a laterally
-                          uniform beam the same as periodic walls (App. C) */
+  HYB_BC_MIRROR = 2,   /* specular reflection without loss or turn */
+  HYB_BC_PERIODIC = 3  /* y and z only (App. C's depth-dose setup): an electron that
+                          leaves through one wall re-enters through the opposite one,
+                          momentum unchanged.  The field solve keeps its mirror ghosts
+                          and the current is not folded across the seam, so this kind
+                          is for runs without field feedback: rejected with
+                          HYB_PHYS_FIELDS, HYB_PHYS_EVOLVE_E or HYB_PHYS_EVOLVE_B */
 };
 
 /* ids of delta rays have this bit set; injected electrons' ids stay below it */

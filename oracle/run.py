@@ -20,7 +20,8 @@ the reading both implementations follow):
   7. elastic scatter (App. B): Davies, or Urban-type model functions
      matched to the Lewis moments
   8. boundaries x, y, z: escape or reflux (Sec. II.A); per axis also open
-     (every electron leaving escapes) or a lossless mirror
+     (every electron leaving escapes), a lossless mirror, or (y, z)
+     periodic
   9. removal below e_min, remaining energy -> the cell's heat
  10. n_sub sub-cycles of Ohm + Faraday (App. A)
  11. Ohmic + ionisation heating, electron-ion exchange, resistivity (App. A)
@@ -55,7 +56,7 @@ PHYS_HEAT = 1 << 6
 PHYS_FSIGMA = 1 << 7
 PHYS_DELTA = 1 << 8
 PHYS_URBAN = 1 << 9
-BC_REFLUX, BC_OPEN, BC_MIRROR = 0, 1, 2
+BC_REFLUX, BC_OPEN, BC_MIRROR, BC_PERIODIC = 0, 1, 2, 3
 DELTA_ID_BIT = 0x80000000    # delta rays take ids DELTA_ID_BIT + 0, 1, ...
 
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
@@ -81,6 +82,11 @@ class OracleRun:
             Zk = float(c["extra_Z"][k])
             Ik = c["extra_I_ex"][k] if c["extra_I_ex"][k] > 0 else 11.0 * K.E * Zk
             self.elems.append(dict(S.element(Zk, c["extra_A"][k], c["extra_rho"][k]), I_ex=Ik))
+        if int(c.get("bc_x", BC_REFLUX)) == BC_PERIODIC:
+            raise ValueError("the x faces are the slab's: no periodic kind in x")
+        if (BC_PERIODIC in (int(c.get("bc_y", 0)), int(c.get("bc_z", 0)))
+                and int(c["physics"]) & (PHYS_FIELDS | PHYS_EVOLVE_E | PHYS_EVOLVE_B)):
+            raise ValueError("periodic walls are for runs without field feedback")
         if int(c["physics"]) & PHYS_URBAN and not int(c["physics"]) & PHYS_SCATTER:
             raise ValueError("the Urban-type model replaces the Davies scatter: set PHYS_SCATTER too")
         if len(self.elems) > 1 and int(c["physics"]) & PHYS_FSIGMA:
@@ -412,6 +418,13 @@ class OracleRun:
             if not np.any(out):
                 continue
             mode = int(c.get("bc_" + "xyz"[d], BC_REFLUX))
+            if mode == BC_PERIODIC:
+                # re-enter through the opposite wall, momentum unchanged
+                n_d = hi - lo
+                x = pos[:, d]
+                x = np.where(out, lo + np.mod(x - lo, n_d), x)
+                pos[:, d] = np.where(out, np.clip(x, lo, np.nextafter(hi, -np.inf)), x)
+                continue
             if mode == BC_MIRROR:
                 # specular: mirror the position about the face, flip the normal momentum
                 x = pos[:, d]

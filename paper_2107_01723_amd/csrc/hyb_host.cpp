@@ -214,7 +214,12 @@ static std::string validate(const hyb_config& c) {
       return "bad compound element";
   if (c.n_extra > 0 && (c.physics & HYB_PHYS_FSIGMA)) return "eq. F_sigma needs a single-element solid";
   for (int b : {c.bc_x, c.bc_y, c.bc_z})
-    if (b != HYB_BC_REFLUX && b != HYB_BC_OPEN && b != HYB_BC_MIRROR) return "unknown boundary kind";
+    if (b != HYB_BC_REFLUX && b != HYB_BC_OPEN && b != HYB_BC_MIRROR && b != HYB_BC_PERIODIC)
+      return "unknown boundary kind";
+  if (c.bc_x == HYB_BC_PERIODIC) return "the x faces are the slab's: no periodic kind in x";
+  if ((c.bc_y == HYB_BC_PERIODIC || c.bc_z == HYB_BC_PERIODIC) &&
+      (c.physics & (HYB_PHYS_FIELDS | HYB_PHYS_EVOLVE_E | HYB_PHYS_EVOLVE_B)))
+    return "periodic walls are for runs without field feedback";
   return "";
 }
 

@@ -234,7 +234,12 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
   const bool below = c < lo;
   const bool above = c >= hi;
   if (!(below || above)) return true;
-  const int mode = R.bc[axis];   // 0 reflux, 1 open, 2 mirror
+  const int mode = R.bc[axis];   // 0 reflux, 1 open, 2 mirror, 3 periodic
+  if (mode == 3) {   // re-enter through the opposite wall; nothing else changes
+    const int n = hi - lo;
+    c = lo + ((c - lo) % n + n) % n;
+    return true;
+  }
   if (mode == 1 || (mode == 0 && eps > (T)R.eps_esc)) {
     lds_add(&led[L_ESCAPED], to_fixed(eps * wn * (T)kLedScale));
     lds_add(&led[L_N + C_ESCAPED], 1LL);

@@ -1,7 +1,8 @@
 """Oracle pins for the depth-dose benchmark setup (App. C): the
-mono-energetic normal-incidence beam, the open and mirror boundary kinds,
-the continuous-slowing-down range of a beam without scatter against the
-integral of 1/S, and the lateral uniformity the mirror walls keep."""
+mono-energetic normal-incidence beam, the open, mirror and periodic
+boundary kinds, the continuous-slowing-down range of a beam without scatter
+against the integral of 1/S, and the lateral uniformity the periodic and
+mirror walls keep."""
 import math
 
 import numpy as np
@@ -49,7 +50,7 @@ def test_open_and_mirror_boundaries():
     """A mirror wall reflects the position and the normal momentum and
     changes nothing else; an open face lets every electron escape, however
     slow (a reflux face would turn a slow one back)."""
-    r, cfg, _, _ = _run(physics=0, bc_x=W.BC_OPEN)
+    r, cfg, _, _ = _run(physics=0, bc_x=W.BC_OPEN, bc_y=W.BC_MIRROR, bc_z=W.BC_MIRROR)
     dx = cfg["dx"]
     pos = np.array([[100.5, 0.2, 4.5], [100.5, 7.9, 4.5], [0.1, 4.0, 4.0]]) * dx
     p0 = PT.momentum_of_energy(np.array([1.0, 1.0, 0.05]) * MEV)
@@ -101,11 +102,41 @@ def test_range_without_scatter_is_the_csda_range():
     assert r.counters["n_stopped"] == 2 * cfg["ny"] * cfg["nz"]
 
 
-def test_mirror_walls_keep_a_uniform_beam_uniform():
-    """With Davies scatter the beam spreads, but mirror walls on a laterally
-    uniform beam keep it uniform in y and z (a wrong reflection piles
-    electrons at a wall)."""
-    r, cfg, beam, _ = _run(physics=R.PHYS_ION | R.PHYS_SCATTER)
+def test_periodic_walls():
+    """A periodic wall: the electron re-enters through the opposite wall at
+    the position a free flight gives modulo the width, with its momentum and
+    energy unchanged and nothing booked; periodic x and periodic walls with
+    field feedback are refused."""
+    r, cfg, _, _ = _run(physics=0)
+    dx, ny, nz = cfg["dx"], cfg["ny"], cfg["nz"]
+    pos = np.array([[100.5, 0.2, 4.5], [100.5, 7.9, 7.95], [50.0, 3.0, 0.05]]) * dx
+    p0 = PT.momentum_of_energy(np.array([1.0, 0.3, 2.0]) * MEV)
+    p = np.array([[0.3, -0.9, 0.1], [0.2, 0.95, 0.3], [0.5, 0.1, -0.8]])
+    p = p / np.linalg.norm(p, axis=1)[:, None] * p0[:, None]
+    r.set_state(dict(pos=pos, p=p, w=np.ones(3), tau=np.full(3, 30.0), ids=np.arange(3, dtype=np.uint32)))
+    r.step()
+    assert r.counters["n_escaped"] == 0 and r.counters["n_reflux"] == 0
+    assert np.array_equal(r.p, p)
+    v = p / (PT.gamma_of(p) * K.ME)[:, None]
+    free = pos / dx + v * cfg["dt"] / dx
+    want = free.copy()
+    want[:, 1] = np.mod(free[:, 1], ny)
+    want[:, 2] = np.mod(free[:, 2], nz)
+    assert np.allclose(r.X, want, rtol=0, atol=1e-12)
+    assert r.X[0, 1] > ny - 3 and r.X[1, 1] < 3 and r.X[2, 2] > nz - 3      # they did wrap
+    assert r.ledger["reflux"] == 0.0 and r.ledger["escaped"] == 0.0
+    with pytest.raises(ValueError):
+        _run(bc_x=W.BC_PERIODIC)
+    with pytest.raises(ValueError):
+        _run(physics=R.PHYS_FIELDS)
+
+
+@pytest.mark.parametrize("wall", [W.BC_PERIODIC, W.BC_MIRROR])
+def test_walls_keep_a_uniform_beam_uniform(wall):
+    """With Davies scatter the beam spreads, but periodic or mirror walls on
+    a laterally uniform beam keep it uniform in y and z (a wrong wrap or
+    reflection piles electrons at a wall)."""
+    r, cfg, beam, _ = _run(physics=R.PHYS_ION | R.PHYS_SCATTER, bc_y=wall, bc_z=wall)
     r.add_beam(dict(beam, per_cell=60))
     r.run(60)
     a = r.alive

@@ -51,7 +51,8 @@ FP32_MIXED = 1
 # boundary kinds per axis (x: the slab faces; y, z: the domain walls)
 BC_REFLUX = 0    # escape above kappa_esc a0 m c^2, else reflux (Sec. II.A)
 BC_OPEN = 1      # every electron that leaves escapes
-BC_MIRROR = 2    # specular reflection, no loss (a laterally uniform beam: periodic)
+BC_MIRROR = 2    # specular reflection, no loss
+BC_PERIODIC = 3  # y, z only: leave through one wall, re-enter through the other (no field feedback)
 
 TABLE_CSBH = 0   # complete-screening Bethe-Heitler spectral shape
 TABLE_FLAT = 1   # flat k dsigma/dk
@@ -211,8 +212,7 @@ def config_depth_dose(urban: bool = False) -> tuple[dict, dict, int]:
     """The paper's depth-dose benchmark setup (App. C): 0.5 MeV electrons at
     normal incidence on tantalum, 256 x 8 x 8 cells over 150 um in x, 50
     unit-weight macro-electrons per front-face cell in the first step, 2 ps;
-    open in x, laterally mirror walls (for a laterally uniform beam the same
-    as the periodic walls the paper uses); ionisation, Davies scatter and
+    open in x, periodic in y and z as in the paper; ionisation, Davies scatter and
     heating (currents of unit-weight electrons give negligible fields).
     Cells are cubic here (150/256 um), so the lateral extent is 4.7 um.
     urban: the paper's other elastic model (Urban-type model functions)
@@ -221,8 +221,8 @@ def config_depth_dose(urban: bool = False) -> tuple[dict, dict, int]:
     dx = 150e-6 / nx
     cfg = base_config(nx=nx, ny=8, nz=8, dx=dx, dt=5e-15, material="Ta", x_lo=0.0, x_hi=nx * dx,
                       physics=PHYS_ION | PHYS_SCATTER | PHYS_HEAT | (PHYS_URBAN if urban else 0),
-                      bc_x=BC_OPEN, bc_y=BC_MIRROR,
-                      bc_z=BC_MIRROR, max_particles=4096, series_len=4)
+                      bc_x=BC_OPEN, bc_y=BC_PERIODIC,
+                      bc_z=BC_PERIODIC, max_particles=4096, series_len=4)
     return cfg, beam(), 400
 
 
