@@ -127,6 +127,8 @@ struct hyb_run {
   hyb_device dev{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;                 // grid work beside the sort
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hyb_engine* eng = nullptr;
   int slot = -1;
   void* base = nullptr;
@@ -581,6 +583,9 @@ static void destroy_run(hyb_run* r) {
   (void)hipStreamSynchronize(r->stream);
   if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
   if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
+  if (r->side) { (void)hipStreamSynchronize(r->side); (void)hipStreamDestroy(r->side); }
+  if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
+  if (r->ev_join) (void)hipEventDestroy(r->ev_join);
   for (auto& p : r->ev_pool) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (r->d_maps) dev_free(r->dev, r->d_maps);
   if (r->base) dev_free(r->dev, r->base);
@@ -759,6 +764,14 @@ static hyb_status ensure_single_plans(hyb_run* r) {
   r->L.sort = r->h.sort_every > 0;
   r->L.delta = (r->h.physics & PHYS_DELTA) != 0;
   r->L.urban = (r->h.physics & PHYS_URBAN) != 0;
+  if (!r->side) {
+    HIPCHK(r, hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking));
+    HIPCHK(r, hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming));
+    HIPCHK(r, hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming));
+  }
+  r->L.side = r->side;
+  r->L.ev_fork = r->ev_fork;
+  r->L.ev_join = r->ev_join;
   return upload_plans(r, r->stream, ps, r->L, &r->d_maps, &r->maps_bytes, r->dev);
 }
 
@@ -1225,6 +1238,8 @@ struct hyb_engine {
   hyb_device dev{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;                 // grid work beside the sort
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int64_t budget = 0, used = 0;
   int32_t max_runs = 0;
   RunDesc* d_descs[2] = {nullptr, nullptr};      // per precision: [max_runs]
@@ -1265,6 +1280,9 @@ static hyb_status eng_rebuild(hyb_engine* e, int p) {
   e->max_sub[p] = maxsub;
   e->L[p] = LaunchSet{};
   if (nres == 0) return HYB_OK;
+  e->L[p].side = e->side;
+  e->L[p].ev_fork = e->ev_fork;
+  e->L[p].ev_join = e->ev_join;
   e->L[p].runs = e->d_descs[p];
   e->L[p].nruns = e->max_runs;
   for (int s = 0; s < e->max_runs; ++s) {
@@ -1307,7 +1325,13 @@ hyb_status hyb_engine_create(const hyb_device* dev, int64_t hbm_budget, int32_t 
     if (!e->d_descs[p]) { hyb_engine_free(e); return HYB_ENOMEM; }
     if (hipMemset(e->d_descs[p], 0, sizeof(RunDesc) * max_runs) != hipSuccess) { hyb_engine_free(e); return HYB_EDEVICE; }
   }
-  if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) { hyb_engine_free(e); return HYB_EDEVICE; }
+  if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_join, hipEventDisableTiming) != hipSuccess) {
+    hyb_engine_free(e);
+    return HYB_EDEVICE;
+  }
   *out = e;
   return HYB_OK;
 }
@@ -1433,6 +1457,9 @@ void hyb_engine_free(hyb_engine* e) {
     if (e->d_descs[p]) dev_free(e->dev, e->d_descs[p]);
   }
   if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+  if (e->side) { (void)hipStreamSynchronize(e->side); (void)hipStreamDestroy(e->side); }
+  if (e->ev_fork) (void)hipEventDestroy(e->ev_fork);
+  if (e->ev_join) (void)hipEventDestroy(e->ev_join);
   delete e;
 }
 

@@ -27,6 +27,10 @@ struct LaunchSet {
   bool delta = false;                                 // some run has delta rays
   bool urban = false;                                 // some run has the Urban-type scatter
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
+  // optional second stream (default priority) and the events that fork the
+  // field solve and heating onto it beside the sort, and join them back
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 void launch_step(const LaunchSet& L, hipStream_t s, int precision, int max_sub);

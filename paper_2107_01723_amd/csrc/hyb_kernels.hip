@@ -1792,6 +1792,23 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
                          L.particle.map);
   }
   if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
+  // The sort (scans, scatter) and the grid work (field sub-cycles, heating)
+  // read and write disjoint data, so with a second stream the grid kernels
+  // run beside the HBM-bound scatter.  Delta-ray appends can book a lost
+  // delta ray's energy as heat, so runs with delta rays keep one stream.
+  const bool split = L.side && L.ev_fork && L.ev_join && !L.delta;
+  auto grid_work = [&](hipStream_t g) {
+    for (int k = 0; k < max_sub; ++k) {
+      hipLaunchKernelGGL(k_ohm<T>, dim3(L.grid.nb), dim3(kBlock), 0, g, L.runs, L.grid.map, k);
+      hipLaunchKernelGGL(k_faraday<T>, dim3(L.grid.nb), dim3(kBlock), 0, g, L.runs, L.grid.map, k);
+    }
+    hipLaunchKernelGGL(k_heat, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
+  };
+  if (split) {
+    (void)hipEventRecord(L.ev_fork, s);
+    (void)hipStreamWaitEvent(L.side, L.ev_fork, 0);
+    grid_work(L.side);
+  }
   if (L.sort) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
     hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map, 0);
@@ -1806,11 +1823,12 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
     hipLaunchKernelGGL(k_spawn_group, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
     hipLaunchKernelGGL(k_spawn_append<T>, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
   }
-  for (int k = 0; k < max_sub; ++k) {
-    hipLaunchKernelGGL(k_ohm<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);
-    hipLaunchKernelGGL(k_faraday<T>, dim3(L.grid.nb), dim3(kBlock), 0, s, L.runs, L.grid.map, k);
+  if (split) {
+    (void)hipEventRecord(L.ev_join, L.side);
+    (void)hipStreamWaitEvent(s, L.ev_join, 0);
+  } else {
+    grid_work(s);
   }
-  hipLaunchKernelGGL(k_heat, dim3(L.cells.nb), dim3(kBlock), 0, s, L.runs, L.cells.map);
   hipLaunchKernelGGL(k_finalize, dim3(L.fin.nb), dim3(kBlock), 0, s, L.runs, L.fin.map);
   hipLaunchKernelGGL(k_advance, dim3(L.adv.nb), dim3(64), 0, s, L.runs, L.adv.map);
 }
