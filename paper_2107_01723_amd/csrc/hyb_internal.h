@@ -344,30 +344,47 @@ __device__ __forceinline__ T kinetic(T u2, T g) { return u2 / ((T)1 + g); }
 template <typename T>
 __device__ __forceinline__ T umag_of(T e) { return m_sqrt(e * (e + (T)2)); }
 
-// Turn direction of (ux,uy,uz) by the polar angle of cosine c and sine s at
-// azimuth phi = 2 pi t, keeping |u|.  Basis: a = unit(uhat x e_m), e_m the
-// axis of the smallest |uhat_i| (ties -> lowest index), b = uhat x a;
-// uhat' = c uhat + s (cos phi a + sin phi b).
+// Turn the unit direction (hx,hy,hz) by the polar angle of cosine c and sine
+// s at azimuth phi = 2 pi t.  Basis: a = unit(h x e_m), e_m the axis of the
+// smallest |h_i| (ties -> lowest index), b = h x a; d = c h + s (cos phi a +
+// sin phi b).
 template <typename T>
-__device__ __forceinline__ void rotate_cs(T& ux, T& uy, T& uz, T c, T s, T t) {
-  const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
-  const T inv = (T)1 / um;
-  const T hx = ux * inv, hy = uy * inv, hz = uz * inv;
+__device__ __forceinline__ void turn_unit(T hx, T hy, T hz, T c, T s, T t, T& dx, T& dy, T& dz) {
   const T ax_ = fabs(hx), ay_ = fabs(hy), az_ = fabs(hz);
   T ax, ay, az;
-  if (ax_ <= ay_ && ax_ <= az_) { ax = (T)0; ay = hz; az = -hy; }        // uhat x x
-  else if (ay_ <= az_)          { ax = -hz; ay = (T)0; az = hx; }        // uhat x y
-  else                          { ax = hy; ay = -hx; az = (T)0; }        // uhat x z
+  if (ax_ <= ay_ && ax_ <= az_) { ax = (T)0; ay = hz; az = -hy; }        // h x x
+  else if (ay_ <= az_)          { ax = -hz; ay = (T)0; az = hx; }        // h x y
+  else                          { ax = hy; ay = -hx; az = (T)0; }        // h x z
   const T an = (T)1 / m_sqrt(ax * ax + ay * ay + az * az);
   ax *= an; ay *= an; az *= an;
   const T bx = hy * az - hz * ay, by = hz * ax - hx * az, bz = hx * ay - hy * ax;
   T cp, sp;
   m_sincos2pi(t, sp, cp);
-  T dx = c * hx + s * (cp * ax + sp * bx);
-  T dy = c * hy + s * (cp * ay + sp * by);
-  T dz = c * hz + s * (cp * az + sp * bz);
+  dx = c * hx + s * (cp * ax + sp * bx);
+  dy = c * hy + s * (cp * ay + sp * by);
+  dz = c * hz + s * (cp * az + sp * bz);
+}
+
+// Turn (ux,uy,uz) by the polar angle of cosine c and sine s at azimuth 2 pi t,
+// keeping |u|.
+template <typename T>
+__device__ __forceinline__ void rotate_cs(T& ux, T& uy, T& uz, T c, T s, T t) {
+  const T um = m_sqrt(ux * ux + uy * uy + uz * uz);
+  const T inv = (T)1 / um;
+  T dx, dy, dz;
+  turn_unit(ux * inv, uy * inv, uz * inv, c, s, t, dx, dy, dz);
   const T dn = um / m_sqrt(dx * dx + dy * dy + dz * dz);
   ux = dx * dn; uy = dy * dn; uz = dz * dn;
+}
+
+// The same turn where |u| = um and 1/um = inv are known; the turned unit
+// vector is used as computed (its length is 1 to rounding, which the ledger's
+// rounding term books like any other).
+template <typename T>
+__device__ __forceinline__ void rotate_known(T& ux, T& uy, T& uz, T um, T inv, T c, T s, T t) {
+  T dx, dy, dz;
+  turn_unit(ux * inv, uy * inv, uz * inv, c, s, t, dx, dy, dz);
+  ux = dx * um; uy = dy * um; uz = dz * um;
 }
 
 // The same turn by the polar angle dth.

@@ -966,7 +966,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
           dE = restricted_loss(R, eps1, g, u2);
         } else {
           const T beta = m_sqrt(u2) * ig;
-          T L = m_log(eps1) - (T)R.ln_iex + (T)0.5 * m_log(g + (T)1) + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
+          // ln(eps) + ln(g + 1) / 2 as one logarithm
+          T L = (T)0.5 * m_log(eps1 * eps1 * (g + (T)1)) - (T)R.ln_iex + (T)0.909 * ig * ig - (T)0.818 * ig - (T)0.246;
           L = L > (T)0 ? L : (T)0;
           dE = (T)R.c_ion * L / beta;
         }
@@ -1132,13 +1133,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
           rotate_cs(ux, uy, uz, (T)(1.0 - w), (T)sqrt(w * (2.0 - w)), cd.c);
         } else {
           const T um = m_sqrt(u2);
+          const T iu = (T)1 / um;
           T lg = m_log((T)R.l_dav * um);
           lg = lg > (T)0 ? lg : (T)0;
-          const T s2 = (T)R.c_dav * g / (um * um * um) * lg;
+          const T s2 = (T)R.c_dav * g * (iu * iu * iu) * lg;
           T sb, cb;
           m_sincos2pi(cd.b, sb, cb);
           const T gam = m_sqrt((T)-2 * m_log(cd.a)) * cb;
-          rotate(ux, uy, uz, gam * m_sqrt(s2), cd.c);
+          T sn, cs;
+          m_sincos(gam * m_sqrt(s2), sn, cs);
+          rotate_known(ux, uy, uz, um, iu, cs, sn, cd.c);
         }
         // elastic: any change of the stored energy is rounding, booked apart
         u2 = ux * ux + uy * uy + uz * uz;
