@@ -294,12 +294,13 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 
 // ---------------------------------------------------------------------------
 // LDS staging of one chunk of particles.  Particles sorted by tile arrive in
-// chunks of kBlock; the chunk's home tile is the smallest tile among its
-// electrons.  Deposits of electrons inside the home tile go to LDS integer
-// accumulators covering the 6x6x6 nodes that tile's stencils can reach, its
-// 4x4x4 cells of collisional heat, and the 5x5x5 tiles around it that its
-// electrons can move to in one step; everything else falls back to global
-// atomics.  The LDS sums are flushed with one atomic per non-zero entry.
+// chunks of kBlock; a chunk has two home tiles (its last tile and its most
+// populated other one).  Deposits of electrons inside a home tile go to LDS
+// integer accumulators covering the 6x6x6 nodes that tile's stencils can
+// reach and its 4x4x4 cells of collisional heat; destinations are counted in
+// the 5x5x5 tiles around the first home, where its electrons can move in one
+// step; everything else falls back to global atomics.  The LDS sums are
+// flushed with one atomic per non-zero entry.
 // ---------------------------------------------------------------------------
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
 // (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
@@ -338,6 +339,7 @@ struct ChunkLds {
   long long heat[3][kTile * kTile * kTile * kHeatCopies];
   unsigned cnt[kNbN];
   int lo[2], hi[2];
+  int tc[2][16], tt[2][16];   // electrons per tile of the chunk, keyed by tile & 15, and the tile
   long long led[L_N + C_N];   // rare ledger terms and event counts of the block
   T ph[6][kBlock];            // emitted photon of each lane: k, u (3), |u|, gamma
   T tsig[kLdsTab], tsub[kLdsTab];   // cross-section columns of the tables, if they fit
@@ -381,6 +383,7 @@ __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
   for (int t = threadIdx.x; t < 3 * kTile * kTile * kTile * kHeatCopies; t += kBlock) (&L.heat[0][0])[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x < 2) { L.lo[threadIdx.x] = kNoTile; L.hi[threadIdx.x] = -1; }
+  if (threadIdx.x < 32) { (&L.tc[0][0])[threadIdx.x] = 0; (&L.tt[0][0])[threadIdx.x] = -1; }
   if (threadIdx.x < L_N + C_N) L.led[threadIdx.x] = 0;
 }
 
@@ -818,12 +821,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         if (lo != kNoTile) atomicMin(&S.lo[slot], lo);
         if (hi >= 0) atomicMax(&S.hi[slot], hi);
       }
+      if (cell != kDead) {
+        atomicAdd(&S.tc[slot][my_tile & 15], 1);
+        S.tt[slot][my_tile & 15] = my_tile;
+      }
     }
     __syncthreads();
-    const int tlo = __builtin_amdgcn_readfirstlane(S.lo[slot]);
+    // The homes: the chunk's last tile (it usually continues into the next
+    // chunk, which inherits its LDS sums) and the most populated other tile.
+    // Where few electrons share a tile a chunk spans several, and its first
+    // and last are cut by the chunk's ends, so the fullest tile in between
+    // keeps more deposits and gathers in LDS.  Tiles sharing a key (t & 15)
+    // pool their counts: a worse pick, never a wrong one.
     const int thi = __builtin_amdgcn_readfirstlane(S.hi[slot]);
+    int tlo;
+    {
+      const int l = threadIdx.x & 63;
+      int c = l < 16 ? S.tc[slot][l] : -1;
+      const int t = l < 16 ? S.tt[slot][l] : -1;
+      if (t == thi) c = 0;
+      int key = c * 64 + l;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) key = max(key, __shfl_xor(key, o, 64));
+      key = __builtin_amdgcn_readfirstlane(key);
+      const int tb = __shfl(t, key & 63, 64);
+      tlo = __builtin_amdgcn_readfirstlane((key >> 6) > 0 && tb >= 0 ? tb : S.lo[slot]);
+    }
     // the other slot was last read before the previous chunk's flush
     if (threadIdx.x == 0) { S.lo[slot ^ 1] = kNoTile; S.hi[slot ^ 1] = -1; }
+    if (threadIdx.x < 16) { S.tc[slot ^ 1][threadIdx.x] = 0; S.tt[slot ^ 1][threadIdx.x] = -1; }
     const Home hm = make_home(R, tlo), hm2 = make_home(R, thi);
     // LDS region slots of the homes: a home that is the tile carried over
     // keeps its slot (its sums go on accumulating), the others take clean slots
@@ -884,7 +910,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     if (far_at >= 0) { G(R.far_off)[far_at] = far_val; far_at = -1; }
     int dest_bin = -1;
     if (cell != kDead) {
-      // home region of the electron: 0 (smallest tile), 1 (largest), -1 none
+      // home region of the electron: 0 (the fullest tile), 1 (the last), -1 none
       const int reg = my_tile == tlo ? 0 : (my_tile == thi ? 1 : -1);
       const int rbx = reg == 1 ? hm2.bx : hm.bx, rby = reg == 1 ? hm2.by : hm.by, rbz = reg == 1 ? hm2.bz : hm.bz;
       const int js = reg == 0 ? js_lo : (reg == 1 ? js_hi : -1);
