@@ -904,16 +904,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         __syncthreads();
       }
     }
+    // A third region: the one carried over from the previous chunk, when its
+    // tile (usually this chunk's first) is neither home.  Its electrons still
+    // deposit into it (it is flushed at the chunk's end) and gather from its
+    // halo if that is still staged.  FP32 only: FP64 has no registers to
+    // spare at two waves per SIMD (with it, 2 spills and 0.7 % slower).
+    constexpr bool kThird = sizeof(T) == 4;
+    const bool use_c = kThird && carry_js >= 0 && carry_tile != tlo && carry_tile != thi;
+    const Home hmc = make_home(R, use_c ? carry_tile : tlo);
+    const int fs_c = !use_c ? -1 : (f_tile0 == carry_tile ? 0 : (f_tile1 == carry_tile ? 1 : -1));
     // offsets returned by the previous chunk's atomics: waiting for them here
     // costs nothing, this chunk's loads (issued later) have landed
     if (base_at >= 0) { G(R.chunk_base)[base_at] = base_val; base_at = -1; }
     if (far_at >= 0) { G(R.far_off)[far_at] = far_val; far_at = -1; }
     int dest_bin = -1;
     if (cell != kDead) {
-      // home region of the electron: 0 (the fullest tile), 1 (the last), -1 none
-      const int reg = my_tile == tlo ? 0 : (my_tile == thi ? 1 : -1);
-      const int rbx = reg == 1 ? hm2.bx : hm.bx, rby = reg == 1 ? hm2.by : hm.by, rbz = reg == 1 ? hm2.bz : hm.bz;
-      const int js = reg == 0 ? js_lo : (reg == 1 ? js_hi : -1);
+      // LDS region of the electron: 0 (the fullest tile), 1 (the last), 2 (the
+      // carried one), -1 none
+      const int reg = my_tile == tlo ? 0 : (my_tile == thi ? 1 : (use_c && my_tile == carry_tile ? 2 : -1));
+      const int rbx = reg == 1 ? hm2.bx : (reg == 2 ? hmc.bx : hm.bx);
+      const int rby = reg == 1 ? hm2.by : (reg == 2 ? hmc.by : hm.by);
+      const int rbz = reg == 1 ? hm2.bz : (reg == 2 ? hmc.bz : hm.bz);
+      const int js = reg == 0 ? js_lo : (reg == 1 ? js_hi : (reg == 2 ? carry_js : -1));
       typename JAcc<T>::type* Js = js >= 0 ? S.J[js] : nullptr;
       const int heat_cell = ci + nx * (cj + ny * ck);
       const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
@@ -928,8 +940,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       // --- gather + Boris push (q = -e) ---
       if (phys & PHYS_FIELDS) {
         T Ex, Ey, Ez, Bx, By, Bz;
-        if (reg >= 0) {   // from the home halo staged in LDS
-          const T* F = &S.F[reg == 0 ? fs_lo : fs_hi][0][0];
+        if (reg >= 0 && (reg < 2 || fs_c >= 0)) {   // from a halo staged in LDS
+          const T* F = &S.F[reg == 0 ? fs_lo : (reg == 1 ? fs_hi : fs_c)][0][0];
           Ex = gather8_lds(F, rbx, rby, rbz, sxa, nya, nza);
           Ey = gather8_lds(F + kHaloN, rbx, rby, rbz, nxa, sya, nza);
           Ez = gather8_lds(F + 2 * kHaloN, rbx, rby, rbz, nxa, nya, sza);
