@@ -64,10 +64,12 @@ Layout make_layout(const hyb_config& c) {
   L.off_heat = take(cells * 8);
   L.off_fsig = take(cells * ts);
   for (int b = 0; b < 2; ++b) {
-    L.off_part[b][0] = take(cap * 4);                       // cell
-    for (int f = 1; f < 9; ++f) L.off_part[b][f] = take(cap * ts);
-    L.off_part[b][9] = take(cap * 4);                       // id
-    L.off_part[b][10] = take(delta ? cap * ts : 0);         // delta-ray depth
+    // one record per electron: cell, id, then ox oy oz ux uy uz wn tau
+    const size_t rec = 8 + 8 * ts;
+    L.off_part[b][0] = take(cap * rec);                     // cell
+    L.off_part[b][9] = L.off_part[b][0] + 4;                // id
+    for (int f = 1; f < 9; ++f) L.off_part[b][f] = L.off_part[b][0] + 8 + (f - 1) * ts;
+    L.off_part[b][10] = take(delta ? cap * ts : 0);         // delta-ray depth (own array)
   }
   const size_t tabn = (size_t)c.table_nT * c.table_nr;
   L.off_tabX = take(tabn * ts);
@@ -1049,19 +1051,27 @@ hyb_status hyb_get_state(hyb_run* r, hyb_state* st) {
   const size_t ts = c.precision == HYB_FP64 ? 8 : 4;
   const PartPtrs& P = r->h.p[ctr.cur];
   std::vector<uint32_t> cell(n), id(n);
-  std::vector<char> raw[9];
-  void* src[9] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau, P.taud};
+  const size_t rec = 8 + 8 * ts;
+  std::vector<char> recs, rawd;
   const int nf = (c.physics & HYB_PHYS_DELTA) ? 9 : 8;
   if (n) {
-    HIPCHK(r, hipMemcpy(cell.data(), P.cell, n * 4, hipMemcpyDeviceToHost));
-    HIPCHK(r, hipMemcpy(id.data(), P.id, n * 4, hipMemcpyDeviceToHost));
-    for (int f = 0; f < nf; ++f) {
-      raw[f].resize(n * ts);
-      HIPCHK(r, hipMemcpy(raw[f].data(), src[f], n * ts, hipMemcpyDeviceToHost));
+    recs.resize(n * rec);
+    HIPCHK(r, hipMemcpy(recs.data(), P.cell, n * rec, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) {
+      memcpy(&cell[i], recs.data() + i * rec, 4);
+      memcpy(&id[i], recs.data() + i * rec + 4, 4);
+    }
+    if (nf == 9) {
+      rawd.resize(n * ts);
+      HIPCHK(r, hipMemcpy(rawd.data(), P.taud, n * ts, hipMemcpyDeviceToHost));
     }
   }
   auto val = [&](int f, size_t i) -> double {
-    return ts == 8 ? ((const double*)raw[f].data())[i] : (double)((const float*)raw[f].data())[i];
+    const char* p = f == 8 ? rawd.data() + i * ts : recs.data() + i * rec + 8 + f * ts;
+    if (ts == 8) { double v; memcpy(&v, p, 8); return v; }
+    float v;
+    memcpy(&v, p, 4);
+    return (double)v;
   };
   size_t alive = 0;
   for (size_t i = 0; i < n; ++i) alive += cell[i] != kDead;
@@ -1186,16 +1196,25 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
       if (!std::isfinite(f[k][i])) return fail(r, HYB_ENUMERIC, "non-finite particle value");
   }
   const PartPtrs& P = r->h.p[0];
-  void* dst[9] = {P.ox, P.oy, P.oz, P.ux, P.uy, P.uz, P.wn, P.tau, P.taud};
   auto put_typed = [&](void* d, const double* v, size_t cnt) -> hipError_t {
     if (ts == 8) return hipMemcpy(d, v, cnt * 8, hipMemcpyHostToDevice);
     std::vector<float> fl(v, v + cnt);
     return hipMemcpy(d, fl.data(), cnt * 4, hipMemcpyHostToDevice);
   };
   if (n) {
-    HIPCHK(r, hipMemcpy(P.cell, cell.data(), n * 4, hipMemcpyHostToDevice));
-    HIPCHK(r, hipMemcpy(P.id, st->id, n * 4, hipMemcpyHostToDevice));
-    for (int k = 0; k < nf; ++k) HIPCHK(r, put_typed(dst[k], f[k].data(), n));
+    const size_t rec = 8 + 8 * ts;
+    std::vector<char> recs(n * rec);
+    for (size_t i = 0; i < n; ++i) {
+      char* q = recs.data() + i * rec;
+      memcpy(q, &cell[i], 4);
+      memcpy(q + 4, &st->id[i], 4);
+      for (int k = 0; k < 8; ++k) {
+        if (ts == 8) memcpy(q + 8 + 8 * k, &f[k][i], 8);
+        else { const float v = (float)f[k][i]; memcpy(q + 8 + 4 * k, &v, 4); }
+      }
+    }
+    HIPCHK(r, hipMemcpy(P.cell, recs.data(), n * rec, hipMemcpyHostToDevice));
+    if (delta) HIPCHK(r, put_typed(P.taud, f[8].data(), n));
   }
   const size_t nodes = (size_t)r->h.nodes, cells = (size_t)r->h.cells;
   for (int d = 0; d < 3; ++d) {

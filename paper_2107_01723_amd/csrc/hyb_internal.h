@@ -298,16 +298,43 @@ __device__ __forceinline__ unsigned atomic_add_u32(unsigned* p, unsigned v) {
   return __hip_atomic_fetch_add(G(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Particle arrays of one buffer, typed for the run's precision.
+// Bytes of one electron's record: cell and id (u32), then ox oy oz ux uy uz
+// wn tau in the run's precision.  A record is contiguous, so the electrons
+// that the sort moves to one tile reach HBM as whole lines.
+template <typename T> constexpr long long kRec = 8 + 8 * (long long)sizeof(T);
+
+// One field of the records: element i at the record base + i records + the
+// field's offset.  Every field of a buffer shares the base, so the compiler
+// sees one record's fields as neighbours and can merge their loads and stores.
+template <typename T, typename U, int OFF>
+struct RecField {
+  gptr<char> b;
+  __device__ __forceinline__ __attribute__((address_space(1))) U& operator[](long long i) const {
+    return *(gptr<U>)(b + i * kRec<T> + OFF);
+  }
+};
+
+// Particle arrays of one buffer, typed for the run's precision (the delta-ray
+// depth is an array of its own).
 template <typename T>
 struct PartG {
-  gptr<uint32_t> cell, id;
-  gptr<T> ox, oy, oz, ux, uy, uz, wn, tau, taud;
+  static constexpr int S = (int)sizeof(T);
+  RecField<T, uint32_t, 0> cell;
+  RecField<T, uint32_t, 4> id;
+  RecField<T, T, 8> ox;
+  RecField<T, T, 8 + S> oy;
+  RecField<T, T, 8 + 2 * S> oz;
+  RecField<T, T, 8 + 3 * S> ux;
+  RecField<T, T, 8 + 4 * S> uy;
+  RecField<T, T, 8 + 5 * S> uz;
+  RecField<T, T, 8 + 6 * S> wn;
+  RecField<T, T, 8 + 7 * S> tau;
+  gptr<T> taud;
 };
 template <typename T>
 __device__ __forceinline__ PartG<T> part_g(const PartPtrs& P) {
-  return PartG<T>{G(P.cell), G(P.id), G((T*)P.ox), G((T*)P.oy), G((T*)P.oz),
-                  G((T*)P.ux), G((T*)P.uy), G((T*)P.uz), G((T*)P.wn), G((T*)P.tau), G((T*)P.taud)};
+  const gptr<char> b = G((char*)P.cell);
+  return PartG<T>{{b}, {b}, {b}, {b}, {b}, {b}, {b}, {b}, {b}, {b}, G((T*)P.taud)};
 }
 
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
