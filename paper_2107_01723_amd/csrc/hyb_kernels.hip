@@ -1224,9 +1224,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       if (!alive) {
         P.cell[i] = kDead;
       } else {
+        // the whole record, unchanged fields too: whole lines reach HBM
+        // without a read-modify-write of the parts left out
         P.cell[i] = pack_cell(ci, cj, ck);
+        P.id[i] = id;
         P.ox[i] = ox; P.oy[i] = oy; P.oz[i] = oz;
         P.ux[i] = ux; P.uy[i] = uy; P.uz[i] = uz;
+        P.wn[i] = wn;
         P.tau[i] = tau;
         if constexpr (D) {
           if (phys & PHYS_DELTA) P.taud[i] = taud;
