@@ -160,3 +160,20 @@ def test_urban_and_davies_runs_in_one_batch(P):
     # the two models did differ
     assert not np.array_equal(ref[0]["p"][:10], ref[1]["p"][:10])
     eng.close()
+
+
+def test_urban_on_a_compound_fp64(P):
+    """The Urban-type scatter on the CH plastic slab (two elements: the
+    transport depths summed over them), 30 steps with collisions and field
+    feedback off: every electron against the oracle."""
+    cfg, srcs, _ = small_config(4000, brem_boost=10.0, physics=URBAN_PHYS, max_particles=20000, **W.plastic())
+    ora = oracle_at(cfg, srcs, 30)
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(30)
+    err, only = particle_errors(run.get_state(), ora.state(), cfg["dx"])
+    print(f"  alive {len(err['ids'])}, max|dp| {err['p'].max():.2e}", flush=True)
+    assert not only and len(err["ids"]) > 500
+    for k in ("p", "pos", "tau"):
+        assert err[k].max() < 1e-10, (k, err[k].max())
+    run.close()
