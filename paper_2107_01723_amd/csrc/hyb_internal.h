@@ -212,7 +212,7 @@ struct RunDesc {
   // counting: a chunk's electrons bound for tile t occupy
   // tile_start[t] + chunk_base[chunk][bin of t] + [0, count), and an electron
   // bound outside its chunk's neighbourhood sits at tile_start[t] + far_off[i].
-  int* chunk_home;          // [chunks] smallest start-of-step tile of the chunk (none: kNoTile)
+  int* chunk_home;          // [chunks] first home tile of the chunk, the centre of its destination bins (none: kNoTile)
   unsigned* chunk_base;     // [chunks][kNbN]
   unsigned* far_off;        // [capacity]
   double* red;              // per-block partial sums for host-side reductions

@@ -326,11 +326,12 @@ template <> struct JAcc<float> {
 constexpr int kHeatCopies = 4;
 constexpr int kLdsTab = 128;   // table rows staged in LDS
 
-// A chunk has two home tiles: the smallest and the largest tile among its
-// electrons.  The electrons of a tile-sorted chunk of kBlock rarely span
-// more than two tiles, so nearly all of them deposit into LDS; the homes'
-// tile indices are reduced into a pair of slots that alternate between
-// chunks, so that a chunk's reduction never races the previous chunk's reads.
+// A chunk has two home tiles: its last tile and its most populated other
+// one.  Where a tile holds ~200 electrons a tile-sorted chunk of kBlock
+// rarely spans more than two tiles, so nearly all of them deposit into LDS.
+// The reductions that pick the homes (last tile, per-tile counts) use slots
+// that alternate between chunks, so that a chunk's reduction never races the
+// previous chunk's reads.
 template <typename T>
 struct ChunkLds {
   // three region slots: the chunk's two homes and the region carried over
@@ -1282,8 +1283,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     // LDS sums to HBM; the flush also clears them, and the next chunk writes
     // LDS only after its own barrier
     {
-      // the region of the largest home carries over to the next chunk (its
-      // tile usually continues there); the rest is flushed
+      // the region of the last tile's home carries over to the next chunk
+      // (that tile usually continues there); the rest is flushed
       const bool last = ch + cr.stride >= cr.end;
       const int keep = last ? -1 : (two ? js_hi : js_lo);
       if (hm.ok && js_lo != keep) lds_flush_region(R, S, js_lo, hm);
