@@ -116,7 +116,7 @@ def time_run(P, cfg, srcs, steps, warmup, label):
     return res
 
 
-def cpu_baseline(cfg, srcs, n_macro=100_000, steps=4):
+def cpu_baseline(cfg, srcs, n_macro=100_000, steps=12):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
     full grid, n_macro electrons all injected in the first step (untimed),
     then `steps` timed steps on one core."""
@@ -151,7 +151,8 @@ def main():
     ap.add_argument("--model", action="store_true",
                     help="also time the energy-partition model over the intensity-Z plane")
     ap.add_argument("--opt-in", action="store_true",
-                    help="also time the workload with delta rays and with eq. F_sigma (FP64)")
+                    help="also time the workload with delta rays, with eq. F_sigma and with the "
+                         "Urban-type scatter (FP64)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 512 MiB with torch (reference kernel for HBM counters)")
     a = ap.parse_args()
