@@ -36,7 +36,7 @@ size_t hist_stride(const hyb_config& c) {
 
 // Sizes of everything a run keeps in device memory.
 struct Layout {
-  size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta, off_heat, off_fsig;
+  size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta[2], off_heat, off_fsig;
   size_t off_part[2][11];
   size_t off_sp_cell, off_sp_pid, off_sp_f[7], off_sp_cnt, off_sp_start, off_sp_blk, off_sp_grp, off_sp_gpid;
   size_t off_tabX, off_tabSIG, off_tabSUB;
@@ -60,7 +60,7 @@ Layout make_layout(const hyb_config& c) {
   for (int d = 0; d < 3; ++d) L.off_J[d] = take(nodes * 8);
   L.off_Te = take(cells * 8);
   L.off_Ti = take(cells * 8);
-  L.off_eta = take(cells * 8);
+  for (int k = 0; k < 2; ++k) L.off_eta[k] = take(cells * 8);
   L.off_heat = take(cells * 8);
   L.off_fsig = take(cells * ts);
   for (int b = 0; b < 2; ++b) {
@@ -129,8 +129,8 @@ struct hyb_run {
   hyb_device dev{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  hipStream_t side = nullptr;                 // grid work beside the sort
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side = nullptr, side2 = nullptr;   // field sub-cycles, heating beside the sort
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   hyb_engine* eng = nullptr;
   int slot = -1;
   void* base = nullptr;
@@ -385,7 +385,7 @@ static void point_desc(hyb_run* r) {
   }
   h.Te = (double*)(b + L.off_Te);
   h.Ti = (double*)(b + L.off_Ti);
-  h.eta = (double*)(b + L.off_eta);
+  for (int k = 0; k < 2; ++k) h.eta[k] = (double*)(b + L.off_eta[k]);
   h.ion_heat = (long long*)(b + L.off_heat);
   h.fsig = b + L.off_fsig;
   for (int k = 0; k < 2; ++k) {
@@ -570,7 +570,7 @@ static hyb_status create_run(const hyb_config* cfg, const hyb_device* dev, hyb_r
         for (int i = r->h.ix_lo; i < r->h.ix_hi; ++i) eta[i + (size_t)c.nx * (j + (size_t)c.ny * k)] = e0;
     HIPCHK(r, hipMemcpy(r->h.Te, T.data(), ncells * 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemcpy(r->h.Ti, T.data(), ncells * 8, hipMemcpyHostToDevice));
-    HIPCHK(r, hipMemcpy(r->h.eta, eta.data(), ncells * 8, hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) HIPCHK(r, hipMemcpy(r->h.eta[k], eta.data(), ncells * 8, hipMemcpyHostToDevice));
   }
   HIPCHK(r, refresh_fsig(r));
   (void)nodes;
@@ -585,9 +585,10 @@ static void destroy_run(hyb_run* r) {
   (void)hipStreamSynchronize(r->stream);
   if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
   if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
-  if (r->side) { (void)hipStreamSynchronize(r->side); (void)hipStreamDestroy(r->side); }
-  if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
-  if (r->ev_join) (void)hipEventDestroy(r->ev_join);
+  for (hipStream_t q : {r->side, r->side2})
+    if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); }
+  for (hipEvent_t v : {r->ev_fork, r->ev_join, r->ev_join2})
+    if (v) (void)hipEventDestroy(v);
   for (auto& p : r->ev_pool) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (r->d_maps) dev_free(r->dev, r->d_maps);
   if (r->base) dev_free(r->dev, r->base);
@@ -768,12 +769,16 @@ static hyb_status ensure_single_plans(hyb_run* r) {
   r->L.urban = (r->h.physics & PHYS_URBAN) != 0;
   if (!r->side) {
     HIPCHK(r, hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking));
+    HIPCHK(r, hipStreamCreateWithFlags(&r->side2, hipStreamNonBlocking));
     HIPCHK(r, hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming));
     HIPCHK(r, hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming));
+    HIPCHK(r, hipEventCreateWithFlags(&r->ev_join2, hipEventDisableTiming));
   }
   r->L.side = r->side;
+  r->L.side2 = r->side2;
   r->L.ev_fork = r->ev_fork;
   r->L.ev_join = r->ev_join;
+  r->L.ev_join2 = r->ev_join2;
   return upload_plans(r, r->stream, ps, r->L, &r->d_maps, &r->maps_bytes, r->dev);
 }
 
@@ -1123,7 +1128,7 @@ hyb_status hyb_get_state(hyb_run* r, hyb_state* st) {
   }
   if (st->Te) HIPCHK(r, hipMemcpy(st->Te, r->h.Te, cells * 8, hipMemcpyDeviceToHost));
   if (st->Ti) HIPCHK(r, hipMemcpy(st->Ti, r->h.Ti, cells * 8, hipMemcpyDeviceToHost));
-  if (st->eta) HIPCHK(r, hipMemcpy(st->eta, r->h.eta, cells * 8, hipMemcpyDeviceToHost));
+  if (st->eta) HIPCHK(r, hipMemcpy(st->eta, r->h.eta[ctr.step & 1], cells * 8, hipMemcpyDeviceToHost));
   if (st->ion_heat) {
     std::vector<long long> q(cells);
     HIPCHK(r, hipMemcpy(q.data(), r->h.ion_heat, cells * 8, hipMemcpyDeviceToHost));
@@ -1224,7 +1229,8 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   }
   if (st->Te) HIPCHK(r, hipMemcpy(r->h.Te, st->Te, cells * 8, hipMemcpyHostToDevice));
   if (st->Ti) HIPCHK(r, hipMemcpy(r->h.Ti, st->Ti, cells * 8, hipMemcpyHostToDevice));
-  if (st->eta) HIPCHK(r, hipMemcpy(r->h.eta, st->eta, cells * 8, hipMemcpyHostToDevice));
+  if (st->eta)   // both buffers: the next step reads one, and a run without heating never writes the other
+    for (int k = 0; k < 2; ++k) HIPCHK(r, hipMemcpy(r->h.eta[k], st->eta, cells * 8, hipMemcpyHostToDevice));
   if (st->Te || st->Ti) HIPCHK(r, refresh_fsig(r));
   HIPCHK(r, hipMemset(r->h.ion_heat, 0, cells * 8));
   if (delta) HIPCHK(r, hipMemset(r->h.sp_cnt, 0, (size_t)r->h.ntiles * 4));
@@ -1257,8 +1263,8 @@ struct hyb_engine {
   hyb_device dev{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  hipStream_t side = nullptr;                 // grid work beside the sort
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side = nullptr, side2 = nullptr;   // field sub-cycles, heating beside the sort
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   int64_t budget = 0, used = 0;
   int32_t max_runs = 0;
   RunDesc* d_descs[2] = {nullptr, nullptr};      // per precision: [max_runs]
@@ -1300,8 +1306,10 @@ static hyb_status eng_rebuild(hyb_engine* e, int p) {
   e->L[p] = LaunchSet{};
   if (nres == 0) return HYB_OK;
   e->L[p].side = e->side;
+  e->L[p].side2 = e->side2;
   e->L[p].ev_fork = e->ev_fork;
   e->L[p].ev_join = e->ev_join;
+  e->L[p].ev_join2 = e->ev_join2;
   e->L[p].runs = e->d_descs[p];
   e->L[p].nruns = e->max_runs;
   for (int s = 0; s < e->max_runs; ++s) {
@@ -1346,8 +1354,10 @@ hyb_status hyb_engine_create(const hyb_device* dev, int64_t hbm_budget, int32_t 
   }
   if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&e->side2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&e->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&e->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_join2, hipEventDisableTiming) != hipSuccess) {
     hyb_engine_free(e);
     return HYB_EDEVICE;
   }
@@ -1476,9 +1486,10 @@ void hyb_engine_free(hyb_engine* e) {
     if (e->d_descs[p]) dev_free(e->dev, e->d_descs[p]);
   }
   if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
-  if (e->side) { (void)hipStreamSynchronize(e->side); (void)hipStreamDestroy(e->side); }
-  if (e->ev_fork) (void)hipEventDestroy(e->ev_fork);
-  if (e->ev_join) (void)hipEventDestroy(e->ev_join);
+  for (hipStream_t q : {e->side, e->side2})
+    if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); }
+  for (hipEvent_t v : {e->ev_fork, e->ev_join, e->ev_join2})
+    if (v) (void)hipEventDestroy(v);
   delete e;
 }
 

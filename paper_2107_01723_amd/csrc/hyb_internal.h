@@ -188,7 +188,8 @@ struct RunDesc {
   // arrays
   void* E[3]; void* B[3];
   long long* J[3];
-  double* Te; double* Ti; double* eta;
+  double* Te; double* Ti;
+  double* eta[2];           // resistivity: step n reads eta[n & 1], heating writes eta[(n + 1) & 1]
   void* fsig;               // [cells] eq. F_sigma of each cell (run precision), start of step
   long long* ion_heat;
   PartPtrs p[2];

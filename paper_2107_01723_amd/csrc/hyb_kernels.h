@@ -27,10 +27,10 @@ struct LaunchSet {
   bool delta = false;                                 // some run has delta rays
   bool urban = false;                                 // some run has the Urban-type scatter
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
-  // optional second stream (default priority) and the events that fork the
-  // field solve and heating onto it beside the sort, and join them back
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // optional streams (default priority) and the events that fork the field
+  // sub-cycles and the heating onto them beside the sort, and join them back
+  hipStream_t side = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
 };
 
 void launch_step(const LaunchSet& L, hipStream_t s, int precision, int max_sub);

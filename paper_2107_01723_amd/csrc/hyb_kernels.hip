@@ -1617,7 +1617,7 @@ __global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs
   const gptr<T> Ex = G((T*)R.E[0]), Ey = G((T*)R.E[1]), Ez = G((T*)R.E[2]);
   const gptr<const long long> Jx = G((const long long*)R.J[0]), Jy = G((const long long*)R.J[1]),
                               Jz = G((const long long*)R.J[2]);
-  const gptr<const double> eta = G((const double*)R.eta);
+  const gptr<const double> eta = G((const double*)R.eta[G(R.ctr)->step & 1]);
   const double inv_dx = 1.0 / R.dx, inv_mu0 = 1.0 / kMu0, ju = R.j_unit;
   const long long nn = R.nodes;
   auto ce = [&](int i, int j, int k) { return eta[i + nx * (j + ny * k)]; };
@@ -1701,6 +1701,11 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
   const double ju = 0.25 * R.j_unit, dV = R.dx * R.dx * R.dx;
   const bool fixed = R.eta_fixed > 0.0;
   const bool want_fs = (R.physics & PHYS_FSIGMA) != 0;
+  // this step's resistivity in, the next step's out: the field sub-cycles,
+  // which read this step's, may run at the same time
+  const long long step = G(R.ctr)->step;
+  const gptr<const double> eta_in = G((const double*)R.eta[step & 1]);
+  const gptr<double> eta_out = G(R.eta[(step + 1) & 1]);
   const Solid sol = R.solid;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < ns; t += (long long)bm.nb * kBlock) {
     const int i = R.ix_lo + (int)(t % w);
@@ -1714,7 +1719,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const double jx = (double)(Jx[n] + Jx[n + sx] + Jx[n + sxy] + Jx[n + sx + sxy]) * ju;
     const double jy = (double)(Jy[n] + Jy[n + 1] + Jy[n + sxy] + Jy[n + 1 + sxy]) * ju;
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
-    double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = G(R.eta)[c], fs = 1.0;
+    double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = eta_in[c], fs = 1.0;
     const double j2 = jx * jx + jy * jy + jz * jz, qh = (double)G(R.ion_heat)[c] * R.heat_unit;
     if (R.mix.n == 1) heat_cell(sol, Te, Ti, eta, j2, qh, R.dt, dV, fixed, want_fs ? &fs : nullptr);
     else heat_cell_mix(R.mix, Te, Ti, eta, j2, qh, R.dt, dV, fixed);
@@ -1724,7 +1729,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     }
     G(R.Te)[c] = Te;
     G(R.Ti)[c] = Ti;
-    G(R.eta)[c] = eta;
+    eta_out[c] = eta;
   }
 }
 
@@ -1856,22 +1861,26 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
                          L.particle.map);
   }
   if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
-  // The sort (scans, scatter) and the grid work (field sub-cycles, heating)
-  // read and write disjoint data, so with a second stream the grid kernels
-  // run beside the HBM-bound scatter.  Delta-ray appends can book a lost
+  // The sort (scans, scatter), the field sub-cycles and the heating read and
+  // write disjoint data (the heating writes the next step's resistivity), so
+  // with two more streams the grid kernels run beside the HBM-bound scatter.  Delta-ray appends can book a lost
   // delta ray's energy as heat, so runs with delta rays keep one stream.
-  const bool split = L.side && L.ev_fork && L.ev_join && !L.delta;
-  auto grid_work = [&](hipStream_t g) {
+  const bool split = L.side && L.side2 && L.ev_fork && L.ev_join && L.ev_join2 && !L.delta;
+  auto fields = [&](hipStream_t g) {
     for (int k = 0; k < max_sub; ++k) {
       hipLaunchKernelGGL(k_ohm<T>, dim3(L.grid.nb), dim3(kBlock), 0, g, L.runs, L.grid.map, k);
       hipLaunchKernelGGL(k_faraday<T>, dim3(L.grid.nb), dim3(kBlock), 0, g, L.runs, L.grid.map, k);
     }
+  };
+  auto heating = [&](hipStream_t g) {
     hipLaunchKernelGGL(k_heat, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
   };
-  if (split) {
+  if (split) {   // field sub-cycles and heating each on a stream of its own
     (void)hipEventRecord(L.ev_fork, s);
     (void)hipStreamWaitEvent(L.side, L.ev_fork, 0);
-    grid_work(L.side);
+    (void)hipStreamWaitEvent(L.side2, L.ev_fork, 0);
+    fields(L.side);
+    heating(L.side2);
   }
   if (L.sort) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
@@ -1889,9 +1898,12 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
   }
   if (split) {
     (void)hipEventRecord(L.ev_join, L.side);
+    (void)hipEventRecord(L.ev_join2, L.side2);
     (void)hipStreamWaitEvent(s, L.ev_join, 0);
+    (void)hipStreamWaitEvent(s, L.ev_join2, 0);
   } else {
-    grid_work(s);
+    fields(s);
+    heating(s);
   }
   hipLaunchKernelGGL(k_finalize, dim3(L.fin.nb), dim3(kBlock), 0, s, L.runs, L.fin.map);
   hipLaunchKernelGGL(k_advance, dim3(L.adv.nb), dim3(64), 0, s, L.runs, L.adv.map);
