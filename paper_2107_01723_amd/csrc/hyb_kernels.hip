@@ -1879,8 +1879,8 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
     (void)hipEventRecord(L.ev_fork, s);
     (void)hipStreamWaitEvent(L.side, L.ev_fork, 0);
     (void)hipStreamWaitEvent(L.side2, L.ev_fork, 0);
-    fields(L.side);
     heating(L.side2);
+    fields(L.side);
   }
   if (L.sort) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
