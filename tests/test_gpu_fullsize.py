@@ -167,3 +167,34 @@ def test_fullsize_fp64_delta_rays(P):
     assert _closure(t) < 1e-6
     assert t["counters"]["n_delta_lost"] == 0
     assert len(np.unique(st1["ids"])) == len(st1["ids"])
+
+
+def test_fullsize_fp64_urban_scatter(P):
+    """The 2e7-electron FP64 workload with the Urban-type scatter: 2000
+    electrons drawn at step 30 stepped once by the oracle in the GPU's fields
+    against the GPU's step of the whole population, and ledger closure."""
+    cfg, srcs, _ = W.config_fp64_large()
+    cfg["physics"] |= W.PHYS_URBAN
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(30)
+    st0 = run.get_state()
+    run.step(1)
+    st1 = run.get_state()
+    t = run.tally()
+    run.close()
+    n0 = len(st0["ids"])
+    pick = np.random.default_rng(7).choice(n0, 2000, replace=False)
+    ids = st0["ids"][pick]
+    ora = OracleRun(cfg)
+    ora.set_state(dict(_subset(st0, ids), step=st0["step"], next_id=st0["next_id"]))
+    ora.step()
+    ref = ora.state()
+    got = _subset(st1, ids)
+    err, only = particle_errors(got, ref, cfg["dx"])
+    print(f"  compared {len(err['ids'])}: max|dp|={err['p'].max():.2e} max|dx|/dx={err['pos'].max():.2e} "
+          f"only-one-side={len(only)}", flush=True)
+    assert not only and len(err["ids"]) > 1800
+    for k in ("p", "pos", "tau", "w"):
+        assert err[k].max() < 1e-10, k
+    assert _closure(t) < 1e-6
