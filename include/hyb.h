@@ -136,7 +136,10 @@ enum {
   HYB_C_DELTA = 5,        /* delta rays emitted (those below e_min included) */
   HYB_C_DELTA_LOST = 6,   /* delta rays that found no free particle slot: their
                              energy is booked as STOPPED in the birth cell */
-  HYB_COUNTER_N = 7
+  HYB_C_ESTEPS = 7,       /* electron-steps: the electrons alive at the start of
+                             each completed step (that step's injections
+                             included), summed over the steps */
+  HYB_COUNTER_N = 8
 };
 
 /* Run configuration (copied by hyb_init).  The solid is one element filling

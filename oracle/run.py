@@ -62,7 +62,7 @@ DELTA_ID_BIT = 0x80000000    # delta rays take ids DELTA_ID_BIT + 0, 1, ...
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
                "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr", "residual")
 COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped", "n_delta",
-                "n_delta_lost")
+                "n_delta_lost", "n_electron_steps")
 
 
 class OracleRun:
@@ -282,6 +282,7 @@ class OracleRun:
         taud = self.taud[idx].copy()
         ids = self.ids[idx]
         m = len(idx)
+        self.counters["n_electron_steps"] += m
         pos_n = pos.copy()             # x^n: birth place of this step's delta rays
 
         # push
@@ -488,13 +489,25 @@ class OracleRun:
         self.taud[idx] = taud
         self.alive[idx] = alive
 
-        # fields
+        self.grid_update()
+        if born is not None and len(born["w"]):
+            self._add_delta_rays(born, n)
+        self.step_index += 1
+
+    def grid_update(self):
+        """The grid side of the step from this step's hot current self.j and
+        collisional heat self.ion_heat: n_sub sub-cycles of Ohm + Faraday
+        (App. A, eqs. Ohms_Law, Ampere_Maxwell, Faraday_Lens), then the Ohmic
+        and collisional heating, exchange and resistivity of the solid cells
+        (App. A, eq. Te_rise)."""
+        c = self.cfg
+        phys = int(c["physics"])
+        dt, dx = self.dt, self.dx
         ev_e = bool(phys & PHYS_EVOLVE_E)
         ev_b = bool(phys & PHYS_EVOLVE_B)
         if ev_e or ev_b:
             self.E, self.B = F.field_update(self.E, self.B, self.j, self.eta, dt, dx,
                                             self.n_sub, ev_e, ev_b)
-        # heat
         if phys & PHYS_HEAT:
             s = self.solid
             j2 = F.cell_current_sq(self.j)
@@ -504,9 +517,6 @@ class OracleRun:
             self.Te[s], self.Ti[s] = Te, Ti
             if c["eta_fixed"] <= 0.0:
                 self.eta[s] = eta
-        if born is not None and len(born["w"]):
-            self._add_delta_rays(born, n)
-        self.step_index += 1
 
     def _add_delta_rays(self, born, n):
         """The step's delta rays join the run: ids DELTA_ID_BIT + delta_next +

@@ -624,8 +624,8 @@ static hyb_status add_source(hyb_run* r, const hyb_source* s) {
     r->w_ref = std::max(r->w_ref, w);
   }
   const double wref = r->w_ref > 0 ? r->w_ref : w;
-  // the accumulator units are per w_ref; FP32-mixed runs stage the current in
-  // 32-bit LDS words, which bounds w / w_ref at 2
+  // the accumulator units are per w_ref; FP32-mixed runs round each current
+  // contribution to a 32-bit integer before the sums, which bounds w / w_ref at 2
   const double wmax = c.precision == HYB_FP64 ? 64.0 : 2.0;
   if (w / wref > wmax) return fail(r, HYB_EINVAL, "source weight too large for the accumulator scale");
   SourceDesc d{};

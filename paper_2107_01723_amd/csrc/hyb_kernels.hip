@@ -303,26 +303,32 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 // flushed with one atomic per non-zero entry.
 // ---------------------------------------------------------------------------
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
-// (e w_ref c / dx^3), accumulated in 64-bit words.  FP32-mixed runs round each
-// contribution to 2^23 units -- as fine as the FP32 state itself -- so the LDS
-// sums fit 32-bit words, which are widened to the 2^40 HBM accumulators at the
-// flush.  Every contribution is rounded the same way whether it goes through
-// LDS or straight to HBM, so the sums stay independent of the electron order.
+// (e w_ref c / dx^3).  FP32-mixed runs round each contribution to 2^23 units
+// -- as fine as the FP32 state itself -- and widen the sums to the 2^40 HBM
+// accumulators at the flush.  Every contribution is rounded the same way
+// whether it goes through LDS or straight to HBM, so the sums stay
+// independent of the electron order.
 //
-// Electrons of a dense tile hit the same few LDS words; each accumulator has
-// `copies` interleaved copies (lane l adds into copy l % copies), which
-// divides the same-address serialisation of the LDS atomics, at the price of
-// more LDS to clear and sum at the flush.  With 2 copies one 32-bit word takes
-// at most kBlock / 2 = 128 contributions of magnitude below 2^24
-// (w / w_ref <= 2), so it cannot overflow.
+// The LDS words are 64-bit in both precisions: two interleaved copies per
+// node in FP64 (lane l adds into copy l % 2, which halves the same-address
+// serialisation of dense tiles), one in FP32-mixed (the LDS bytes of the two
+// 32-bit copies it had before).  A region's words are flushed at the latest after
+// kMaxCarryChunks chunks (its run of chunks ends, or the carry is cut), so a
+// word sums at most kMaxCarryChunks * kBlock contributions; in FP32 each is
+// below 2^24 in magnitude (w / w_ref <= 2), so the sum stays below 2^44 and,
+// widened by 2^17, below 2^61: no sum can wrap, however long a tile keeps
+// its region over a workgroup's chunks.
 template <typename T> struct JAcc {
   using type = long long;
   static constexpr int shift = 0, copies = 2;
 };
 template <> struct JAcc<float> {
-  using type = int;
-  static constexpr int shift = 17, copies = 2;
+  using type = long long;
+  static constexpr int shift = 17, copies = 1;
 };
+constexpr int kMaxCarryChunks = 4096;
+static_assert((long long)kMaxCarryChunks * kChunk * (1LL << 24) * (1LL << JAcc<float>::shift) < (1LL << 62),
+              "FP32 LDS current sums could wrap");
 constexpr int kHeatCopies = 4;
 constexpr int kLdsTab = 128;   // table rows staged in LDS
 
@@ -788,6 +794,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   unsigned base_val = 0, far_val = 0;
   long long base_at = -1, far_at = -1;
   int carry_js = -1, carry_tile = -1;   // LDS region slot carried over, and its tile
+  int carry_n = 0;                      // chunks the carried region has summed
   int f_tile0 = -1, f_tile1 = -1;       // tiles whose field halos the two LDS slots hold
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
@@ -843,6 +850,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         atomicAdd(&S.tc[slot][my_tile & 15], 1);
         S.tt[slot][my_tile & 15] = my_tile;
       }
+      // electron-steps: the chunk's electrons alive at the start of the step
+      const unsigned long long al = __ballot(cell != kDead);
+      if ((threadIdx.x & 63) == 0 && al) lds_add(&S.led[L_N + C_ESTEPS], (long long)__popcll(al));
     }
     __syncthreads();
     // The homes: the chunk's last tile (it usually continues into the next
@@ -1286,7 +1296,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       // the region of the last tile's home carries over to the next chunk
       // (that tile usually continues there); the rest is flushed
       const bool last = ch + cr.stride >= cr.end;
-      const int keep = last ? -1 : (two ? js_hi : js_lo);
+      int keep = last ? -1 : (two ? js_hi : js_lo);
+      // chunks summed into the kept region; at the bound it is flushed
+      const int n_keep = keep >= 0 && keep == carry_js ? carry_n + 1 : 1;
+      if (n_keep >= kMaxCarryChunks) keep = -1;
+      carry_n = keep >= 0 ? n_keep : 0;
       if (hm.ok && js_lo != keep) lds_flush_region(R, S, js_lo, hm);
       if (two && js_hi != keep) lds_flush_region(R, S, js_hi, hm2);
       if (carry_js >= 0 && carry_js != js_lo && carry_js != js_hi) lds_flush_region(R, S, carry_js, make_home(R, carry_tile));

@@ -29,7 +29,7 @@ def run_scan(requests, ticks_per_poll: int = 8, max_runs: int = 64, hbm_budget: 
     queue = []                     # arrived, waiting for admission
     resident = {}                  # run handle value -> (request index, Run)
     lat, done_at, results = {}, {}, {}
-    particle_steps = 0.0
+    particle_steps = 0            # electrons alive at the start of each step, summed
     t0 = time.perf_counter()
     max_res = 0
     while pending or queue or resident:
@@ -54,7 +54,7 @@ def run_scan(requests, ticks_per_poll: int = 8, max_runs: int = 64, hbm_budget: 
                 lat[i] = now - requests[i]["arrival"]
                 results[i] = dict(conversion=t["conversion"], n_alive=t["n_alive"], step=t["step"],
                                   ledger=t["ledger"])
-                particle_steps += sum(s["n_macro"] for s in requests[i]["srcs"]) * requests[i]["steps"]
+                particle_steps += t["counters"]["n_electron_steps"]
                 eng.retire(r)
                 if verbose:
                     print(f"# run {i:3d} done: latency {lat[i]:7.2f} s, resident {len(resident)}, "
@@ -67,4 +67,4 @@ def run_scan(requests, ticks_per_poll: int = 8, max_runs: int = 64, hbm_budget: 
     L = np.array([lat[i] for i in sorted(lat)])
     return dict(runs=len(L), p50_s=float(np.percentile(L, 50)), p99_s=float(np.percentile(L, 99)),
                 max_s=float(L.max()), wall_s=wall, max_resident=max_res,
-                injected_particle_steps_per_s=particle_steps / wall, results=results)
+                electron_steps=particle_steps, electron_steps_per_s=particle_steps / wall, results=results)

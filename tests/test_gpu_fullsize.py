@@ -18,7 +18,7 @@ import pytest
 import workloads as W
 from oracle import OracleRun
 
-from parity_util import particle_errors
+from parity_util import field_rel, particle_errors, rel
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -198,3 +198,97 @@ def test_fullsize_fp64_urban_scatter(P):
     for k in ("p", "pos", "tau", "w"):
         assert err[k].max() < 1e-10, k
     assert _closure(t) < 1e-6
+
+
+def _box_subset(st, lo, hi, dx):
+    """Electrons whose start-of-step cell lies in the box [lo, hi)."""
+    c = np.floor(st["pos"] / dx).astype(np.int64)
+    sel = np.all((c >= lo) & (c < hi), axis=1)
+    return {k: (st[k][sel] if k in ("pos", "p", "w", "tau", "tau_d", "ids") else st[k]) for k in st}, int(sel.sum())
+
+
+def _pick_boxes(st, cfg, cap=1_500_000):
+    """Two boxes of cells away from the walls: one around the densest 4^3
+    tile (where tiles carry their LDS regions over many chunks) and one
+    around a tile drawn at random from the occupied ones; each is shrunk
+    until it holds at most `cap` electrons."""
+    dx = cfg["dx"]
+    dims = np.array([cfg["nx"], cfg["ny"], cfg["nz"]])
+    c = np.floor(st["pos"] / dx).astype(np.int64)
+    t = c >> 2
+    nt = dims // 4
+    key = t[:, 0] + nt[0] * (t[:, 1] + nt[1] * t[:, 2])
+    u, cnt = np.unique(key, return_counts=True)
+    rng = np.random.default_rng(11)
+    centres = [u[np.argmax(cnt)], u[rng.integers(len(u))]]
+    boxes = []
+    for k in centres:
+        tc = np.array([k % nt[0], (k // nt[0]) % nt[1], k // (nt[0] * nt[1])]) * 4 + 2
+        for half in (8, 6, 5, 4, 3):
+            lo = np.maximum(tc - half, 2)
+            hi = np.minimum(tc + half, dims - 2)
+            n = int(np.sum(np.all((c >= lo) & (c < hi), axis=1)))
+            if n <= cap:
+                break
+        boxes.append((lo, hi, n))
+    return boxes
+
+
+@pytest.mark.parametrize("which,precision,n_pre", [("c2", W.FP64, 30), ("c2", W.FP64, 60),
+                                                   ("c2", W.FP32_MIXED, 60), ("c3", W.FP32_MIXED, 25)])
+def test_fullsize_grid_parity(P, which, precision, n_pre):
+    """Grid side at full size, in the configuration bench.py times.  (1) The
+    hot current and collisional heat of the GPU's step of the whole
+    population, in two boxes (the densest tile's surroundings and a random
+    occupied tile's), against the oracle's step of every electron that
+    starts in the box and of the step's injections: j_h on the nodes only
+    those electrons reach, heat in the box's cells.  (2) The GPU's j_h and heat fed to the oracle's field
+    and heating update from the GPU's start-of-step grid: E, B, Te, Ti and
+    eta over the whole grid."""
+    if which == "c2":
+        cfg, srcs, _ = W.config_fp64_large()
+    else:
+        cfg, srcs, _ = W.config_mixed_large()
+    cfg["precision"] = precision
+    fp64 = precision == W.FP64
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(n_pre)
+    st0 = run.get_state()
+    run.step(1)
+    st1 = run.get_state()
+    run.close()
+    dx = cfg["dx"]
+    print(f"  {which} precision {precision} step {n_pre}: {len(st0['ids'])} electrons", flush=True)
+    tol_j = 1e-10 if fp64 else 1e-5
+    tol_h = 1e-10 if fp64 else 1e-4
+    for lo, hi, n in _pick_boxes(st0, cfg):
+        sub, n = _box_subset(st0, lo, hi, dx)
+        ora = OracleRun(cfg)
+        for s in srcs:           # the electrons this step injects (at the front face) heat the box too
+            ora.add_source(s)
+        ora.set_state(dict(sub, step=st0["step"], next_id=st0["next_id"]))
+        ora.step()
+        ref = ora.state()
+        sl = tuple(slice(lo[d] + 1, hi[d] - 1) for d in range(3))     # nodes [lo+1, hi-2]
+        ej = field_rel([g[sl] for g in st1["j"]], [r[sl] for r in ref["j"]])
+        cl = tuple(slice(lo[d], hi[d]) for d in range(3))
+        eh = rel(st1["ion_heat"][cl], ref["ion_heat"][cl])
+        print(f"  box {lo}-{hi}: {n} electrons, j {ej:.2e}, heat {eh:.2e}", flush=True)
+        assert n > 1000
+        assert ej <= tol_j and eh <= tol_h
+    # the oracle's grid update from the GPU's start-of-step grid and this step's j_h and heat
+    ora = OracleRun(cfg)
+    ora.set_state(dict(pos=np.zeros((0, 3)), p=np.zeros((0, 3)), w=np.zeros(0), tau=np.zeros(0),
+                       ids=np.zeros(0, dtype=np.uint32), E=st0["E"], B=st0["B"], Te=st0["Te"],
+                       Ti=st0["Ti"], eta=st0["eta"]))
+    ora.j = tuple(np.array(x, dtype=np.float64) for x in st1["j"])
+    ora.ion_heat = np.array(st1["ion_heat"], dtype=np.float64)
+    ora.grid_update()
+    s = ora.solid
+    tol_f = 1e-10 if fp64 else 1e-5
+    errs = dict(E=field_rel(st1["E"], ora.E), B=field_rel(st1["B"], ora.B), Te=rel(st1["Te"][s], ora.Te[s]),
+                Ti=rel(st1["Ti"][s], ora.Ti[s]), eta=rel(st1["eta"][s], ora.eta[s]))
+    print("  grid update: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert errs["E"] <= tol_f and errs["B"] <= tol_f
+    assert errs["Te"] <= 1e-10 and errs["Ti"] <= 1e-10 and errs["eta"] <= 1e-10
