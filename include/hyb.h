@@ -421,6 +421,18 @@ const char* hyb_status_string(hyb_status s);
 hyb_status hyb_model_scan(const hyb_model* m, const double* I0, const double* Z, int64_t n,
                           double* out, const hyb_device* dev);
 
+/* hyb_model_scan for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and results, staged through a device array that the
+ * library holds for the life of the process, one copy per GPU (4 MiB), so
+ * no device allocation or free happens in the call.  Same arguments,
+ * ownership and errors as hyb_model_scan, plus HYB_EINVAL when
+ * n > 65536 points or dev->device is outside [0, 64).  The first call on a
+ * device looks up that device's copy.  Calls that overlap on one GPU share
+ * the array and race: serialise them.  Synchronous. */
+hyb_status hyb_model_scan_static(const hyb_model* m, const double* I0, const double* Z, int64_t n,
+                                 double* out, const hyb_device* dev);
+
 /* sizeof of the ABI structs, for bindings to check their layouts:
  * config, source, device, tally_out, state, run_info, envelope, beam, model. */
 void hyb_abi_sizes(int64_t sizes[9]);

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -819,6 +820,68 @@ static hyb_status step_graph(hyb_run* r, int32_t nsteps) {
 }
 
 // ---------------------------------------------------------------------------
+// the energy-partition model scan (Sec. III.B): input checks and the staged
+// run shared by hyb_model_scan and its allocation-free variant
+// ---------------------------------------------------------------------------
+static const char* model_inputs_error(const hyb_model* m, const double* I0, const double* Z, int64_t n,
+                                      const double* out) {
+  if (!m) return "null model";
+  if (n < 0 || n > (1LL << 28)) return "n out of range";
+  if (n == 0) return nullptr;
+  if (!I0 || !Z || !out) return "null array";
+  if (!(m->wavelength > 0) || !(m->eta_l2e > 0) || !(m->r_fwhm > 0) || !(m->t_fwhm > 0) ||
+      !(m->fg_mean > 0) || m->fg_mean > 1 || !(m->sqrt_fg_mean > 0) || m->sqrt_fg_mean > 1 ||
+      !(m->kappa_esc > 0) || !(m->kappa_tnsa >= 0) || !(m->e_th > 0) || !(m->Lx > 0) || !(m->Ly > 0) ||
+      !(m->Lz > 0) || !(m->theta_c >= 0) || !(m->theta_c < 0.5 * kPi) || !(m->eta_mean >= 0) ||
+      !(m->n_i > 0) || m->nsteps < 1 || m->nsteps > 1000000)
+    return "bad model inputs";
+  for (int64_t i = 0; i < n; ++i)
+    if (!(I0[i] > 0) || !std::isfinite(I0[i]) || !(Z[i] >= 1) || !(Z[i] < 200))
+      return "scan point outside I0 > 0, 1 <= Z < 200";
+  return nullptr;
+}
+
+// Inputs in, the model, outputs out, through the device staging buf (8 n
+// doubles: I0, Z, then the 6 n results); waits for the stream.
+static hipError_t model_scan_on(const hyb_model& m, const double* I0, const double* Z, int64_t n, double* out,
+                                double* buf, hipStream_t s) {
+  double* dI = buf;
+  double* dZ = buf + n;
+  double* dout = buf + 2 * n;
+  hipError_t e = hipMemcpyAsync(dI, I0, n * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dZ, Z, n * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    launch_model(m, dI, dZ, n, dout, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 6 * n * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t w = hipStreamSynchronize(s);
+  return e != hipSuccess ? e : w;
+}
+
+// Staging of hyb_model_scan_static: a file-scope device array, one copy per
+// GPU for the life of the process (8 doubles per scan point, 4 MiB).  In
+// host code the array's name is not a device address; the address of the
+// current device's copy comes from hipGetSymbolAddress, looked up once per
+// device and kept in scan_scratch_ptr.
+constexpr int64_t kScanStaticMax = 1 << 16;
+constexpr int kScanStaticDevices = 64;
+static __device__ __align__(256) double scratch[8 * kScanStaticMax];
+static double* scan_scratch_ptr[kScanStaticDevices];
+static std::mutex scan_scratch_mu;
+
+static hyb_status scan_scratch(int device, double** p) {
+  std::lock_guard<std::mutex> lock(scan_scratch_mu);
+  if (!scan_scratch_ptr[device]) {
+    void* q = nullptr;
+    HIPCHK(nullptr, hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+    scan_scratch_ptr[device] = (double*)q;
+  }
+  *p = scan_scratch_ptr[device];
+  return HYB_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -841,19 +904,8 @@ const char* hyb_last_error(const hyb_run* run) { return run ? run->err.c_str() :
 
 hyb_status hyb_model_scan(const hyb_model* m, const double* I0, const double* Z, int64_t n, double* out,
                           const hyb_device* dev) {
-  if (!m) return fail(nullptr, HYB_EINVAL, "null model");
-  if (n < 0 || n > (1LL << 28)) return fail(nullptr, HYB_EINVAL, "n out of range");
+  if (const char* why = model_inputs_error(m, I0, Z, n, out)) return fail(nullptr, HYB_EINVAL, why);
   if (n == 0) return HYB_OK;
-  if (!I0 || !Z || !out) return fail(nullptr, HYB_EINVAL, "null array");
-  if (!(m->wavelength > 0) || !(m->eta_l2e > 0) || !(m->r_fwhm > 0) || !(m->t_fwhm > 0) ||
-      !(m->fg_mean > 0) || m->fg_mean > 1 || !(m->sqrt_fg_mean > 0) || m->sqrt_fg_mean > 1 ||
-      !(m->kappa_esc > 0) || !(m->kappa_tnsa >= 0) || !(m->e_th > 0) || !(m->Lx > 0) || !(m->Ly > 0) ||
-      !(m->Lz > 0) || !(m->theta_c >= 0) || !(m->theta_c < 0.5 * kPi) || !(m->eta_mean >= 0) ||
-      !(m->n_i > 0) || m->nsteps < 1 || m->nsteps > 1000000)
-    return fail(nullptr, HYB_EINVAL, "bad model inputs");
-  for (int64_t i = 0; i < n; ++i)
-    if (!(I0[i] > 0) || !std::isfinite(I0[i]) || !(Z[i] >= 1) || !(Z[i] < 200))
-      return fail(nullptr, HYB_EINVAL, "scan point outside I0 > 0, 1 <= Z < 200");
   hyb_device d{};
   if (dev) d = *dev;
   HIPCHK(nullptr, hipSetDevice(d.device));
@@ -861,20 +913,28 @@ hyb_status hyb_model_scan(const hyb_model* m, const double* I0, const double* Z,
   const size_t bytes = (size_t)n * 8 * sizeof(double);
   double* buf = (double*)dev_alloc(d, bytes);
   if (!buf) return fail(nullptr, HYB_ENOMEM, "device allocation failed");
-  double* dI = buf;
-  double* dZ = buf + n;
-  double* dout = buf + 2 * n;
-  hipError_t e = hipMemcpyAsync(dI, I0, n * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(dZ, Z, n * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) {
-    launch_model(*m, dI, dZ, n, dout, s);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 6 * n * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipStreamSynchronize(s);
+  const hipError_t e = model_scan_on(*m, I0, Z, n, out, buf, s);
   dev_free(d, buf);
   if (e != hipSuccess) return fail(nullptr, HYB_EDEVICE, std::string("hyb_model_scan: ") + hipGetErrorString(e));
+  return HYB_OK;
+}
+
+hyb_status hyb_model_scan_static(const hyb_model* m, const double* I0, const double* Z, int64_t n,
+                                 double* out, const hyb_device* dev) {
+  if (const char* why = model_inputs_error(m, I0, Z, n, out)) return fail(nullptr, HYB_EINVAL, why);
+  if (n > kScanStaticMax)
+    return fail(nullptr, HYB_EINVAL, "n exceeds the static staging of hyb_model_scan_static (65536 points)");
+  if (n == 0) return HYB_OK;
+  hyb_device d{};
+  if (dev) d = *dev;
+  if (d.device < 0 || d.device >= kScanStaticDevices) return fail(nullptr, HYB_EINVAL, "device ordinal out of range");
+  HIPCHK(nullptr, hipSetDevice(d.device));
+  double* buf = nullptr;
+  hyb_status st = scan_scratch(d.device, &buf);
+  if (st != HYB_OK) return st;
+  const hipError_t e = model_scan_on(*m, I0, Z, n, out, buf, (hipStream_t)d.stream);
+  if (e != hipSuccess)
+    return fail(nullptr, HYB_EDEVICE, std::string("hyb_model_scan_static: ") + hipGetErrorString(e));
   return HYB_OK;
 }
 

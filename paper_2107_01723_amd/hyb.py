@@ -30,6 +30,7 @@ ABI_FUNCTIONS = (
     "hyb_init", "hyb_inject", "hyb_inject_envelope", "hyb_inject_beam", "hyb_step", "hyb_tally", "hyb_get_state", "hyb_set_state",
     "hyb_run_info_get", "hyb_table_get", "hyb_timing_enable", "hyb_timing_get", "hyb_use_graph",
     "hyb_footprint", "hyb_free", "hyb_last_error", "hyb_status_string", "hyb_abi_sizes", "hyb_model_scan",
+    "hyb_model_scan_static",
     "hyb_engine_create", "hyb_engine_admit", "hyb_engine_step", "hyb_engine_poll",
     "hyb_engine_retire", "hyb_engine_stats", "hyb_engine_free",
 )
@@ -171,6 +172,8 @@ def lib():
         "hyb_inject_envelope": (C.c_int, [vp, P(Envelope)]),
         "hyb_inject_beam": (C.c_int, [vp, P(Beam)]),
         "hyb_model_scan": (C.c_int, [P(Model), P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double), vp]),
+        "hyb_model_scan_static": (C.c_int, [P(Model), P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double),
+                                            vp]),
         "hyb_step": (C.c_int, [vp, C.c_int32]),
         "hyb_tally": (C.c_int, [vp, P(TallyOut)]),
         "hyb_get_state": (C.c_int, [vp, P(State)]),
@@ -270,6 +273,27 @@ def model_scan(m: dict, I0, Z, device: int = 0, stream=None):
     del mem
     if st != HYB_OK:
         raise HybError(st, "hyb_model_scan: " + lib().hyb_last_error(None).decode())
+    return out.reshape(len(I0), 6).T.copy()
+
+
+def model_scan_static(m: dict, I0, Z, device: int = 0, stream=None):
+    """The same scan through hyb_model_scan_static, which stages through the
+    library's per-GPU device array and allocates no device memory (at most
+    65536 points).  Returns an array [6, n] like model_scan."""
+    I0 = np.ascontiguousarray(np.asarray(I0, dtype=np.float64).ravel())
+    Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).ravel())
+    if I0.shape != Z.shape:
+        raise ValueError("I0 and Z differ in length")
+    mod = Model()
+    for name, _ in Model._fields_:
+        setattr(mod, name, m[name])
+    out = np.zeros(6 * len(I0))
+    dev = Device()
+    dev.device = device
+    dev.stream = stream
+    st = lib().hyb_model_scan_static(C.byref(mod), _dptr(I0), _dptr(Z), len(I0), _dptr(out), C.byref(dev))
+    if st != HYB_OK:
+        raise HybError(st, "hyb_model_scan_static: " + lib().hyb_last_error(None).decode())
     return out.reshape(len(I0), 6).T.copy()
 
 
