@@ -294,63 +294,55 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 
 // ---------------------------------------------------------------------------
 // LDS staging of one chunk of particles.  Particles sorted by tile arrive in
-// chunks of kBlock; a chunk has two home tiles (its last tile and its most
-// populated other one).  Deposits of electrons inside a home tile go to LDS
-// integer accumulators covering the 6x6x6 nodes that tile's stencils can
-// reach and its 4x4x4 cells of collisional heat; destinations are counted in
-// the 5x5x5 tiles around the first home, where its electrons can move in one
-// step; everything else falls back to global atomics.  The LDS sums are
-// flushed with one atomic per non-zero entry.
+// chunks of kBlock; the chunk's most populated tiles (up to kRegions) are its
+// regions.  Deposits of an electron in a region tile go to LDS integer
+// accumulators covering the 6x6x6 nodes that tile's stencils can reach and
+// its 4x4x4 cells of collisional heat; the two most populated regions also
+// stage their field halos for the gather; destinations are counted in the
+// 5x5x5 tiles around the most populated one, where its electrons can move in
+// one step; everything else falls back to global gathers and atomics.  The
+// LDS sums are flushed with one atomic per non-zero entry.
 // ---------------------------------------------------------------------------
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
-// (e w_ref c / dx^3).  FP32-mixed runs round each contribution to 2^23 units
-// -- as fine as the FP32 state itself -- and widen the sums to the 2^40 HBM
-// accumulators at the flush.  Every contribution is rounded the same way
-// whether it goes through LDS or straight to HBM, so the sums stay
+// (e w_ref c / dx^3) in 64-bit LDS words.  FP32-mixed runs round each
+// contribution to 2^20 units and sum them in 32-bit LDS words, widened to the
+// 2^40 HBM accumulators at the flush.  Every contribution is rounded the same
+// way whether it goes through LDS or straight to HBM, so the sums stay
 // independent of the electron order.
 //
-// The LDS words are 64-bit in both precisions: two interleaved copies per
-// node in FP64 (lane l adds into copy l % 2, which halves the same-address
-// serialisation of dense tiles), one in FP32-mixed (the LDS bytes of the two
-// 32-bit copies it had before).  A region's words are flushed at the latest after
-// kMaxCarryChunks chunks (its run of chunks ends, or the carry is cut), so a
-// word sums at most kMaxCarryChunks * kBlock contributions; in FP32 each is
-// below 2^24 in magnitude (w / w_ref <= 2), so the sum stays below 2^44 and,
-// widened by 2^17, below 2^61: no sum can wrap, however long a tile keeps
-// its region over a workgroup's chunks.
+// A region whose tile recurs in the workgroup's next chunk carries its sums
+// over (dense tiles span many chunks), for at most JAcc::max_chunks chunks
+// before a flush.  Bounds: a chunk adds at most kBlock contributions to a
+// word; FP32: each of magnitude at most 2^21 (w / w_ref <= 2), 3 chunks stay
+// below 2^31; FP64: each below 2^46 (w / w_ref <= 64), 31 chunks below 2^59.
 template <typename T> struct JAcc {
   using type = long long;
-  static constexpr int shift = 0, copies = 2;
+  static constexpr int shift = 0, max_chunks = 31;
 };
 template <> struct JAcc<float> {
-  using type = long long;
-  static constexpr int shift = 17, copies = 1;
+  using type = int;
+  static constexpr int shift = 20, max_chunks = 3;
 };
-constexpr int kMaxCarryChunks = 4096;
-static_assert((long long)kMaxCarryChunks * kChunk * (1LL << 24) * (1LL << JAcc<float>::shift) < (1LL << 62),
+static_assert((long long)JAcc<float>::max_chunks * kBlock * 2 * (1LL << (40 - JAcc<float>::shift)) < (1LL << 31),
               "FP32 LDS current sums could wrap");
-constexpr int kHeatCopies = 4;
+static_assert((long long)JAcc<double>::max_chunks * kBlock * 64 * (1LL << 40) < (1LL << 62),
+              "FP64 LDS current sums could wrap");
+constexpr int kRegions = 6;    // LDS regions per chunk
+constexpr int kKeys = 64;      // census keys of a chunk's tiles (one per lane of a wave)
 constexpr int kLdsTab = 128;   // table rows staged in LDS
 
-// A chunk has two home tiles: its last tile and its most populated other
-// one.  Where a tile holds ~200 electrons a tile-sorted chunk of kBlock
-// rarely spans more than two tiles, so nearly all of them deposit into LDS.
-// The reductions that pick the homes (last tile, per-tile counts) use slots
-// that alternate between chunks, so that a chunk's reduction never races the
-// previous chunk's reads.
+// The per-tile counts that pick the regions use slots that alternate between
+// chunks, so that counting the next chunk never races the reads of this one.
 template <typename T>
 struct ChunkLds {
-  // three region slots: the chunk's two homes and the region carried over
-  // from the previous chunk of the workgroup
-  typename JAcc<T>::type J[3][3 * kHaloN * JAcc<T>::copies];
-  long long heat[3][kTile * kTile * kTile * kHeatCopies];
+  typename JAcc<T>::type J[kRegions][3 * kHaloN];
+  long long heat[kRegions][kTile * kTile * kTile];
   unsigned cnt[kNbN];
-  int lo[2], hi[2];
-  int tc[2][16], tt[2][16];   // electrons per tile of the chunk, keyed by tile & 15, and the tile
+  int tc[2][kKeys], tt[2][kKeys];   // electrons per tile of a chunk, by census key, and the tile
   long long led[L_N + C_N];   // rare ledger terms and event counts of the block
   T ph[6][kBlock];            // emitted photon of each lane: k, u (3), |u|, gamma
   T tsig[kLdsTab], tsub[kLdsTab];   // cross-section columns of the tables, if they fit
-  T F[2][6][kHaloN];                // E, B on the 6^3-node halos of the two homes
+  T F[2][6][kHaloN];                // E, B on the 6^3-node halos of the two fullest regions
 };
 
 struct Home {
@@ -386,29 +378,23 @@ __device__ __forceinline__ int nb_bin(const Home& h, int tx, int ty, int tz) {
 
 template <typename T>
 __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
-  for (int t = threadIdx.x; t < 3 * 3 * kHaloN * JAcc<T>::copies; t += kBlock) (&L.J[0][0])[t] = 0;
-  for (int t = threadIdx.x; t < 3 * kTile * kTile * kTile * kHeatCopies; t += kBlock) (&L.heat[0][0])[t] = 0;
+  for (int t = threadIdx.x; t < kRegions * 3 * kHaloN; t += kBlock) (&L.J[0][0])[t] = 0;
+  for (int t = threadIdx.x; t < kRegions * kTile * kTile * kTile; t += kBlock) (&L.heat[0][0])[t] = 0;
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
-  if (threadIdx.x < 2) { L.lo[threadIdx.x] = kNoTile; L.hi[threadIdx.x] = -1; }
-  if (threadIdx.x < 32) { (&L.tc[0][0])[threadIdx.x] = 0; (&L.tt[0][0])[threadIdx.x] = -1; }
+  if (threadIdx.x < 2 * kKeys) { (&L.tc[0][0])[threadIdx.x] = 0; (&L.tt[0][0])[threadIdx.x] = -1; }
   if (threadIdx.x < L_N + C_N) L.led[threadIdx.x] = 0;
 }
 
-// Adds the LDS sums of one home region to HBM (one atomic per non-zero
-// entry) and clears them for the next chunk.
+// Adds the LDS sums of one region to HBM (one atomic per non-zero entry)
+// and clears them for the next chunk.
 template <typename T>
 __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& L, int r, const Home& h) {
-  constexpr int C = JAcc<T>::copies;
   const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
   typename JAcc<T>::type* J = L.J[r];
   for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
-    long long v = 0;
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-      v += (long long)J[t * C + q];
-      J[t * C + q] = 0;
-    }
+    long long v = (long long)J[t];
     if (v == 0) continue;
+    J[t] = 0;
     v *= (1LL << JAcc<T>::shift);
     const int c = t / kHaloN, l = t % kHaloN;
     const int i = h.bx + l % kHalo, j = h.by + (l / kHalo) % kHalo, k = h.bz + l / (kHalo * kHalo);
@@ -416,15 +402,13 @@ __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& 
     atomic_add_i64(&R.J[c][i + sx * j + sxy * k], v);
   }
   if (threadIdx.x < kTile * kTile * kTile) {
-    long long v = 0;
-#pragma unroll
-    for (int q = 0; q < kHeatCopies; ++q) {
-      v += L.heat[r][threadIdx.x * kHeatCopies + q];
-      L.heat[r][threadIdx.x * kHeatCopies + q] = 0;
-    }
+    const long long v = L.heat[r][threadIdx.x];
     const int l = threadIdx.x;
     const int i = kTile * h.tx + (l & 3), j = kTile * h.ty + ((l >> 2) & 3), k = kTile * h.tz + (l >> 4);
-    if (v != 0 && i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.ion_heat[i + R.nx * (j + R.ny * k)], v);
+    if (v != 0) {
+      L.heat[r][threadIdx.x] = 0;
+      if (i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.ion_heat[i + R.nx * (j + R.ny * k)], v);
+    }
   }
 }
 
@@ -457,24 +441,22 @@ __device__ __forceinline__ void deposit8(long long* __restrict__ J, typename JAc
                                          int bx, int by, int bz, int sx, int sxy, const Axis<T>& ax,
                                          const Axis<T>& ay, const Axis<T>& az, T amp) {
   using A = typename JAcc<T>::type;
-  constexpr int C = JAcc<T>::copies;
   const T a00 = amp * az.w0 * ay.w0, a10 = amp * az.w0 * ay.w1;
   const T a01 = amp * az.w1 * ay.w0, a11 = amp * az.w1 * ay.w1;
   const A v[8] = {jfix(a00 * ax.w0), jfix(a00 * ax.w1), jfix(a10 * ax.w0), jfix(a10 * ax.w1),
                   jfix(a01 * ax.w0), jfix(a01 * ax.w1), jfix(a11 * ax.w0), jfix(a11 * ax.w1)};
   if (Js) {
-    const int q = threadIdx.x & (C - 1);
     const int i0 = ax.i0 - bx, i1 = ax.i1 - bx;
     const int j0 = (ay.i0 - by) * kHalo, j1 = (ay.i1 - by) * kHalo;
     const int k0 = (az.i0 - bz) * kHalo * kHalo, k1 = (az.i1 - bz) * kHalo * kHalo;
-    lds_add(&Js[(i0 + j0 + k0) * C + q], v[0]);
-    lds_add(&Js[(i1 + j0 + k0) * C + q], v[1]);
-    lds_add(&Js[(i0 + j1 + k0) * C + q], v[2]);
-    lds_add(&Js[(i1 + j1 + k0) * C + q], v[3]);
-    lds_add(&Js[(i0 + j0 + k1) * C + q], v[4]);
-    lds_add(&Js[(i1 + j0 + k1) * C + q], v[5]);
-    lds_add(&Js[(i0 + j1 + k1) * C + q], v[6]);
-    lds_add(&Js[(i1 + j1 + k1) * C + q], v[7]);
+    lds_add(&Js[i0 + j0 + k0], v[0]);
+    lds_add(&Js[i1 + j0 + k0], v[1]);
+    lds_add(&Js[i0 + j1 + k0], v[2]);
+    lds_add(&Js[i1 + j1 + k0], v[3]);
+    lds_add(&Js[i0 + j0 + k1], v[4]);
+    lds_add(&Js[i1 + j0 + k1], v[5]);
+    lds_add(&Js[i0 + j1 + k1], v[6]);
+    lds_add(&Js[i1 + j1 + k1], v[7]);
   } else {
     constexpr long long up = 1LL << JAcc<T>::shift;
     const int r00 = ay.i0 * sx + az.i0 * sxy, r10 = ay.i1 * sx + az.i0 * sxy;
@@ -736,6 +718,77 @@ __device__ __forceinline__ double urban_one_minus_cos(const RunDesc& R, double u
   return -log1p(-(1.0 - ub) * -expm1(-2.0 * a)) / a;
 }
 
+// Counts a chunk's electrons per start-of-step tile into census slot q, and
+// its electron-steps.  The kKeys keys are the tile's x index mod 16 and its y
+// and z indices mod 2, so that sixteen tiles in a row along x (a sparse
+// chunk's tiles) or a 2x2 block across y and z (the tiles of an injection
+// spot) never share a key.
+template <typename T>
+__device__ __forceinline__ void chunk_census(const RunDesc& R, ChunkLds<T>& S, uint32_t cell, int q) {
+  if (cell != kDead) {
+    const int i = cell_i(cell), j = cell_j(cell), k = cell_k(cell);
+    const int key = ((i >> 2) & 15) | (((j >> 2) & 1) << 4) | (((k >> 2) & 1) << 5);
+    atomicAdd(&S.tc[q][key], 1);
+    S.tt[q][key] = tile_of(R, i, j, k);
+  }
+  const unsigned long long al = __ballot(cell != kDead);
+  if ((threadIdx.x & 63) == 0 && al) lds_add(&S.led[L_N + C_ESTEPS], (long long)__popcll(al));
+}
+
+// The regions of a chunk from its census (slot q): each region of the
+// previous chunk (tile rt[k], cn holding 5 bits per slot: the chunks it has
+// summed) whose tile recurs keeps its slot and its sums, up to the carry
+// bound; the most populated other tiles take the free slots.  Returns the
+// tiles (nrt), their chunk counts (ncn), the slots carried over (kept) and
+// the two fullest tiles (ta, tb).  Tiles sharing a census key pool their
+// counts: a worse pick, never a wrong one.  Every wave makes the same picks.
+template <typename T>
+__device__ __forceinline__ void pick_regions(const ChunkLds<T>& S, int q, const int (&rt)[kRegions], int cn,
+                                             int (&nrt)[kRegions], int& ncn, int& kept, int& ta, int& tb) {
+  const int l = threadIdx.x & 63;
+  const int t = S.tt[q][l];
+  int c = t >= 0 ? S.tc[q][l] : 0;
+  int a = -1, b = -1, na = 0, nb = 0, m_cn = 0, m_kept = 0;   // fullest two (tile, count)
+#pragma unroll
+  for (int k = 0; k < kRegions; ++k) {
+    nrt[k] = -1;
+    const int m = (cn >> (5 * k)) & 31;
+    if (rt[k] < 0 || m >= JAcc<T>::max_chunks) continue;
+    int cc = t == rt[k] ? c : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cc = max(cc, __shfl_xor(cc, o, 64));
+    cc = __builtin_amdgcn_readfirstlane(cc);
+    if (cc == 0) continue;
+    nrt[k] = rt[k];
+    m_cn |= (m + 1) << (5 * k);
+    m_kept |= 1 << k;
+    if (cc > na) { b = a; nb = na; a = rt[k]; na = cc; }
+    else if (cc > nb) { b = rt[k]; nb = cc; }
+    if (t == rt[k]) c = 0;
+  }
+  bool more = true;   // tiles left to place (no early exit: every slot index stays static)
+#pragma unroll
+  for (int k = 0; k < kRegions; ++k) {
+    if (!more || nrt[k] >= 0) continue;
+    int key = c > 0 ? (c << 6) | l : -1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) key = max(key, __shfl_xor(key, o, 64));
+    key = __builtin_amdgcn_readfirstlane(key);
+    if (key < 0) { more = false; continue; }
+    const int tile = __builtin_amdgcn_readfirstlane(__shfl(t, key & 63, 64));
+    const int cnt = key >> 6;
+    nrt[k] = tile;
+    m_cn |= 1 << (5 * k);
+    if (cnt > na) { b = a; nb = na; a = tile; na = cnt; }
+    else if (cnt > nb) { b = tile; nb = cnt; }
+    if (l == (key & 63)) c = 0;
+  }
+  ncn = m_cn;
+  kept = m_kept;
+  ta = a;
+  tb = b;
+}
+
 // ---------------------------------------------------------------------------
 // the particle step: gather, Boris, deposit, move, ionisation,
 // bremsstrahlung, elastic scatter, boundaries, low-energy removal
@@ -793,9 +846,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   // tile offsets returned by the counting atomics, stored a chunk later
   unsigned base_val = 0, far_val = 0;
   long long base_at = -1, far_at = -1;
-  int carry_js = -1, carry_tile = -1;   // LDS region slot carried over, and its tile
-  int carry_n = 0;                      // chunks the carried region has summed
   int f_tile0 = -1, f_tile1 = -1;       // tiles whose field halos the two LDS slots hold
+  // The regions: the chunk's most populated tiles, up to kRegions, each with
+  // an LDS slot for its electrons' current and heat.  A chunk of tile-sorted
+  // electrons spans one tile where ~200 electrons share a tile and several
+  // where few do (3 at the median, 7 at the 90th percentile at ~55 per
+  // tile); the newly injected electrons at the buffer's tail are not yet
+  // sorted and spread over the tiles of the injection spot.  The regions of
+  // the next chunk are picked at the end of this one, from the cells already
+  // prefetched, so that regions whose tile continues keep their sums and the
+  // others are flushed while the next chunk's state is in flight.
+  int rt[kRegions], fl[kRegions];   // tile of each slot now; tile to flush from each slot (-1 none)
+  int cn = 0, ta = -1, tb = -1;     // chunk counts per slot; the two fullest tiles
+  int pta = -1;                     // fullest tile of the previous chunk (its destination bins)
+  constexpr bool kFlushEarly = sizeof(T) == 8;
+  long long pch = -1;               // the previous chunk
+#pragma unroll
+  for (int k = 0; k < kRegions; ++k) { rt[k] = -1; fl[k] = -1; }
+  if (cr.beg < cr.end) {
+    chunk_census(R, S, cell_next, 0);
+    __syncthreads();
+    int nrt[kRegions], kept;
+    pick_regions<T>(S, 0, rt, 0, nrt, cn, kept, ta, tb);
+#pragma unroll
+    for (int k = 0; k < kRegions; ++k) rt[k] = nrt[k];
+  }
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
     const long long i = ch * kBlock + threadIdx.x;
@@ -805,7 +880,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       cell_next = ch + cr.stride < cr.end && in < n ? P.cell[in] : kDead;
     }
     int ci = 0, cj = 0, ck = 0, my_tile = -1;
-    // the electron's state is in flight while the chunk's homes are reduced
+    // the electron's state is in flight while the previous chunk's regions are flushed
     T ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, wn = 0, tau = 0, taud = 0;
     uint32_t id = 0;
     if (cell != kDead) {
@@ -835,85 +910,42 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         if (phys & PHYS_DELTA) taud = P.taud[i];
       }
     }
-    {
-      int lo = cell != kDead ? my_tile : kNoTile, hi = my_tile;
+    // the previous chunk's regions that do not carry over, and its
+    // destination counts, go to HBM while this chunk's state is in flight
+    // (FP64 flushed them at the previous chunk's end: it has no registers to
+    // spare for the state loads in flight)
+    if (!kFlushEarly && pch >= 0) {
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o, 64));
-        hi = max(hi, __shfl_xor(hi, o, 64));
-      }
-      if ((threadIdx.x & 63) == 0) {
-        if (lo != kNoTile) atomicMin(&S.lo[slot], lo);
-        if (hi >= 0) atomicMax(&S.hi[slot], hi);
-      }
-      if (cell != kDead) {
-        atomicAdd(&S.tc[slot][my_tile & 15], 1);
-        S.tt[slot][my_tile & 15] = my_tile;
-      }
-      // electron-steps: the chunk's electrons alive at the start of the step
-      const unsigned long long al = __ballot(cell != kDead);
-      if ((threadIdx.x & 63) == 0 && al) lds_add(&S.led[L_N + C_ESTEPS], (long long)__popcll(al));
+      for (int k = 0; k < kRegions; ++k)
+        if (fl[k] >= 0) lds_flush_region(R, S, k, make_home(R, fl[k]));
+      if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
     }
     __syncthreads();
-    // The homes: the chunk's last tile (it usually continues into the next
-    // chunk, which inherits its LDS sums) and the most populated other tile.
-    // Where few electrons share a tile a chunk spans several, and its first
-    // and last are cut by the chunk's ends, so the fullest tile in between
-    // keeps more deposits and gathers in LDS.  Tiles sharing a key (t & 15)
-    // pool their counts: a worse pick, never a wrong one.
-    const int thi = __builtin_amdgcn_readfirstlane(S.hi[slot]);
-    int tlo;
-    {
-      const int l = threadIdx.x & 63;
-      int c = l < 16 ? S.tc[slot][l] : -1;
-      const int t = l < 16 ? S.tt[slot][l] : -1;
-      if (t == thi) c = 0;
-      int key = c * 64 + l;
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) key = max(key, __shfl_xor(key, o, 64));
-      key = __builtin_amdgcn_readfirstlane(key);
-      const int tb = __shfl(t, key & 63, 64);
-      tlo = __builtin_amdgcn_readfirstlane((key >> 6) > 0 && tb >= 0 ? tb : S.lo[slot]);
-    }
-    // the other slot was last read before the previous chunk's flush
-    if (threadIdx.x == 0) { S.lo[slot ^ 1] = kNoTile; S.hi[slot ^ 1] = -1; }
-    if (threadIdx.x < 16) { S.tc[slot ^ 1][threadIdx.x] = 0; S.tt[slot ^ 1][threadIdx.x] = -1; }
-    const Home hm = make_home(R, tlo), hm2 = make_home(R, thi);
-    // LDS region slots of the homes: a home that is the tile carried over
-    // keeps its slot (its sums go on accumulating), the others take clean slots
-    const bool two = hm2.ok && thi != tlo;
-    int js_lo = -1, js_hi = -1;
-    if (hm.ok) js_lo = carry_js >= 0 && carry_tile == tlo ? carry_js : (carry_js == 0 ? 1 : 0);
-    if (two) {
-      if (carry_js >= 0 && carry_tile == thi) js_hi = carry_js;
-      else {
-        js_hi = 0;
-        while (js_hi == js_lo || js_hi == carry_js) ++js_hi;
-      }
-    }
-    // LDS field-halo slot of each home (fields do not change during the launch)
-    int fs_lo = -1, fs_hi = -1;
+    // this chunk's census was read when its regions were picked
+    if (threadIdx.x < kKeys) { S.tc[slot][threadIdx.x] = 0; S.tt[slot][threadIdx.x] = -1; }
+    const Home hm = make_home(R, ta), hm2 = make_home(R, tb);
     if (phys & PHYS_FIELDS) {
-      // a home whose halo a slot already holds keeps it; a new one takes the
-      // other home's free slot, else the slot of the smaller (older) tile
-      if (hm.ok) fs_lo = f_tile0 == tlo ? 0 : (f_tile1 == tlo ? 1 : -1);
-      if (two) fs_hi = f_tile0 == thi ? 0 : (f_tile1 == thi ? 1 : -1);
-      const bool need_lo = hm.ok && fs_lo < 0;
-      if (need_lo) fs_lo = fs_hi >= 0 ? 1 - fs_hi : (f_tile0 <= f_tile1 ? 0 : 1);
-      const bool need_hi = two && fs_hi < 0;
-      if (need_hi) fs_hi = 1 - fs_lo;
-      const int nst = (need_lo ? 1 : 0) + (need_hi ? 1 : 0);
+      // a region whose halo a slot already holds keeps it (fields do not
+      // change during the launch); a new one takes the other region's free
+      // slot, else the slot of the smaller (older) tile
+      int fs_a = !hm.ok ? -1 : (f_tile0 == ta ? 0 : (f_tile1 == ta ? 1 : -1));
+      int fs_b = !hm2.ok ? -1 : (f_tile0 == tb ? 0 : (f_tile1 == tb ? 1 : -1));
+      const bool need_a = hm.ok && fs_a < 0;
+      if (need_a) fs_a = fs_b >= 0 ? 1 - fs_b : (f_tile0 <= f_tile1 ? 0 : 1);
+      const bool need_b = hm2.ok && fs_b < 0;
+      if (need_b) fs_b = 1 - fs_a;
+      const int nst = (need_a ? 1 : 0) + (need_b ? 1 : 0);
       if (nst) {
         // the new halos, staged in LDS: the six field loads of a node are
         // issued together (rows of 6 nodes along x are contiguous in HBM);
         // nodes outside the grid are never gathered
 #pragma unroll 1
         for (int t = threadIdx.x; t < nst * kHaloN; t += kBlock) {
-          const bool is_lo = need_lo && t < kHaloN;
+          const bool is_a = need_a && t < kHaloN;
           const int l = t >= kHaloN ? t - kHaloN : t;
-          const int i = (is_lo ? hm.bx : hm2.bx) + l % kHalo;
-          const int j = (is_lo ? hm.by : hm2.by) + (l / kHalo) % kHalo;
-          const int k = (is_lo ? hm.bz : hm2.bz) + l / (kHalo * kHalo);
+          const int i = (is_a ? hm.bx : hm2.bx) + l % kHalo;
+          const int j = (is_a ? hm.by : hm2.by) + (l / kHalo) % kHalo;
+          const int k = (is_a ? hm.bz : hm2.bz) + l / (kHalo * kHalo);
           const bool in = i >= 0 && j >= 0 && k >= 0 && i <= nx && j <= ny && k <= nz;
           const long long o = in ? i + (long long)sx * j + (long long)sxy * k : 0;
           T v[6];
@@ -923,37 +955,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
           v[3] = in ? B0[o] : (T)0;
           v[4] = in ? B1[o] : (T)0;
           v[5] = in ? B2[o] : (T)0;
-          T* d = &S.F[is_lo ? fs_lo : fs_hi][0][l];
+          T* d = &S.F[is_a ? fs_a : fs_b][0][l];
 #pragma unroll
           for (int f = 0; f < 6; ++f) d[f * kHaloN] = v[f];
         }
-        if (need_lo) { if (fs_lo == 0) f_tile0 = tlo; else f_tile1 = tlo; }
-        if (need_hi) { if (fs_hi == 0) f_tile0 = thi; else f_tile1 = thi; }
+        if (need_a) { if (fs_a == 0) f_tile0 = ta; else f_tile1 = ta; }
+        if (need_b) { if (fs_b == 0) f_tile0 = tb; else f_tile1 = tb; }
         __syncthreads();
       }
     }
-    // A third region: the one carried over from the previous chunk, when its
-    // tile (usually this chunk's first) is neither home.  Its electrons still
-    // deposit into it (it is flushed at the chunk's end) and gather from its
-    // halo if that is still staged.  FP32 only: FP64 has no registers to
-    // spare at two waves per SIMD (with it, 2 spills and 0.7 % slower).
-    constexpr bool kThird = sizeof(T) == 4;
-    const bool use_c = kThird && carry_js >= 0 && carry_tile != tlo && carry_tile != thi;
-    const Home hmc = make_home(R, use_c ? carry_tile : tlo);
-    const int fs_c = !use_c ? -1 : (f_tile0 == carry_tile ? 0 : (f_tile1 == carry_tile ? 1 : -1));
     // offsets returned by the previous chunk's atomics: waiting for them here
     // costs nothing, this chunk's loads (issued later) have landed
     if (base_at >= 0) { G(R.chunk_base)[base_at] = base_val; base_at = -1; }
     if (far_at >= 0) { G(R.far_off)[far_at] = far_val; far_at = -1; }
     int dest_bin = -1;
     if (cell != kDead) {
-      // LDS region of the electron: 0 (the fullest tile), 1 (the last), 2 (the
-      // carried one), -1 none
-      const int reg = my_tile == tlo ? 0 : (my_tile == thi ? 1 : (use_c && my_tile == carry_tile ? 2 : -1));
-      const int rbx = reg == 1 ? hm2.bx : (reg == 2 ? hmc.bx : hm.bx);
-      const int rby = reg == 1 ? hm2.by : (reg == 2 ? hmc.by : hm.by);
-      const int rbz = reg == 1 ? hm2.bz : (reg == 2 ? hmc.bz : hm.bz);
-      const int js = reg == 0 ? js_lo : (reg == 1 ? js_hi : (reg == 2 ? carry_js : -1));
+      // LDS slot of the electron's tile (-1: none), the first node of that
+      // tile's halo, and the staged field halo of the tile (-1: none)
+      int js = -1;
+#pragma unroll
+      for (int k = 0; k < kRegions; ++k) js = my_tile == rt[k] ? k : js;
+      const int rbx = (ci & ~(kTile - 1)) - 1, rby = (cj & ~(kTile - 1)) - 1, rbz = (ck & ~(kTile - 1)) - 1;
+      const int fsl = my_tile == f_tile0 ? 0 : (my_tile == f_tile1 ? 1 : -1);
       typename JAcc<T>::type* Js = js >= 0 ? S.J[js] : nullptr;
       const int heat_cell = ci + nx * (cj + ny * ck);
       const int heat_local = (ci & 3) + 4 * (cj & 3) + 16 * (ck & 3);
@@ -968,8 +991,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       // --- gather + Boris push (q = -e) ---
       if (phys & PHYS_FIELDS) {
         T Ex, Ey, Ez, Bx, By, Bz;
-        if (reg >= 0 && (reg < 2 || fs_c >= 0)) {   // from a halo staged in LDS
-          const T* F = &S.F[reg == 0 ? fs_lo : (reg == 1 ? fs_hi : fs_c)][0][0];
+        if (fsl >= 0) {   // from a halo staged in LDS
+          const T* F = &S.F[fsl][0][0];
           Ex = gather8_lds(F, rbx, rby, rbz, sxa, nya, nza);
           Ey = gather8_lds(F + kHaloN, rbx, rby, rbz, nxa, sya, nza);
           Ez = gather8_lds(F + 2 * kHaloN, rbx, rby, rbz, nxa, nya, sza);
@@ -1009,7 +1032,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       // --- hot-current deposit at x^n with the pushed velocity ---
       {
         const T amp = -wn * (T)(kJScale / (double)(1LL << JAcc<T>::shift));
-        constexpr int CN = kHaloN * JAcc<T>::copies;
+        constexpr int CN = kHaloN;
         deposit8(R.J[0], Js, rbx, rby, rbz, sx, sxy, sxa, nya, nza, amp * vx);
         deposit8(R.J[1], Js ? Js + CN : Js, rbx, rby, rbz, sx, sxy, nxa, sya, nza, amp * vy);
         deposit8(R.J[2], Js ? Js + 2 * CN : Js, rbx, rby, rbz, sx, sxy, nxa, nya, sza, amp * vz);
@@ -1245,8 +1268,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
         alive = false;
       }
       if (heat != 0) {
-        if (reg >= 0)
-          lds_add(&S.heat[js][heat_local * kHeatCopies + (threadIdx.x & (kHeatCopies - 1))], heat);
+        if (js >= 0)
+          lds_add(&S.heat[js][heat_local], heat);
         else atomic_add_i64(&R.ion_heat[heat_cell], heat);
       }
       if (!alive) {
@@ -1289,28 +1312,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       if ((threadIdx.x & 63) == 0 && same) atomicAdd(&S.cnt[lead], (unsigned)__popcll(same));
       if (dest_bin >= 0 && dest_bin != lead) atomicAdd(&S.cnt[dest_bin], 1u);
     }
+    if (count && threadIdx.x == 0) G(R.chunk_home)[ch] = hm.ok ? ta : kNoTile;
+    // the next chunk's census and regions
+    chunk_census(R, S, cell_next, slot ^ 1);
     __syncthreads();
-    // LDS sums to HBM; the flush also clears them, and the next chunk writes
-    // LDS only after its own barrier
     {
-      // the region of the last tile's home carries over to the next chunk
-      // (that tile usually continues there); the rest is flushed
-      const bool last = ch + cr.stride >= cr.end;
-      int keep = last ? -1 : (two ? js_hi : js_lo);
-      // chunks summed into the kept region; at the bound it is flushed
-      const int n_keep = keep >= 0 && keep == carry_js ? carry_n + 1 : 1;
-      if (n_keep >= kMaxCarryChunks) keep = -1;
-      carry_n = keep >= 0 ? n_keep : 0;
-      if (hm.ok && js_lo != keep) lds_flush_region(R, S, js_lo, hm);
-      if (two && js_hi != keep) lds_flush_region(R, S, js_hi, hm2);
-      if (carry_js >= 0 && carry_js != js_lo && carry_js != js_hi) lds_flush_region(R, S, carry_js, make_home(R, carry_tile));
-      carry_js = keep;
-      carry_tile = keep < 0 ? -1 : (two ? thi : tlo);
+      int nrt[kRegions], ncn, kept, nta, ntb;
+      pick_regions<T>(S, slot ^ 1, rt, cn, nrt, ncn, kept, nta, ntb);
+#pragma unroll
+      for (int k = 0; k < kRegions; ++k) {
+        fl[k] = rt[k] >= 0 && !((kept >> k) & 1) ? rt[k] : -1;
+        rt[k] = nrt[k];
+      }
+      cn = ncn;
+      pta = ta; ta = nta; tb = ntb;
+      pch = ch;
     }
-    if (count) {
-      lds_flush_counts(R, S, hm, ch, base_val, base_at);
-      if (threadIdx.x == 0) G(R.chunk_home)[ch] = tlo;
+    if (kFlushEarly) {
+#pragma unroll
+      for (int k = 0; k < kRegions; ++k)
+        if (fl[k] >= 0) lds_flush_region(R, S, k, make_home(R, fl[k]));
+      if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
     }
+  }
+  // the last chunk's regions and destination counts
+  if (!kFlushEarly && pch >= 0) {
+#pragma unroll
+    for (int k = 0; k < kRegions; ++k)
+      if (fl[k] >= 0) lds_flush_region(R, S, k, make_home(R, fl[k]));
+    if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
   }
   if (base_at >= 0) G(R.chunk_base)[base_at] = base_val;
   if (far_at >= 0) G(R.far_off)[far_at] = far_val;
