@@ -288,6 +288,10 @@ static void fill_desc(hyb_run* r) {
   h.seed = c.seed;
   h.nodes = (long long)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
   h.cells = (long long)c.nx * c.ny * c.nz;
+  h.fd_sx = make_fastdiv((uint32_t)(c.nx + 1));
+  h.fd_sy = make_fastdiv((uint32_t)(c.ny + 1));
+  h.fd_w = make_fastdiv((uint32_t)(h.ix_hi - h.ix_lo));
+  h.fd_ny = make_fastdiv((uint32_t)c.ny);
   h.capacity = c.max_particles;
   h.dx = c.dx; h.dt = c.dt;
   const double n_i = c.rho / (c.A * kAmu);
@@ -768,6 +772,7 @@ static hyb_status ensure_single_plans(hyb_run* r) {
   r->L.sort = r->h.sort_every > 0;
   r->L.delta = (r->h.physics & PHYS_DELTA) != 0;
   r->L.urban = (r->h.physics & PHYS_URBAN) != 0;
+  r->L.compound = r->h.mix.n > 1;
   if (!r->side) {
     HIPCHK(r, hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking));
     HIPCHK(r, hipStreamCreateWithFlags(&r->side2, hipStreamNonBlocking));
@@ -1376,6 +1381,7 @@ static hyb_status eng_rebuild(hyb_engine* e, int p) {
     if (e->slots[p][s] && e->slots[p][s]->h.sort_every > 0) e->L[p].sort = true;
     if (e->slots[p][s] && (e->slots[p][s]->h.physics & PHYS_DELTA)) e->L[p].delta = true;
     if (e->slots[p][s] && (e->slots[p][s]->h.physics & PHYS_URBAN)) e->L[p].urban = true;
+    if (e->slots[p][s] && e->slots[p][s]->h.mix.n > 1) e->L[p].compound = true;
   }
   hyb_run tmp;
   hyb_status st = upload_plans(&tmp, e->stream, ps, e->L[p], &e->d_maps[p], &e->maps_bytes[p], e->dev);

@@ -58,6 +58,23 @@ __host__ __device__ __forceinline__ int cell_i(uint32_t c) { return (int)(c & 0x
 __host__ __device__ __forceinline__ int cell_j(uint32_t c) { return (int)((c >> 11) & 0x3FFu); }
 __host__ __device__ __forceinline__ int cell_k(uint32_t c) { return (int)(c >> 21); }
 
+// Division of 32-bit unsigned values by a run constant d >= 1 through a
+// multiply-high: q = (umulhi(t, m) + t) >> s with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1 (the round-up multiplier of Granlund and
+// Montgomery), exact for every t < 2^32 with the sum taken in 64 bits.  The
+// grid kernels turn flat node and cell indices into (i, j, k) with it
+// instead of 64-bit divisions.
+struct FastDiv {
+  uint32_t m, s;
+  __host__ __device__ __forceinline__ uint32_t div(uint32_t t) const;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t s = 0;
+  while (((uint64_t)1 << s) < d) ++s;
+  const uint64_t m = (((((uint64_t)1) << s) - d) << 32) / d + 1;
+  return FastDiv{(uint32_t)m, s};
+}
+
 // Injection schedule and sampling parameters of one source (normalised units:
 // lengths in cells, energies in m c^2).
 struct SourceDesc {
@@ -129,6 +146,8 @@ struct Mix {
 // Read-only description of one run (device memory; one per resident run).
 struct RunDesc {
   int nx, ny, nz, ix_lo, ix_hi;
+  FastDiv fd_sx, fd_sy;   // by nx + 1 and ny + 1 (node index -> i, j, k)
+  FastDiv fd_w, fd_ny;    // by the slab width ix_hi - ix_lo and ny (solid cell index -> i, j, k)
   int n_sub, precision, nsrc;
   uint32_t physics, seed;
   long long nodes, cells, capacity;
@@ -258,6 +277,10 @@ __host__ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t
     k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
   }
   return U4{c0, c1, c2, c3};
+}
+
+__host__ __device__ __forceinline__ uint32_t FastDiv::div(uint32_t t) const {
+  return (uint32_t)(((uint64_t)mulhi32(t, m) + t) >> s);
 }
 
 // 23-bit uniform strictly inside (0, 1), exact in FP32 and FP64

@@ -26,6 +26,7 @@ struct LaunchSet {
   bool sort = false;                                  // some run sorts its particles
   bool delta = false;                                 // some run has delta rays
   bool urban = false;                                 // some run has the Urban-type scatter
+  bool compound = false;                              // some run's solid has several elements
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;   // optional timing of the particle kernel
   // optional streams (default priority) and the events that fork the field
   // sub-cycles and the heating onto them beside the sort, and join them back

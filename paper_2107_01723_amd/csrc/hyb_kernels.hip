@@ -1640,7 +1640,9 @@ __global__ __launch_bounds__(kBlock) void k_zero_step(const RunDesc* __restrict_
   const long long nt = sort_step(R.sort_every, ctr->step) ? R.ntiles : 0;
   const long long tot = 3 * nn + R.cells + nt;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
-    if (t < 3 * nn) G(R.J[t / nn])[t % nn] = 0;
+    if (t < nn) G(R.J[0])[t] = 0;
+    else if (t < 2 * nn) G(R.J[1])[t - nn] = 0;
+    else if (t < 3 * nn) G(R.J[2])[t - 2 * nn] = 0;
     else if (t < 3 * nn + R.cells) G(R.ion_heat)[t - 3 * nn] = 0;
     else G(R.tile_cnt)[t - 3 * nn - R.cells] = 0;
   }
@@ -1663,13 +1665,13 @@ __global__ __launch_bounds__(kBlock) void k_ohm(const RunDesc* __restrict__ runs
                               Jz = G((const long long*)R.J[2]);
   const gptr<const double> eta = G((const double*)R.eta[G(R.ctr)->step & 1]);
   const double inv_dx = 1.0 / R.dx, inv_mu0 = 1.0 / kMu0, ju = R.j_unit;
-  const long long nn = R.nodes;
+  const uint32_t nn = (uint32_t)R.nodes;   // < 2^31 (checked at init)
   auto ce = [&](int i, int j, int k) { return eta[i + nx * (j + ny * k)]; };
-  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < nn; t += (long long)bm.nb * kBlock) {
-    const int i = (int)(t % sx);
-    const long long q = t / sx;
-    const int j = (int)(q % (ny + 1));
-    const int k = (int)(q / (ny + 1));
+  for (uint32_t t = bm.lb * kBlock + threadIdx.x; t < nn; t += bm.nb * kBlock) {
+    const uint32_t q = R.fd_sx.div(t), kk = R.fd_sy.div(q);
+    const int i = (int)(t - q * (uint32_t)sx);
+    const int j = (int)(q - kk * (uint32_t)(ny + 1));
+    const int k = (int)kk;
     const int idx = (int)t;
     const int jm = clampi(j - 1, 0, ny - 1), jc = clampi(j, 0, ny - 1);
     const int km = clampi(k - 1, 0, nz - 1), kc = clampi(k, 0, nz - 1);
@@ -1716,12 +1718,12 @@ __global__ __launch_bounds__(kBlock) void k_faraday(const RunDesc* __restrict__ 
   const gptr<const T> Ex = G((const T*)R.E[0]), Ey = G((const T*)R.E[1]), Ez = G((const T*)R.E[2]);
   const gptr<T> Bx = G((T*)R.B[0]), By = G((T*)R.B[1]), Bz = G((T*)R.B[2]);
   const T h = (T)(R.dt / R.n_sub / R.dx);
-  const long long nn = R.nodes;
-  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < nn; t += (long long)bm.nb * kBlock) {
-    const int i = (int)(t % sx);
-    const long long q = t / sx;
-    const int j = (int)(q % (ny + 1));
-    const int k = (int)(q / (ny + 1));
+  const uint32_t nn = (uint32_t)R.nodes;   // < 2^31 (checked at init)
+  for (uint32_t t = bm.lb * kBlock + threadIdx.x; t < nn; t += bm.nb * kBlock) {
+    const uint32_t q = R.fd_sx.div(t), kk = R.fd_sy.div(q);
+    const int i = (int)(t - q * (uint32_t)sx);
+    const int j = (int)(q - kk * (uint32_t)(ny + 1));
+    const int k = (int)kk;
     const int idx = (int)t;
     if (j < ny && k < nz)   // Bx: dEz/dy - dEy/dz
       Bx[idx] -= h * ((Ez[idx + sx] - Ez[idx]) - (Ey[idx + sxy] - Ey[idx]));
@@ -1732,7 +1734,10 @@ __global__ __launch_bounds__(kBlock) void k_faraday(const RunDesc* __restrict__ 
   }
 }
 
-// Ohmic + collisional heating, exchange and resistivity of the solid cells (FP64)
+// Ohmic + collisional heating, exchange and resistivity of the solid cells
+// (FP64).  MIX: some run of the launch has a compound solid (the
+// single-element instance keeps the compound code out of its registers).
+template <bool MIX>
 __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ runs,
                                                  const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
@@ -1741,7 +1746,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
   const int nx = R.nx, ny = R.ny;
   const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
   const int w = R.ix_hi - R.ix_lo;
-  const long long ns = (long long)w * ny * R.nz;
+  const uint32_t ns = (uint32_t)w * ny * R.nz;   // < 2^31 (checked at init)
   const double ju = 0.25 * R.j_unit, dV = R.dx * R.dx * R.dx;
   const bool fixed = R.eta_fixed > 0.0;
   const bool want_fs = (R.physics & PHYS_FSIGMA) != 0;
@@ -1750,12 +1755,12 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
   const long long step = G(R.ctr)->step;
   const gptr<const double> eta_in = G((const double*)R.eta[step & 1]);
   const gptr<double> eta_out = G(R.eta[(step + 1) & 1]);
-  const Solid sol = R.solid;
-  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < ns; t += (long long)bm.nb * kBlock) {
-    const int i = R.ix_lo + (int)(t % w);
-    const long long q = t / w;
-    const int j = (int)(q % ny);
-    const int k = (int)(q / ny);
+  const Solid& sol = R.solid;   // read in place: a copy of the constants would take registers
+  for (uint32_t t = bm.lb * kBlock + threadIdx.x; t < ns; t += bm.nb * kBlock) {
+    const uint32_t q = R.fd_w.div(t), kk = R.fd_ny.div(q);
+    const int i = R.ix_lo + (int)(t - q * (uint32_t)w);
+    const int j = (int)(q - kk * (uint32_t)ny);
+    const int k = (int)kk;
     const int c = i + nx * (j + ny * k);
     const int n = i + sx * j + sxy * k;
     const gptr<const long long> Jx = G((const long long*)R.J[0]), Jy = G((const long long*)R.J[1]),
@@ -1765,7 +1770,7 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
     double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = eta_in[c], fs = 1.0;
     const double j2 = jx * jx + jy * jy + jz * jz, qh = (double)G(R.ion_heat)[c] * R.heat_unit;
-    if (R.mix.n == 1) heat_cell(sol, Te, Ti, eta, j2, qh, R.dt, dV, fixed, want_fs ? &fs : nullptr);
+    if (!MIX || R.mix.n == 1) heat_cell(sol, Te, Ti, eta, j2, qh, R.dt, dV, fixed, want_fs ? &fs : nullptr);
     else heat_cell_mix(R.mix, Te, Ti, eta, j2, qh, R.dt, dV, fixed);
     if (want_fs) {
       if (R.precision == 0) G((double*)R.fsig)[c] = fs;
@@ -1917,7 +1922,8 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
     }
   };
   auto heating = [&](hipStream_t g) {
-    hipLaunchKernelGGL(k_heat, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
+    if (L.compound) hipLaunchKernelGGL(k_heat<true>, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
+    else hipLaunchKernelGGL(k_heat<false>, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
   };
   if (split) {   // field sub-cycles and heating each on a stream of its own
     (void)hipEventRecord(L.ev_fork, s);
