@@ -38,6 +38,7 @@ size_t hist_stride(const hyb_config& c) {
 // Sizes of everything a run keeps in device memory.
 struct Layout {
   size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta[2], off_heat, off_fsig;
+  size_t off_Jacc[3], off_heat_acc, off_stamp, off_pj, off_ph;
   size_t off_part[2][11];
   size_t off_sp_cell, off_sp_pid, off_sp_f[7], off_sp_cnt, off_sp_start, off_sp_blk, off_sp_grp, off_sp_gpid;
   size_t off_tabX, off_tabSIG, off_tabSUB;
@@ -64,6 +65,15 @@ Layout make_layout(const hyb_config& c) {
   for (int k = 0; k < 2; ++k) L.off_eta[k] = take(cells * 8);
   L.off_heat = take(cells * 8);
   L.off_fsig = take(cells * ts);
+  // the particle kernel's accumulators and per-tile partials, summed into
+  // J and the heat by the gather
+  const size_t ntl = (size_t)((c.nx + kTile - 1) / kTile) * ((c.ny + kTile - 1) / kTile) *
+                     ((c.nz + kTile - 1) / kTile);
+  for (int d = 0; d < 3; ++d) L.off_Jacc[d] = take(nodes * 8);
+  L.off_heat_acc = take(cells * 8);
+  L.off_stamp = take(ntl * 4);
+  L.off_pj = take(ntl * 3 * kPjHalo * ts);
+  L.off_ph = take(ntl * kTile * kTile * kTile * 8);
   for (int b = 0; b < 2; ++b) {
     // one record per electron: cell, id, then ox oy oz ux uy uz wn tau
     const size_t rec = 8 + 8 * ts;
@@ -374,6 +384,8 @@ static void fill_desc(hyb_run* r) {
   h.ntz = (c.nz + kTile - 1) / kTile;
   h.ntiles = h.ntx * h.nty * h.ntz;
   h.scan_nblk = (h.ntiles + kScanTile - 1) / kScanTile;
+  h.fd_gx = make_fastdiv((uint32_t)(c.nx >> 2) + 1);
+  h.fd_gy = make_fastdiv((uint32_t)(c.ny >> 2) + 1);
   h.hist_stride = (long long)hist_stride(c);
   set_units(h, r->w_ref > 0 ? r->w_ref : 1.0);
   r->solid_cells = (int64_t)(h.ix_hi - h.ix_lo) * c.ny * c.nz;
@@ -387,7 +399,12 @@ static void point_desc(hyb_run* r) {
     h.E[d] = b + L.off_E[d];
     h.B[d] = b + L.off_B[d];
     h.J[d] = (long long*)(b + L.off_J[d]);
+    h.Jacc[d] = (long long*)(b + L.off_Jacc[d]);
   }
+  h.heat_acc = (long long*)(b + L.off_heat_acc);
+  h.tstamp = (int*)(b + L.off_stamp);
+  h.pj = b + L.off_pj;
+  h.ph = (long long*)(b + L.off_ph);
   h.Te = (double*)(b + L.off_Te);
   h.Ti = (double*)(b + L.off_Ti);
   for (int k = 0; k < 2; ++k) h.eta[k] = (double*)(b + L.off_eta[k]);
@@ -453,20 +470,21 @@ static void dev_free(const hyb_device& d, void* p) {
 
 // Launch plans of a batch.  Particle plans get a multiple of 8 blocks per run
 // so the XCD split inside the particle kernel stays aligned.
-struct PlanSpec { std::vector<BlockMap> zero, inject, particle, grid, cells, fin, adv, scan, scan1; };
+struct PlanSpec { std::vector<BlockMap> zero, inject, particle, gather, grid, cells, fin, adv, scan, scan1; };
 
 static void add_run_plans(PlanSpec& ps, int run, const RunDesc& h) {
   auto add = [&](std::vector<BlockMap>& v, int nb) {
     for (int b = 0; b < nb; ++b) v.push_back(BlockMap{run, b, nb, 0});
   };
   const long long cap = h.capacity;
-  add(ps.zero, clampi((3 * h.nodes + h.cells + 1023) / 1024, 1, 4096));
+  add(ps.zero, clampi((h.ntiles + 1023) / 1024, 1, 1024));
   add(ps.inject, clampi((cap / 16 + 255) / 256, 1, 512));
   // the particle plan must start on a multiple of 8 blocks
   while (ps.particle.size() % 8) ps.particle.push_back(BlockMap{run, 0, 0, -1});
   int npb = clampi((cap + 255) / 256, 8, 4096);
   npb = (npb + 7) / 8 * 8;
   add(ps.particle, npb);
+  add(ps.gather, clampi((long long)((h.ny >> 2) + 1) * ((h.nz >> 2) + 1), 1, 4096));   // rows of tiles
   add(ps.grid, clampi((h.nodes + 511) / 512, 1, 4096));
   const long long sc = (long long)(h.ix_hi - h.ix_lo) * h.ny * h.nz;
   add(ps.cells, clampi((sc + 255) / 256, 1, 4096));
@@ -480,7 +498,8 @@ static hyb_status upload_plans(hyb_run* owner, hipStream_t s, const PlanSpec& ps
                                BlockMap** d_maps, size_t* maps_bytes, const hyb_device& dev) {
   std::vector<BlockMap> all;
   std::vector<std::pair<Plan*, const std::vector<BlockMap>*>> parts = {
-      {&L.zero, &ps.zero}, {&L.inject, &ps.inject}, {&L.particle, &ps.particle}, {&L.grid, &ps.grid},
+      {&L.zero, &ps.zero}, {&L.inject, &ps.inject}, {&L.particle, &ps.particle}, {&L.gather, &ps.gather},
+      {&L.grid, &ps.grid},
       {&L.cells, &ps.cells}, {&L.fin, &ps.fin}, {&L.adv, &ps.adv}, {&L.scan, &ps.scan},
       {&L.scan1, &ps.scan1}};
   std::vector<size_t> offs;
@@ -1291,6 +1310,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
     if (st->E) HIPCHK(r, put_typed(r->h.E[d], st->E + d * nodes, nodes));
     if (st->B) HIPCHK(r, put_typed(r->h.B[d], st->B + d * nodes, nodes));
     HIPCHK(r, hipMemset(r->h.J[d], 0, nodes * 8));
+    HIPCHK(r, hipMemset(r->h.Jacc[d], 0, nodes * 8));
   }
   if (st->Te) HIPCHK(r, hipMemcpy(r->h.Te, st->Te, cells * 8, hipMemcpyHostToDevice));
   if (st->Ti) HIPCHK(r, hipMemcpy(r->h.Ti, st->Ti, cells * 8, hipMemcpyHostToDevice));
@@ -1298,6 +1318,9 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
     for (int k = 0; k < 2; ++k) HIPCHK(r, hipMemcpy(r->h.eta[k], st->eta, cells * 8, hipMemcpyHostToDevice));
   if (st->Te || st->Ti) HIPCHK(r, refresh_fsig(r));
   HIPCHK(r, hipMemset(r->h.ion_heat, 0, cells * 8));
+  HIPCHK(r, hipMemset(r->h.heat_acc, 0, cells * 8));
+  // claims carry the step number, which a state may set back
+  HIPCHK(r, hipMemset(r->h.tstamp, 0, (size_t)r->h.ntiles * 4));
   if (delta) HIPCHK(r, hipMemset(r->h.sp_cnt, 0, (size_t)r->h.ntiles * 4));
   HIPCHK(r, hipMemset(r->h.acc_led, 0, 16 * 8));
   HIPCHK(r, hipMemset(r->h.acc_hist, 0, hist_stride(c) * kHistCopies * 8));

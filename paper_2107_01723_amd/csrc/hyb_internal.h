@@ -211,6 +211,19 @@ struct RunDesc {
   double* eta[2];           // resistivity: step n reads eta[n & 1], heating writes eta[(n + 1) & 1]
   void* fsig;               // [cells] eq. F_sigma of each cell (run precision), start of step
   long long* ion_heat;
+  // The particle kernel's current and collisional heat: a workgroup that
+  // first claims a tile in a step (tstamp[t] < step + 1, raised by its
+  // atomicMax) stores that tile's LDS sums whole, as plain stores, in pj/ph;
+  // every other contribution is added atomically into Jacc / heat_acc.  The
+  // gather then sums, per node and cell, the accumulators and the partials
+  // of the claimed tiles whose halos hold it into J / ion_heat, and clears
+  // the accumulators it found non-zero.
+  long long* Jacc[3];
+  long long* heat_acc;
+  int* tstamp;              // [ntiles] step + 1 of the tile's last claim (0: never)
+  void* pj;                 // [ntiles][3][216] current partials of the tiles (32-bit FP32, 64-bit FP64)
+  long long* ph;            // [ntiles][64] heat partials of the tile's cells
+  FastDiv fd_gx, fd_gy;     // by the gather's tile counts along x and y: (nx >> 2) + 1, (ny >> 2) + 1
   PartPtrs p[2];
   Counters* ctr;
   const SourceDesc* src;
@@ -239,6 +252,7 @@ struct RunDesc {
 };
 
 constexpr int kTile = 4;           // tile edge in cells
+constexpr int kPjHalo = (kTile + 2) * (kTile + 2) * (kTile + 2);   // nodes of a tile's deposit halo
 constexpr int kChunk = 256;        // electrons per chunk of the particle kernels (one workgroup)
 constexpr int kNb = 5;             // destination tiles counted per chunk: home +-2 per axis
 constexpr int kNbN = kNb * kNb * kNb;

@@ -21,7 +21,7 @@ struct Plan {
 struct LaunchSet {
   const RunDesc* runs = nullptr;   // device array [nruns]
   int nruns = 0;
-  Plan zero, inject, particle, grid, cells, fin, adv;
+  Plan zero, inject, particle, gather, grid, cells, fin, adv;
   Plan scan, scan1;   // tile-count scan: one block per kScanTile tiles; one block per run
   bool sort = false;                                  // some run sorts its particles
   bool delta = false;                                 // some run has delta rays

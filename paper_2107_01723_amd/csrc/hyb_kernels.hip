@@ -8,6 +8,8 @@
 // graph and replayed while particles are injected and removed.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hyb_internal.h"
 #include "hyb_kernels.h"
 #include "hyb_solid.h"
@@ -331,6 +333,48 @@ constexpr int kRegions = 6;    // LDS regions per chunk
 constexpr int kKeys = 64;      // census keys of a chunk's tiles (one per lane of a wave)
 constexpr int kLdsTab = 128;   // table rows staged in LDS
 
+// A tile's 216 halo nodes split into 27 parts by the tile that owns the
+// node: part e (a step of -1, 0 or +1 per axis, index (ex + 1) + 3 (ey + 1)
+// + 9 (ez + 1); 13 is the tile itself) holds the halo layer 0 (e = -1) or 5
+// (e = +1) on its fixed axes and layers 1..4 on the others, x fastest.  A
+// tile's partials (pj: [tile][component][216]) list the parts one after
+// the other, part 13 first: position p is halo node l[p] (x + 6 y + 36 z),
+// part e starts at off[e].  The gather of a tile reads the part of each
+// neighbour that lies in it as one run of words.
+struct PjPerm {
+  unsigned char l[kHaloN];
+  short off[27];
+};
+__host__ __device__ constexpr int pj_layer(int e, int o) { return e < 0 ? 0 : (e > 0 ? kHalo - 1 : 1 + o); }
+constexpr PjPerm make_pj_perm() {
+  PjPerm P{};
+  int pos = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int e = 0; e < 27; ++e) {
+      if ((pass == 0) != (e == 13)) continue;
+      const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+      P.off[e] = (short)pos;
+      for (int oz = 0; oz < (ez ? 1 : kTile); ++oz)
+        for (int oy = 0; oy < (ey ? 1 : kTile); ++oy)
+          for (int ox = 0; ox < (ex ? 1 : kTile); ++ox)
+            P.l[pos++] = (unsigned char)(pj_layer(ex, ox) + kHalo * (pj_layer(ey, oy) + kHalo * pj_layer(ez, oz)));
+    }
+  return P;
+}
+__constant__ PjPerm kPjPerm = make_pj_perm();
+static_assert(make_pj_perm().off[13] == 0 && make_pj_perm().l[kHaloN - 1] == kHaloN - 1, "halo order");
+
+// Word, inside the partials of tile u = v - e, of component c of own node o
+// of tile v, which u holds in its part e (indexed by o over the axes where
+// e is 0).
+__device__ __forceinline__ int pj_word(int ex, int ey, int ez, int c, int ox, int oy, int oz) {
+  int idx = 0, sc = 1;
+  if (!ex) { idx += ox; sc = kTile; }
+  if (!ey) { idx += oy * sc; sc *= kTile; }
+  if (!ez) idx += oz * sc;
+  return c * kHaloN + kPjPerm.off[(ex + 1) + 3 * (ey + 1) + 9 * (ez + 1)] + idx;
+}
+
 // The per-tile counts that pick the regions use slots that alternate between
 // chunks, so that counting the next chunk never races the reads of this one.
 template <typename T>
@@ -343,6 +387,8 @@ struct ChunkLds {
   T ph[6][kBlock];            // emitted photon of each lane: k, u (3), |u|, gamma
   T tsig[kLdsTab], tsub[kLdsTab];   // cross-section columns of the tables, if they fit
   T F[2][6][kHaloN];                // E, B on the 6^3-node halos of the two fullest regions
+  int own[kRegions];                // the region's tile was first claimed this step by this workgroup
+  unsigned char perm[kHaloN];       // halo node of each position of the partials (kPjPerm.l)
 };
 
 struct Home {
@@ -383,14 +429,33 @@ __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x < 2 * kKeys) { (&L.tc[0][0])[threadIdx.x] = 0; (&L.tt[0][0])[threadIdx.x] = -1; }
   if (threadIdx.x < L_N + C_N) L.led[threadIdx.x] = 0;
+  if (threadIdx.x < kHaloN) L.perm[threadIdx.x] = kPjPerm.l[threadIdx.x];
 }
 
-// Adds the LDS sums of one region to HBM (one atomic per non-zero entry)
-// and clears them for the next chunk.
+// Moves the LDS sums of one region to HBM and clears them for the next
+// chunk: the tile's partials as whole lines of plain stores if this
+// workgroup holds the tile's claim of the step, else one atomic per
+// non-zero entry into the accumulators.
 template <typename T>
-__device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& L, int r, const Home& h) {
+__device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& L, int r, int tile) {
+  using A = typename JAcc<T>::type;
+  A* J = L.J[r];
+  if (L.own[r]) {
+    A* const dst = (A*)R.pj + (long long)tile * (3 * kHaloN);
+    for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
+      const int c = t >= 2 * kHaloN ? 2 : (t >= kHaloN ? 1 : 0);
+      A* w = &J[c * kHaloN + L.perm[t - c * kHaloN]];
+      dst[t] = *w;
+      *w = 0;
+    }
+    if (threadIdx.x < kTile * kTile * kTile) {
+      R.ph[(long long)tile * (kTile * kTile * kTile) + threadIdx.x] = L.heat[r][threadIdx.x];
+      L.heat[r][threadIdx.x] = 0;
+    }
+    return;
+  }
+  const Home h = make_home(R, tile);
   const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
-  typename JAcc<T>::type* J = L.J[r];
   for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
     long long v = (long long)J[t];
     if (v == 0) continue;
@@ -399,7 +464,7 @@ __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& 
     const int c = t / kHaloN, l = t % kHaloN;
     const int i = h.bx + l % kHalo, j = h.by + (l / kHalo) % kHalo, k = h.bz + l / (kHalo * kHalo);
     if (i < 0 || j < 0 || k < 0 || i > R.nx || j > R.ny || k > R.nz) continue;
-    atomic_add_i64(&R.J[c][i + sx * j + sxy * k], v);
+    atomic_add_i64(&R.Jacc[c][i + sx * j + sxy * k], v);
   }
   if (threadIdx.x < kTile * kTile * kTile) {
     const long long v = L.heat[r][threadIdx.x];
@@ -407,7 +472,7 @@ __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& 
     const int i = kTile * h.tx + (l & 3), j = kTile * h.ty + ((l >> 2) & 3), k = kTile * h.tz + (l >> 4);
     if (v != 0) {
       L.heat[r][threadIdx.x] = 0;
-      if (i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.ion_heat[i + R.nx * (j + R.ny * k)], v);
+      if (i < R.nx && j < R.ny && k < R.nz) atomic_add_i64(&R.heat_acc[i + R.nx * (j + R.ny * k)], v);
     }
   }
 }
@@ -789,6 +854,21 @@ __device__ __forceinline__ void pick_regions(const ChunkLds<T>& S, int q, const 
   tb = b;
 }
 
+// The first thread claims, for this step, the tile of every slot that took
+// a new tile for this chunk (bit k of fresh; the carried regions keep their
+// claim), and records in S.own whether this workgroup was the first.  The
+// atomics go out after the chunk's state loads, which the wave waits for
+// next anyway.
+template <typename T>
+__device__ __forceinline__ void claim_regions(const RunDesc& R, ChunkLds<T>& S, const int (&rt)[kRegions],
+                                              int fresh, int stampv) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kRegions; ++k)
+      if ((fresh >> k) & 1) S.own[k] = atomicMax(&R.tstamp[rt[k]], stampv) < stampv;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the particle step: gather, Boris, deposit, move, ionisation,
 // bremsstrahlung, elastic scatter, boundaries, low-energy removal
@@ -863,13 +943,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   long long pch = -1;               // the previous chunk
 #pragma unroll
   for (int k = 0; k < kRegions; ++k) { rt[k] = -1; fl[k] = -1; }
+  const int stampv = (int)(step + 1);
+  int fresh = 0;                    // slots that took a new tile for the coming chunk
   if (cr.beg < cr.end) {
     chunk_census(R, S, cell_next, 0);
     __syncthreads();
     int nrt[kRegions], kept;
     pick_regions<T>(S, 0, rt, 0, nrt, cn, kept, ta, tb);
 #pragma unroll
-    for (int k = 0; k < kRegions; ++k) rt[k] = nrt[k];
+    for (int k = 0; k < kRegions; ++k) {
+      rt[k] = nrt[k];
+      if (rt[k] >= 0) fresh |= 1 << k;
+    }
   }
   int slot = 0;
   for (long long ch = cr.beg; ch < cr.end; ch += cr.stride, slot ^= 1) {
@@ -917,12 +1002,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     if (!kFlushEarly && pch >= 0) {
 #pragma unroll
       for (int k = 0; k < kRegions; ++k)
-        if (fl[k] >= 0) lds_flush_region(R, S, k, make_home(R, fl[k]));
+        if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k]);
       if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
     }
     __syncthreads();
-    // this chunk's census was read when its regions were picked
+    // this chunk's census was read when its regions were picked; the
+    // previous regions of reused slots are flushed
     if (threadIdx.x < kKeys) { S.tc[slot][threadIdx.x] = 0; S.tt[slot][threadIdx.x] = -1; }
+    claim_regions(R, S, rt, fresh, stampv);
     const Home hm = make_home(R, ta), hm2 = make_home(R, tb);
     if (phys & PHYS_FIELDS) {
       // a region whose halo a slot already holds keeps it (fields do not
@@ -1033,9 +1120,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       {
         const T amp = -wn * (T)(kJScale / (double)(1LL << JAcc<T>::shift));
         constexpr int CN = kHaloN;
-        deposit8(R.J[0], Js, rbx, rby, rbz, sx, sxy, sxa, nya, nza, amp * vx);
-        deposit8(R.J[1], Js ? Js + CN : Js, rbx, rby, rbz, sx, sxy, nxa, sya, nza, amp * vy);
-        deposit8(R.J[2], Js ? Js + 2 * CN : Js, rbx, rby, rbz, sx, sxy, nxa, nya, sza, amp * vz);
+        deposit8(R.Jacc[0], Js, rbx, rby, rbz, sx, sxy, sxa, nya, nza, amp * vx);
+        deposit8(R.Jacc[1], Js ? Js + CN : Js, rbx, rby, rbz, sx, sxy, nxa, sya, nza, amp * vy);
+        deposit8(R.Jacc[2], Js ? Js + 2 * CN : Js, rbx, rby, rbz, sx, sxy, nxa, nya, sza, amp * vz);
       }
 
       // --- move ---
@@ -1270,7 +1357,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       if (heat != 0) {
         if (js >= 0)
           lds_add(&S.heat[js][heat_local], heat);
-        else atomic_add_i64(&R.ion_heat[heat_cell], heat);
+        else atomic_add_i64(&R.heat_acc[heat_cell], heat);
       }
       if (!alive) {
         P.cell[i] = kDead;
@@ -1319,8 +1406,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     {
       int nrt[kRegions], ncn, kept, nta, ntb;
       pick_regions<T>(S, slot ^ 1, rt, cn, nrt, ncn, kept, nta, ntb);
+      fresh = 0;
 #pragma unroll
       for (int k = 0; k < kRegions; ++k) {
+        if (nrt[k] >= 0 && !((kept >> k) & 1)) fresh |= 1 << k;
         fl[k] = rt[k] >= 0 && !((kept >> k) & 1) ? rt[k] : -1;
         rt[k] = nrt[k];
       }
@@ -1331,7 +1420,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     if (kFlushEarly) {
 #pragma unroll
       for (int k = 0; k < kRegions; ++k)
-        if (fl[k] >= 0) lds_flush_region(R, S, k, make_home(R, fl[k]));
+        if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k]);
       if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
     }
   }
@@ -1339,7 +1428,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   if (!kFlushEarly && pch >= 0) {
 #pragma unroll
     for (int k = 0; k < kRegions; ++k)
-      if (fl[k] >= 0) lds_flush_region(R, S, k, make_home(R, fl[k]));
+      if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k]);
     if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
   }
   if (base_at >= 0) G(R.chunk_base)[base_at] = base_val;
@@ -1621,7 +1710,7 @@ __global__ __launch_bounds__(kBlock) void k_spawn_append(const RunDesc* __restri
       const T e = kinetic(u2, m_sqrt((T)1 + u2)) * wn;
       acc[L_STOPPED] += to_fixed(e * (T)kLedScale);
       acc[L_N + C_DELTA_LOST] += 1;
-      atomic_add_i64(&R.ion_heat[cell_i(c) + R.nx * (cell_j(c) + R.ny * cell_k(c))], to_fixed(e * (T)kHeatScale));
+      atomic_add_i64(&R.heat_acc[cell_i(c) + R.nx * (cell_j(c) + R.ny * cell_k(c))], to_fixed(e * (T)kHeatScale));
     }
   }
   block_flush<L_N, C_N>(acc, R.acc_led, R.events);
@@ -1636,16 +1725,128 @@ __global__ __launch_bounds__(kBlock) void k_zero_step(const RunDesc* __restrict_
   const RunDesc& R = runs[bm.run];
   const auto ctr = G(R.ctr);
   if (!ctr->active) return;
-  const long long nn = R.nodes;
-  const long long nt = sort_step(R.sort_every, ctr->step) ? R.ntiles : 0;
-  const long long tot = 3 * nn + R.cells + nt;
-  for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
-    if (t < nn) G(R.J[0])[t] = 0;
-    else if (t < 2 * nn) G(R.J[1])[t - nn] = 0;
-    else if (t < 3 * nn) G(R.J[2])[t - 2 * nn] = 0;
-    else if (t < 3 * nn + R.cells) G(R.ion_heat)[t - 3 * nn] = 0;
-    else G(R.tile_cnt)[t - 3 * nn - R.cells] = 0;
-  }
+  // (the current and heat accumulators are cleared by the gather)
+  if (!sort_step(R.sort_every, ctr->step)) return;
+  for (int t = bm.lb * kBlock + threadIdx.x; t < R.ntiles; t += bm.nb * kBlock) G(R.tile_cnt)[t] = 0;
+}
+
+// The step's current j_h on the Yee edges and collisional heat per cell
+// (eq. Ampere_Maxwell, App. A): per tile v of the node grid (node i in tile
+// i >> 2, so one more tile per axis than the cells have where n is a
+// multiple of 4), each of its nodes sums the accumulator and, of the up to
+// eight tiles whose deposit halos hold the node, the partials of those
+// claimed this step; each cell its accumulator and its own tile's partial.
+// The accumulators are cleared where they were not zero.
+constexpr int kGatherU = 4;   // tiles per workgroup iteration of the gather
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ runs,
+                                                   const BlockMap* __restrict__ bmap) {
+  using A = typename JAcc<T>::type;
+  const BlockMap bm = bmap[blockIdx.x];
+  const RunDesc& R = runs[bm.run];
+  const auto ctr = G(R.ctr);
+  if (!ctr->active) return;
+  const int stampv = (int)(ctr->step + 1);
+  const int nx = R.nx, ny = R.ny, nz = R.nz;
+  const int sx = nx + 1, sxy = (nx + 1) * (ny + 1);
+  const int gx = (nx >> 2) + 1, gy = (ny >> 2) + 1, gz = (nz >> 2) + 1;
+  // component (3: heat; one per wave), node or cell of the tile
+  const int c = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), o = threadIdx.x & 63;
+  const int ox = o & 3, oy = (o >> 2) & 3, oz = o >> 4;
+  // The node's other tile along each axis (-1, +1; 0: none; cells have
+  // none) and, for the up to eight tiles u holding it (m: bit 0 x, 1 y, 2 z
+  // take the other tile), the node's word in u's partials: pb + p3 u.  Every
+  // load below is issued unconditionally (lanes with nothing to read load a
+  // word they do not use), so that the loads of an iteration are all in
+  // flight together instead of each waiting at the end of its branch.
+  const bool hc = c == 3;
+  const int ax = hc ? 0 : (ox == 0 ? -1 : (ox == kTile - 1 ? 1 : 0));
+  const int ay = hc ? 0 : (oy == 0 ? -1 : (oy == kTile - 1 ? 1 : 0));
+  const int az = hc ? 0 : (oz == 0 ? -1 : (oz == kTile - 1 ? 1 : 0));
+  int pb[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+    pb[m] = hc ? o : pj_word(-(m & 1 ? ax : 0), -(m & 2 ? ay : 0), -(m & 4 ? az : 0), c, ox, oy, oz);
+  const long long pstr = hc ? kTile * kTile * kTile : 3 * kHaloN;   // words per tile
+  const gptr<const A> pj = G((const A*)R.pj);
+  const gptr<const long long> ph = G((const long long*)R.ph);
+  // A workgroup sweeps whole rows of tiles along x, kGatherU tiles per
+  // iteration, so that the partials and the node rows are read as
+  // sequential streams; the workgroups stride over the rows, so that those
+  // running at a time share one window of the grid.  The claims of the 27
+  // tiles around each tile of an iteration are staged in LDS one iteration
+  // ahead.
+  const uint32_t ngr = (uint32_t)(gx + kGatherU - 1) / kGatherU, nrows = (uint32_t)gy * gz;
+  const uint32_t myrows = (uint32_t)bm.lb < nrows ? (nrows - 1 - bm.lb) / bm.nb + 1 : 0;
+  const uint32_t nit = myrows * ngr;
+  __shared__ int st[2][kGatherU][27];
+  const bool stager = threadIdx.x < 27 * kGatherU;
+  auto claim_of = [&](uint32_t it) -> int {   // the claim a stager thread stages for iteration it
+    if (it >= nit) return 0;
+    const int g = (int)threadIdx.x / 27, n = (int)threadIdx.x % 27;
+    const uint32_t row = bm.lb + (it / ngr) * bm.nb;
+    const uint32_t vzu = R.fd_gy.div(row);
+    const int ux = (int)(it % ngr) * kGatherU + g + n % 3 - 1, uy = (int)(row - vzu * (uint32_t)gy) + (n / 3) % 3 - 1,
+              uz = (int)vzu + n / 9 - 1;
+    const bool in = ux >= 0 && uy >= 0 && uz >= 0 && ux < R.ntx && uy < R.nty && uz < R.ntz;
+    return in ? G((const int*)R.tstamp)[ux + R.ntx * (uy + R.nty * uz)] : 0;
+  };
+  if (stager) st[0][threadIdx.x / 27][threadIdx.x % 27] = claim_of(0);
+  __syncthreads();
+  // the waves of the current and of the heat take separate loops (the
+  // component is uniform per wave), each with the same barriers
+  auto sweep = [&](auto hc_tag) {
+    constexpr bool HC = decltype(hc_tag)::value;
+    const gptr<long long> acc = G(HC ? R.heat_acc : R.Jacc[HC ? 0 : c]);
+    const gptr<long long> out = G(HC ? R.ion_heat : R.J[HC ? 0 : c]);
+    int buf = 0;
+    for (uint32_t it = 0; it < nit; ++it, buf ^= 1) {
+      const int nxt = stager ? claim_of(it + 1) : 0;   // lands while this iteration's loads run
+      const uint32_t row = bm.lb + (it / ngr) * bm.nb;
+      const uint32_t vzu = R.fd_gy.div(row);
+      const int vy = (int)(row - vzu * (uint32_t)gy), vz = (int)vzu, vx0 = (int)(it % ngr) * kGatherU;
+      bool in[kGatherU];
+      int at[kGatherU], usem[kGatherU];
+      long long a0[kGatherU];
+      long long w[kGatherU][HC ? 1 : 8];
+#pragma unroll
+      for (int g = 0; g < kGatherU; ++g) {
+        const int vx = vx0 + g;
+        const int i = kTile * vx + ox, j = kTile * vy + oy, k = kTile * vz + oz;
+        in[g] = HC ? (i < nx && j < ny && k < nz) : (i <= nx && j <= ny && k <= nz);
+        at[g] = in[g] ? (HC ? i + nx * (j + ny * k) : i + sx * j + sxy * k) : 0;
+        a0[g] = acc[at[g]];
+        usem[g] = 0;
+#pragma unroll
+        for (int m = 0; m < (HC ? 1 : 8); ++m) {
+          const int dx = m & 1 ? ax : 0, dy = m & 2 ? ay : 0, dz = m & 4 ? az : 0;
+          const bool use = in[g] && (!(m & 1) || ax) && (!(m & 2) || ay) && (!(m & 4) || az) &&
+                           st[buf][g][13 + dx + 3 * dy + 9 * dz] == stampv;
+          const long long u = (vx + dx) + (long long)R.ntx * ((vy + dy) + (long long)R.nty * (vz + dz));
+          const long long wa = use ? pb[m] + u * pstr : 0;
+          w[g][m] = HC ? ph[wa] : (long long)pj[wa];
+          usem[g] |= use ? 1 << m : 0;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);   // every load above is issued before the first sum waits
+#pragma unroll
+      for (int g = 0; g < kGatherU; ++g) {
+        long long a = 0;
+#pragma unroll
+        for (int m = 0; m < (HC ? 1 : 8); ++m) a += (usem[g] >> m) & 1 ? w[g][m] : 0LL;
+        if (!HC) a *= (1LL << JAcc<T>::shift);
+        if (in[g]) {
+          if (a0[g] != 0) acc[at[g]] = 0;
+          out[at[g]] = a0[g] + a;
+        }
+      }
+      if (stager) st[buf ^ 1][threadIdx.x / 27][threadIdx.x % 27] = nxt;
+      __syncthreads();
+    }
+  };
+  if (hc) sweep(std::true_type{});
+  else sweep(std::false_type{});
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -1910,10 +2111,16 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
                          L.particle.map);
   }
   if (L.ev_stop) (void)hipEventRecord(L.ev_stop, s);
-  // The sort (scans, scatter), the field sub-cycles and the heating read and
-  // write disjoint data (the heating writes the next step's resistivity), so
-  // with two more streams the grid kernels run beside the HBM-bound scatter.  Delta-ray appends can book a lost
-  // delta ray's energy as heat, so runs with delta rays keep one stream.
+  auto gather = [&]() { hipLaunchKernelGGL(k_gather<T>, dim3(L.gather.nb), dim3(kBlock), 0, s, L.runs, L.gather.map); };
+  // The gather of the step's current and heat comes first (delta-ray
+  // appends can book a lost delta ray's energy as heat: runs with delta rays
+  // gather after them).  Then the sort (scans, scatter), the field
+  // sub-cycles and the heating read and write disjoint data (the heating
+  // writes the next step's resistivity), so with two more streams the grid
+  // kernels run beside the HBM-bound scatter; runs with delta rays keep one
+  // stream.  (Running the gather beside the scatter instead measured slower:
+  // the kernels after it then overlap less.)
+  if (!L.delta) gather();
   const bool split = L.side && L.side2 && L.ev_fork && L.ev_join && L.ev_join2 && !L.delta;
   auto fields = [&](hipStream_t g) {
     for (int k = 0; k < max_sub; ++k) {
@@ -1925,7 +2132,14 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
     if (L.compound) hipLaunchKernelGGL(k_heat<true>, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
     else hipLaunchKernelGGL(k_heat<false>, dim3(L.cells.nb), dim3(kBlock), 0, g, L.runs, L.cells.map);
   };
-  if (split) {   // field sub-cycles and heating each on a stream of its own
+  if (L.sort) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map, 0);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
+  }
+  // the fork comes after the short scans: launched beside the grid kernels,
+  // whose workgroups fill the machine, they would wait for free slots
+  if (split) {   // field sub-cycles and heating each on a stream of their own
     (void)hipEventRecord(L.ev_fork, s);
     (void)hipStreamWaitEvent(L.side, L.ev_fork, 0);
     (void)hipStreamWaitEvent(L.side2, L.ev_fork, 0);
@@ -1933,9 +2147,6 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
     fields(L.side);
   }
   if (L.sort) {
-    hipLaunchKernelGGL(k_scan_reduce, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(L.scan1.nb), dim3(kBlock), 0, s, L.runs, L.scan1.map, 0);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 0);
     if (L.delta) hipLaunchKernelGGL((k_scatter<T, true>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
     else hipLaunchKernelGGL((k_scatter<T, false>), dim3(L.particle.nb), dim3(kBlock), 0, s, L.runs, L.particle.map);
   }
@@ -1945,6 +2156,7 @@ static void launch_step_t(const LaunchSet& L, hipStream_t s, int max_sub) {
     hipLaunchKernelGGL(k_scan_tiles, dim3(L.scan.nb), dim3(kBlock), 0, s, L.runs, L.scan.map, 1);
     hipLaunchKernelGGL(k_spawn_group, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
     hipLaunchKernelGGL(k_spawn_append<T>, dim3(L.inject.nb), dim3(kBlock), 0, s, L.runs, L.inject.map);
+    gather();
   }
   if (split) {
     (void)hipEventRecord(L.ev_join, L.side);
