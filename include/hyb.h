@@ -139,7 +139,11 @@ enum {
   HYB_C_ESTEPS = 7,       /* electron-steps: the electrons alive at the start of
                              each completed step (that step's injections
                              included), summed over the steps */
-  HYB_COUNTER_N = 8
+  HYB_C_INJ_LOST = 8,     /* scheduled electrons that found no particle slot
+                             (never expected: delta rays leave the slots of
+                             the injections still to come free; hyb_tally
+                             reports HYB_ENOSPACE if it is not zero) */
+  HYB_COUNTER_N = 9
 };
 
 /* Run configuration (copied by hyb_init).  The solid is one element filling
@@ -361,7 +365,8 @@ hyb_status hyb_inject_beam(hyb_run* run, const hyb_beam* beam);
 hyb_status hyb_step(hyb_run* run, int32_t nsteps);
 
 /* Copy out tallies, ledger, counters and the alive kinetic energy.
- * Synchronises the stream. */
+ * Synchronises the stream.  Returns HYB_ENOSPACE (with everything copied
+ * out) if scheduled electrons found no particle slot (HYB_C_INJ_LOST). */
 hyb_status hyb_tally(hyb_run* run, hyb_tally_out* out);
 
 /* Copy the whole state to host buffers (particles in internal order).

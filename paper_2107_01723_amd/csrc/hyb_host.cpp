@@ -1126,6 +1126,7 @@ hyb_status hyb_tally(hyb_run* r, hyb_tally_out* out) {
   out->kinetic = kin * r->h.w_ref * kMec2;
   out->n_alive = (int64_t)llround(alive);
   out->conversion = led[HYB_L_INJECTED] > 0 ? led[HYB_L_PHOTON_THR] / led[HYB_L_INJECTED] : 0.0;
+  if (out->counters[HYB_C_INJ_LOST] > 0) return fail(r, HYB_ENOSPACE, "scheduled electrons found no particle slot");
   return HYB_OK;
 }
 

@@ -35,7 +35,7 @@ constexpr double kHeatScale = 1099511627776.0;      // 2^40
 
 enum { L_INJECTED = 0, L_FIELD_LOSS, L_FIELD_GAIN, L_ION, L_STOPPED, L_RAD_D, L_RAD_S,
        L_ESCAPED, L_REFLUX, L_PHOTON_THR, L_RESIDUAL, L_N };
-enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_DELTA, C_DELTA_LOST, C_ESTEPS, C_N };
+enum { C_INJECTED = 0, C_EMITTED, C_REFLUX, C_ESCAPED, C_STOPPED, C_DELTA, C_DELTA_LOST, C_ESTEPS, C_INJ_LOST, C_N };
 
 enum : uint32_t {
   PHYS_FIELDS = 1u << 0, PHYS_ION = 1u << 1, PHYS_BREM = 1u << 2, PHYS_SCATTER = 1u << 3,

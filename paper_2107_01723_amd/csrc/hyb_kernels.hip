@@ -43,6 +43,21 @@ __device__ __forceinline__ long long inject_count(const RunDesc& R, long long st
   return tot;
 }
 
+// Number of electrons the sources will inject after `step`: the particle
+// slots that delta rays must leave free.
+__device__ __forceinline__ long long later_injections(const RunDesc& R, long long step) {
+  long long tot = 0;
+  for (int s = 0; s < R.nsrc; ++s) {
+    const gptr<const SourceDesc> S = G(R.src) + s;
+    long long i0 = step + 1 - S->s0;
+    i0 = i0 > 0 ? i0 : 0;
+    if (i0 >= S->ns) continue;
+    const long long extra = (S->rem < S->ns ? S->rem : S->ns) - i0;
+    tot += (S->ns - i0) * S->base + (extra > 0 ? extra : 0);
+  }
+  return tot;
+}
+
 // Block-wide sum of per-thread integer accumulators, then one atomic per
 // non-zero term: ledger terms to `led`, event counts to `evt`.  The
 // registers hold the NL ledger terms and the first NC event counts; `extra`,
@@ -102,6 +117,11 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
 #pragma unroll
   for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
   for (long long t = (long long)bm.lb * kBlock + threadIdx.x; t < tot; t += (long long)bm.nb * kBlock) {
+    const long long slot = n0 + t;
+    if (slot >= R.capacity) {   // never write past the particle arrays; counted
+      acc[L_N + C_INJ_LOST] += 1;
+      continue;
+    }
     int s = 0;
     long long off = 0;
     while (s < R.nsrc - 1 && t >= off + cnt[s]) { off += cnt[s]; ++s; }
@@ -153,8 +173,6 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
     const T um = umag_of(eps);
     const T ux = um * ct, uy = um * st * cpc, uz = um * st * spc;
     const T tau = -m_log((T)1 - b.b);
-    const long long slot = n0 + t;
-    if (slot >= R.capacity) break;   // never write past the particle arrays
     P.cell[slot] = pack_cell(R.ix_lo, cy, cz);
     P.ox[slot] = (T)0;
     P.oy[slot] = oy;
@@ -1676,6 +1694,7 @@ __global__ __launch_bounds__(kBlock) void k_spawn_append(const RunDesc* __restri
   n0 = sorted ? ctr->n_sorted : (n0 < R.capacity ? n0 : R.capacity);
   const PartG<T> P = part_g<T>(R.p[sorted ? ctr->cur ^ 1 : ctr->cur]);
   const long long id0 = ctr->delta_next;
+  const long long cap = R.capacity - later_injections(R, step);   // slots of injections to come stay free
   long long acc[L_N + C_N];
 #pragma unroll
   for (int i = 0; i < L_N + C_N; ++i) acc[i] = 0;
@@ -1694,7 +1713,7 @@ __global__ __launch_bounds__(kBlock) void k_spawn_append(const RunDesc* __restri
     const T ux = G((const T*)R.sp_f[3])[a], uy = G((const T*)R.sp_f[4])[a], uz = G((const T*)R.sp_f[5])[a];
     const T wn = G((const T*)R.sp_f[6])[a];
     const long long slot = n0 + r;
-    if (slot < R.capacity) {
+    if (slot < cap) {
       const Uni4<T> u = draws<T>(id, R.seed, step, SLOT_BIRTH);
       P.cell[slot] = c;
       P.ox[slot] = G((const T*)R.sp_f[0])[a];
@@ -2046,8 +2065,8 @@ __global__ void k_advance(const RunDesc* __restrict__ runs, const BlockMap* __re
   }
   if (R.physics & PHYS_DELTA) {   // the step's delta rays were appended
     const long long ns = c->n_spawn < R.spawn_cap ? c->n_spawn : R.spawn_cap;
-    const long long n = c->n_total + ns;
-    c->n_total = n < R.capacity ? n : R.capacity;
+    const long long n = c->n_total + ns, cap = R.capacity - later_injections(R, c->step);
+    c->n_total = n < cap ? n : (c->n_total > cap ? c->n_total : cap);
     c->delta_next += ns;
     c->n_spawn = 0;
   }

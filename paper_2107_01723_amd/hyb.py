@@ -21,7 +21,7 @@ FP64, FP32_MIXED = 0, 1
 LEDGER_KEYS = ("injected", "field_loss", "field_gain", "ionisation", "stopped",
                "rad_discrete", "rad_subcut", "escaped", "reflux", "photon_thr", "residual")
 COUNTER_KEYS = ("n_injected", "n_emitted", "n_reflux", "n_escaped", "n_stopped", "n_delta",
-                "n_delta_lost", "n_electron_steps")
+                "n_delta_lost", "n_electron_steps", "n_injection_lost")
 PHYS_DELTA = 1 << 8
 PHYS_URBAN = 1 << 9
 DELTA_ID_BIT = 0x80000000
@@ -125,7 +125,7 @@ class TallyOut(C.Structure):
         ("series", C.POINTER(C.c_double)),
         ("flow", C.c_double * 4), ("ledger", C.c_double * 11),
         ("kinetic", C.c_double), ("conversion", C.c_double),
-        ("counters", C.c_int64 * 8), ("n_alive", C.c_int64), ("step", C.c_int64),
+        ("counters", C.c_int64 * 9), ("n_alive", C.c_int64), ("step", C.c_int64),
     ]
 
 

@@ -152,3 +152,42 @@ def test_delta_run_alone_equals_mixed(P):
     assert np.array_equal(alone[1][1]["tau_d"][o1], finished[1][1]["tau_d"][o2])
     assert alone[1][0]["counters"] == finished[1][0]["counters"]
     eng.close()
+
+
+def test_scan_smallest_runs_against_oracle(P):
+    """The two smallest runs of the 64-run scan (the bench's request stream),
+    served by the engine beside two larger ones: after 40 steps (inside the
+    1 ps injection) each one's state is taken, the oracle steps it once
+    (with that step's injections) and the engine's next step of the batch
+    matches it per electron within 1e-5 (FP32-mixed), electrons whose
+    discrete path differs counted (<= 0.5 %)."""
+    from oracle import OracleRun
+    from parity_util import particle_errors
+    reqs = W.scan_runs(64, seed=0)
+    size = [r["srcs"][0]["n_macro"] * r["cfg"]["nx"] * r["cfg"]["ny"] * r["cfg"]["nz"] for r in reqs]
+    order = np.argsort(size)
+    small, big = [int(k) for k in order[:2]], [int(order[len(order) // 2]), int(order[len(order) // 2 + 1])]
+    eng = P.Engine(max_runs=8)
+    runs = {k: eng.admit(reqs[k]["cfg"], reqs[k]["srcs"], reqs[k]["steps"]) for k in small + big}
+    assert all(r is not None for r in runs.values())
+    eng.step(40)
+    st0 = {k: runs[k].get_state() for k in small}
+    eng.step(1)
+    for k in small:
+        cfg, src = reqs[k]["cfg"], reqs[k]["srcs"][0]
+        st1 = runs[k].get_state()
+        ora = OracleRun(cfg)
+        ora.add_source(src)
+        ora.set_state(dict(st0[k]))
+        ora.step()
+        err, only = particle_errors(st1, ora.state(), cfg["dx"])
+        tol = 1e-5
+        bad = (err["p"] > tol) | (err["pos"] > tol) | (err["tau"] > tol)
+        nflip = int(np.sum(bad)) + len(only)
+        print(f"  scan run {k} ({cfg['nx']}x{cfg['ny']}x{cfg['nz']}, {src['n_macro']} electrons scheduled): "
+              f"{len(err['ids'])} compared, max|dp|={err['p'][~bad].max():.2e} "
+              f"max|dx|/dx={err['pos'][~bad].max():.2e} flips={nflip}", flush=True)
+        assert len(err["ids"]) > 10_000
+        assert nflip <= 0.005 * len(err["ids"]), (nflip, only[:10])
+        assert err["w"].max() <= tol
+    eng.close()

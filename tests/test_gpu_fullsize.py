@@ -80,6 +80,53 @@ def test_fullsize_sampled_electrons(P, precision, n_pre, tol):
     assert err["w"].max() <= tol
 
 
+@pytest.mark.parametrize("which,n_pre", [("c3", 25), ("c5", 40)])
+def test_fullsize_sampled_electrons_fp32_large(P, which, n_pre):
+    """FP32-mixed at the two large workloads, during the injection (the
+    injection plane's tiles hold 1e5-1e6 electrons, so the workgroups carry
+    LDS regions over many chunks and the chunks of the unsorted injected
+    tail use every region): 2000 electrons drawn from the whole population,
+    one step, oracle vs GPU within 1e-5 per electron, electrons whose
+    discrete path differs counted (<= 0.5 %).  The oracle steps only the
+    sample (no injection) and skips its grid update, which this step's
+    particles do not see."""
+    if which == "c3":
+        cfg, srcs, _ = W.config_mixed_large()
+    else:
+        cfg, srcs, _ = W.config_huge()
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(n_pre)
+    cap = run.tally()["n_alive"] + 1
+    st0 = run.get_state(capacity=cap + srcs[0]["n_macro"] // 50)
+    run.step(1)
+    st1 = run.get_state(capacity=cap + 2 * srcs[0]["n_macro"] // 50)
+    run.close()
+    n0 = len(st0["ids"])
+    print(f"  {which} step {n_pre}: {n0} electrons alive", flush=True)
+    assert n0 > 20_000_000
+    pick = np.random.default_rng(13).choice(n0, 2000, replace=False)
+    ids = st0["ids"][pick]
+    ora = OracleRun(cfg)
+    ora.grid_update = lambda: None
+    ora.set_state(dict(_subset(st0, ids), step=st0["step"], next_id=st0["next_id"]))
+    del st0
+    ora.step()
+    ref = ora.state()
+    got = _subset(st1, ids)
+    del st1
+    err, only = particle_errors(got, ref, cfg["dx"])
+    tol = 1e-5
+    bad = (err["p"] > tol) | (err["pos"] > tol) | (err["tau"] > tol)
+    nflip = int(np.sum(bad)) + len(only)
+    print(f"  compared {len(err['ids'])}: max|dp|={err['p'][~bad].max():.2e} "
+          f"max|dx|/dx={err['pos'][~bad].max():.2e} max|dtau|={err['tau'][~bad].max():.2e} "
+          f"flips={nflip}", flush=True)
+    assert len(err["ids"]) > 1800
+    assert nflip <= 0.005 * len(ids), (nflip, only[:10])
+    assert err["w"].max() <= tol
+
+
 def _check_run_properties(t, st):
     """Properties of a whole run at any size."""
     assert _closure(t) < 1e-6

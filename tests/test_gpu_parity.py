@@ -140,6 +140,44 @@ def test_free_run_fp64(P, nsteps, wscale):
     run.close()
 
 
+def test_free_run_fp32_mixed(P):
+    """FP32-mixed free-running 10 steps from the oracle's FP64 state with every
+    field feedback on, at 1/100 of the weight (the FP64 10-step run's
+    setting).  No electron's discrete path differs (no error above 1e-4 and
+    none alive on one side only); 97 % of the electrons are within 1e-5 and
+    all within 1e-4: FP32 rounding accumulates over the ten steps, most
+    where an electron has lost most of its energy (the worst are below
+    0.2 MeV, against a median of 0.6 MeV), which the print shows."""
+    cfg, srcs, _ = small_config(10000, precision=W.FP32_MIXED, brem_boost=10.0)
+    from oracle import particles as PT
+    srcs[0]["weight"] = PT.default_weight(srcs[0], cfg["I0"]) * 0.01
+    ora = oracle_at(cfg, srcs, 50)
+    run = gpu_from_oracle(P, cfg, srcs, ora)
+    ora.run(10)
+    run.step(10)
+    err, only = particle_errors(run.get_state(), ora.state(), cfg["dx"])
+    n = len(err["ids"])
+    tol = 1e-5
+    bad = (err["p"] > tol) | (err["pos"] > tol) | (err["tau"] > tol)
+    nflip = int(np.sum(bad)) + len(only)
+    e = np.maximum(np.maximum(err["p"], err["pos"]), err["tau"])
+    hist = np.histogram(e[bad], bins=[1e-5, 1e-4, 1e-3, 1e-2, np.inf])[0]
+    ref = ora.state()
+    ke = 0.51099895 * (np.sqrt(1.0 + np.sum((ref["p"] / 2.7309245e-22) ** 2, axis=1)) - 1.0)   # MeV
+    o = np.argsort(ref["ids"])
+    kid = dict(zip(ref["ids"][o], ke[o]))
+    worst = np.argsort(-e)[:8]
+    print("  worst: " + " ".join(f"{e[k]:.1e}@{kid.get(err['ids'][k], -1):.3f}MeV" for k in worst)
+          + f"; median energy {np.median(ke):.3f} MeV", flush=True)
+    print(f"  n={n} max|dp|={err['p'][~bad].max():.2e} max|dx|/dx={err['pos'][~bad].max():.2e} "
+          f"max|dtau|={err['tau'][~bad].max():.2e} flips={nflip} (error 1e-5..1e-4: {hist[0]}, "
+          f"..1e-3: {hist[1]}, ..1e-2: {hist[2]}, above: {hist[3]}; one side only {len(only)})", flush=True)
+    assert n > 1000
+    assert not only and e.max() <= 1e-4, (e.max(), only[:10])
+    assert nflip <= 0.03 * n, nflip
+    run.close()
+
+
 def test_whole_run_fp64_no_field_feedback(P):
     """The whole small workload (1e4 electrons, 200 steps) with the push in
     fields switched off, so particles are independent: every particle, the
@@ -172,10 +210,12 @@ def test_whole_run_fp64_no_field_feedback(P):
 
 def test_whole_run_fp32_no_field_feedback(P):
     """FP32-mixed whole run (200 steps) without field feedback against the FP64
-    oracle.  FP32 rounding accumulates along each trajectory, so per-particle
-    errors are reported, not bounded; the conversion efficiency must agree within
-    1e-4, the histograms within 1e-3 in L1 (a handful of photons change bin),
-    and every physical ledger term within 1e-3."""
+    oracle.  FP32 rounding accumulates along each trajectory (200 Davies
+    rotations), so per-particle errors are reported, not bounded; the
+    conversion efficiency must agree within 1e-4, the energy spectrum (the
+    histogram summed over angle) within 1e-4 in L1, the (E, theta) histogram
+    within 5e-4 (photons near an angle-bin edge change bin with the drift of
+    their electron's direction), and every physical ledger term within 1e-4."""
     cfg, srcs, steps = small_config(10000, precision=W.FP32_MIXED, brem_boost=10.0,
                                     physics=W.PHYS_ALL & ~W.PHYS_FIELDS)
     ora = oracle_at(cfg, srcs, steps)
@@ -187,14 +227,22 @@ def test_whole_run_fp32_no_field_feedback(P):
     t = run.tally()
     eff_rel = abs(t["conversion"] - ora.conversion_efficiency()) / ora.conversion_efficiency()
     h_l1 = np.sum(np.abs(t["hist_E"] - ora.hist_E)) / np.sum(ora.hist_E)
+    shp = (cfg["tally_nE"], cfg["tally_ntheta"])
+    ge, re_ = np.reshape(t["hist_E"], shp), np.reshape(ora.hist_E, shp)
+    e_l1 = np.sum(np.abs(ge.sum(axis=1) - re_.sum(axis=1))) / np.sum(re_)
+    a_l1 = np.sum(np.abs(ge.sum(axis=0) - re_.sum(axis=0))) / np.sum(re_)
+    dled = {k: abs(t["ledger"][k] - ora.ledger[k]) / abs(ora.ledger[k])
+            for k in ("injected", "ionisation", "rad_discrete", "reflux", "photon_thr")}
     pct = np.percentile(err["p"], [50, 90, 99])
     print(f"  alive={len(err['ids'])} only-one-side={len(only)} |dp| p50/p90/p99={pct} "
-          f"eff rel={eff_rel:.2e} hist L1={h_l1:.2e}", flush=True)
+          f"eff rel={eff_rel:.2e} hist L1={h_l1:.2e} (energy {e_l1:.2e}, angle {a_l1:.2e}); ledger "
+          + " ".join(f"{k} {v:.1e}" for k, v in dled.items()), flush=True)
     assert len(only) < 0.01 * len(err["ids"])
     assert eff_rel < 1e-4
-    assert h_l1 < 1e-3
-    for k in ("injected", "ionisation", "rad_discrete", "reflux", "photon_thr"):
-        assert abs(t["ledger"][k] - ora.ledger[k]) <= 1e-3 * abs(ora.ledger[k]), k
+    assert e_l1 < 1e-4
+    assert h_l1 < 5e-4
+    for k, v in dled.items():
+        assert v <= 1e-4, k
     run.close()
 
 
@@ -337,7 +385,8 @@ def test_f_sigma_enhancement(P, precision, tol):
     t = run.tally()
     dh = ora.hist_E - h0
     l1 = np.sum(np.abs(t["hist_E"] - dh)) / np.sum(np.abs(dh))   # the GPU tallies the 2 steps
-    assert l1 <= (1e-9 if precision == W.FP64 else 1e-3), l1
+    print(f"  2-step histogram L1 {l1:.2e}", flush=True)
+    assert l1 <= (1e-9 if precision == W.FP64 else 1e-4), l1
     assert np.sum(dh) > 0
     run.close()
 
@@ -376,6 +425,33 @@ def test_envelope_injection(P, precision, tol):
 
 
 DELTA_PHYS = (W.PHYS_ALL & ~W.PHYS_FIELDS) | W.PHYS_DELTA
+
+
+@pytest.mark.parametrize("sort_every", [1, 4])
+def test_delta_rays_leave_injection_slots(P, sort_every):
+    """A delta-ray run whose particle buffer holds exactly the scheduled
+    injections: the delta rays may only take the slots that stopped,
+    escaped or (between sorts) dead electrons leave, never those of the
+    injections still to come.  Every scheduled electron is injected, none is
+    lost, the delta rays without a slot are counted and booked as stopped
+    (the ledger closes), and the tally reports no error."""
+    cfg, srcs, _ = small_config(6000, brem_boost=10.0, physics=DELTA_PHYS, sort_every=sort_every,
+                                max_particles=6000)
+    run = P.Run(cfg)
+    run.inject(srcs[0])
+    run.step(120)
+    t = run.tally()
+    led = t["ledger"]
+    out = (t["kinetic"] + led["field_loss"] - led["field_gain"] + led["ionisation"] + led["stopped"]
+           + led["rad_discrete"] + led["rad_subcut"] + led["escaped"] + led["reflux"] + led["residual"])
+    print(f"  injected {t['counters']['n_injected']}, delta rays {t['counters']['n_delta']}, "
+          f"without a slot {t['counters']['n_delta_lost']}, alive {t['n_alive']}", flush=True)
+    assert t["counters"]["n_injected"] == 6000
+    assert t["counters"]["n_injection_lost"] == 0
+    assert t["counters"]["n_delta_lost"] > 0
+    assert t["n_alive"] <= 6000
+    assert abs(led["injected"] - out) <= 1e-6 * led["injected"]
+    run.close()
 
 
 @pytest.mark.parametrize("sort_every", [0, 3])
@@ -487,11 +563,13 @@ def test_depth_dose_benchmark_setup(P, precision):
         for k in ("injected", "ionisation", "stopped", "escaped"):
             assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-9), k
     else:
+        dl = {k: abs(t["ledger"][k] - ora.ledger[k]) / abs(ora.ledger[k]) for k in ("injected", "ionisation", "escaped")}
+        print("  FP32 ledger rel " + " ".join(f"{k} {v:.1e}" for k, v in dl.items()), flush=True)
         # a few discrete decisions (escape through the front, removal) flip in FP32
         assert abs(t["counters"]["n_escaped"] - ora.counters["n_escaped"]) <= 0.01 * 3200
-        assert l1 < 2e-2
+        assert l1 < 2e-3
         for k in ("injected", "ionisation", "escaped"):
-            assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=2e-2), k
+            assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-4), k
     assert t["counters"]["n_reflux"] == 0
     run.close()
 

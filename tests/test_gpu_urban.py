@@ -119,10 +119,12 @@ def test_depth_dose_with_urban_scatter(P, precision):
         for k in ("injected", "ionisation", "stopped", "escaped"):
             assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-9), k
     else:
+        dl = {k: abs(t["ledger"][k] - ora.ledger[k]) / abs(ora.ledger[k]) for k in ("injected", "ionisation", "escaped")}
+        print("  FP32 ledger rel " + " ".join(f"{k} {v:.1e}" for k, v in dl.items()), flush=True)
         assert abs(t["counters"]["n_escaped"] - ora.counters["n_escaped"]) <= 0.01 * 3200
-        assert l1 < 2e-2
+        assert l1 < 2e-3
         for k in ("injected", "ionisation", "escaped"):
-            assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=2e-2), k
+            assert t["ledger"][k] == pytest.approx(ora.ledger[k], rel=1e-4), k
     run.close()
 
 
