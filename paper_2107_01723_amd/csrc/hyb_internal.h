@@ -129,6 +129,16 @@ struct Solid {
   double a_s;     // atomic screening length 1.4 a_B Z^(-1/3)
   double ln_as;   // ln(a_s m_e c / hbar), the complete-screening logarithm
   double tc_c;    // electron-ion exchange: 1 / tau = tc_c lnL / (Te m_i + Ti m_e)^1.5
+  // products and quotients of constants the per-cell update multiplies by
+  double t_ev;    // k_B / (e Z^(4/3)): Te [K] -> More's reduced temperature [eV]
+  double ld_e;    // e^2 / (eps0 k_B): 1 / lambda_D^2 per n_e / T
+  double ld_i;    // e^2 n_i / (eps0 k_B): the ions' share per Z*^2 / Ti
+  double bc2;     // (e^2 / (12 pi eps0 k_B))^2: classical closest approach^2 * (T / Z*)^2
+  double bq2;     // hbar^2 / (12 m_e k_B): de Broglie length^2 * T
+  double r02;     // r0^2
+  double inv_znk; // 1 / (Z n_i k_B)
+  double tcold;   // lambda1 r0 sqrt(m_e / 3): tau_cold = tcold / sqrt(k_B Te)
+  double eta_c;   // lambda2 m_e / (n_i e^2): eta = eta_c / (Z* tau)
 };
 
 // A compound solid (App. A): its elements, each as if it filled the cell at

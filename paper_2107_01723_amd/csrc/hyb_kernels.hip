@@ -1828,7 +1828,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
       bool in[kGatherU];
       int at[kGatherU], usem[kGatherU];
       long long a0[kGatherU];
-      long long w[kGatherU][HC ? 1 : 8];
+      using W = std::conditional_t<HC, long long, A>;   // partials: 32-bit words in FP32 runs
+      W w[kGatherU][HC ? 1 : 8];
 #pragma unroll
       for (int g = 0; g < kGatherU; ++g) {
         const int vx = vx0 + g;
@@ -1844,7 +1845,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
                            st[buf][g][13 + dx + 3 * dy + 9 * dz] == stampv;
           const long long u = (vx + dx) + (long long)R.ntx * ((vy + dy) + (long long)R.nty * (vz + dz));
           const long long wa = use ? pb[m] + u * pstr : 0;
-          w[g][m] = HC ? ph[wa] : (long long)pj[wa];
+          if constexpr (HC) w[g][m] = ph[wa];
+          else w[g][m] = pj[wa];
           usem[g] |= use ? 1 << m : 0;
         }
       }
@@ -1990,8 +1992,8 @@ __global__ __launch_bounds__(kBlock) void k_heat(const RunDesc* __restrict__ run
     const double jz = (double)(Jz[n] + Jz[n + 1] + Jz[n + sx] + Jz[n + 1 + sx]) * ju;
     double Te = G(R.Te)[c], Ti = G(R.Ti)[c], eta = eta_in[c], fs = 1.0;
     const double j2 = jx * jx + jy * jy + jz * jz, qh = (double)G(R.ion_heat)[c] * R.heat_unit;
-    if (!MIX || R.mix.n == 1) heat_cell(sol, Te, Ti, eta, j2, qh, R.dt, dV, fixed, want_fs ? &fs : nullptr);
-    else heat_cell_mix(R.mix, Te, Ti, eta, j2, qh, R.dt, dV, fixed);
+    if (!MIX || R.mix.n == 1) heat_cell(sol, Te, Ti, eta, j2, qh, R.dt, dV, fixed, want_fs, fs);
+    else heat_cell_mix(R.mix, Te, Ti, eta, j2, qh, R.dt, dV, fixed, false, fs);
     if (want_fs) {
       if (R.precision == 0) G((double*)R.fsig)[c] = fs;
       else G((float*)R.fsig)[c] = (float)fs;

@@ -24,6 +24,16 @@ __host__ __device__ inline Solid make_solid(double Z, double A, double rho, doub
   const double a_bohr = 4.0 * kPi * kEps0 * kHbar * kHbar / (kMe * kE * kE);
   s.a_s = 1.4 * a_bohr / cbrt(Z);
   s.ln_as = log(s.a_s * kMe * kC / kHbar);
+  s.t_ev = kKb / kE / s.z43;
+  s.ld_e = kE * kE / (kEps0 * kKb);
+  s.ld_i = kE * kE * n_i / (kEps0 * kKb);
+  const double bc = kE * kE / (12.0 * kPi * kEps0 * kKb);
+  s.bc2 = bc * bc;
+  s.bq2 = kHbar * kHbar / (12.0 * kMe * kKb);
+  s.r02 = s.r0 * s.r0;
+  s.inv_znk = 1.0 / (Z * n_i * kKb);
+  s.tcold = lambda1 * s.r0 * sqrt(kMe / 3.0);
+  s.eta_c = lambda2 * kMe / (n_i * kE * kE);
   return s;
 }
 
@@ -34,15 +44,17 @@ __host__ __device__ inline double zstar(const Solid& s, double Te) {
   const double a1 = 0.003323, a2 = 0.971832, a3 = 9.26148e-5, a4 = 3.10165;
   const double b0 = -1.7630, b1 = 1.43175, b2 = 0.31546;
   const double c1 = -0.366667, c2 = 0.983333;
-  const double T0 = Te * kKb / kE / s.z43;
+  const double T0 = Te * s.t_ev;
   const double Tf = T0 / (1.0 + T0);
   const double lnT0 = log(T0);
   const double Ac = a1 * exp(a2 * lnT0) + a3 * exp(a4 * lnT0);
   const double Tf2 = Tf * Tf, Tf7 = Tf2 * Tf2 * Tf2 * Tf;
   const double Bc = -exp(b0 + b1 * Tf + b2 * Tf7);
-  const double Cc = c1 * Tf + c2;
+  const double Cc = c1 * Tf + c2;                                    // > 0.6 for Tf in [0, 1]
   const double lnQ1 = log(Ac) + Bc * s.lnR;                          // Q1 = Ac R^Bc
-  const double lnQ = log(exp(Cc * s.lnR) + exp(Cc * lnQ1)) / Cc;     // Q = (R^C + Q1^C)^(1/C)
+  // Q = (R^C + Q1^C)^(1/C): ln Q = max + ln(1 + e^(-C |ln Q1 - ln R|)) / C
+  const double dl = lnQ1 - s.lnR;
+  const double lnQ = (dl > 0.0 ? lnQ1 : s.lnR) + log1p(exp(-Cc * fabs(dl))) / Cc;
   const double x = alpha * exp(beta * lnQ);
   return s.Z * x / (1.0 + x + sqrt(1.0 + 2.0 * x));
 }
@@ -55,14 +67,11 @@ __host__ __device__ inline double coulomb_log(const Solid& s, double Te, double 
   const double ne = Zs * s.n_i;
   const double c = cbrt(ne);
   const double TF = s.tf_c * c * c;
-  const double Teff = sqrt(Te * Te + TF * TF);
-  const double inv_ld2 = kE * kE * ne / (kEps0 * kKb * Teff) + Zs * Zs * kE * kE * s.n_i / (kEps0 * kKb * Ti);
-  const double lam_d = 1.0 / sqrt(inv_ld2);
-  const double bmax = fmax(lam_d, s.r0);
-  const double bmin = fmax(Zs * kE * kE / (12.0 * kPi * kEps0 * kKb * Teff),
-                           kHbar / (2.0 * sqrt(3.0 * kMe * kKb * Teff)));
-  const double r = bmax / bmin;
-  return fmax(2.0, 0.5 * log(1.0 + r * r));
+  const double rT = 1.0 / sqrt(Te * Te + TF * TF);   // 1 / Teff
+  const double inv_ld2 = s.ld_e * ne * rT + s.ld_i * Zs * Zs / Ti;
+  const double bmax2 = fmax(1.0 / inv_ld2, s.r02);
+  const double bmin2 = fmax(s.bc2 * Zs * Zs * rT * rT, s.bq2 * rT);
+  return fmax(2.0, 0.5 * log(1.0 + bmax2 / bmin2));
 }
 
 // Bremsstrahlung enhancement by the ionised background, eq. (F_sigma):
@@ -79,10 +88,10 @@ __host__ __device__ inline double f_sigma(const Solid& s, double Ti, double Zs) 
 // tau = max(hot, cold) limits of App. A; Zs = Z*(Te).
 __host__ __device__ inline double resistivity_z(const Solid& s, double Te, double Ti, double Zs) {
   const double lnL = coulomb_log(s, Te, Ti, Zs);
-  const double kT = kKb * Te;
-  const double tau_hot = s.th_c * kT * sqrt(kT) / (Zs * Zs * s.n_i * lnL);
-  const double tau_cold = s.lambda1 * s.r0 / sqrt(3.0 * kT / kMe);
-  return s.lambda2 * kMe / (Zs * s.n_i * kE * kE * fmax(tau_hot, tau_cold));
+  const double kT = kKb * Te, skT = sqrt(kT);
+  const double tau_hot = s.th_c * kT * skT / (Zs * Zs * s.n_i * lnL);
+  const double tau_cold = s.tcold / skT;             // lambda1 r0 / sqrt(3 k_B Te / m_e)
+  return s.eta_c / (Zs * fmax(tau_hot, tau_cold));
 }
 
 __host__ __device__ inline double resistivity(const Solid& s, double Te, double Ti) {
@@ -91,19 +100,19 @@ __host__ __device__ inline double resistivity(const Solid& s, double Te, double 
 
 // Heat capacity per electron in units of kB, App. A.
 __host__ __device__ inline double heat_capacity(const Solid& s, double Te) {
-  const double Tp = kKb * Te / kE / s.z43;
+  const double Tp = Te * s.t_ev;
   return 0.3 + 1.2 * Tp * (2.2 + Tp) / ((1.1 + Tp) * (1.1 + Tp));
 }
 
 // One cell: Ohmic + collisional heating eq. (Te_rise), exact electron-ion
-// exchange with rates frozen after heating, new resistivity and, if fs is
-// given, the new eq. (F_sigma) factor.
+// exchange with rates frozen after heating, new resistivity and, if want_fs,
+// the new eq. (F_sigma) factor in fs.
 __host__ __device__ inline void heat_cell(const Solid& s, double& Te, double& Ti, double& eta, double j2,
                                           double ion_heat_J, double dt, double dV, bool fixed_eta,
-                                          double* fs = nullptr) {
+                                          bool want_fs, double& fs) {
   const double rho_eps = eta * j2 * dt + ion_heat_J / dV;
   const double C = heat_capacity(s, Te);
-  const double Te1 = Te + rho_eps / (s.Z * s.n_i * C * kKb);
+  const double Te1 = Te + rho_eps * s.inv_znk / C;
   const double Zs1 = zstar(s, Te1);
   const double lnL1 = coulomb_log(s, Te1, Ti, Zs1);
   const double denom = Te1 * s.m_i + Ti * kMe;
@@ -111,17 +120,17 @@ __host__ __device__ inline void heat_cell(const Solid& s, double& Te, double& Ti
   const double e4 = kE * kE * kE * kE;
   const double a = Zs1 * Zs1 * e4 * s.n_i * inv_tc;
   const double b = Zs1 * Zs1 * Zs1 * e4 * s.n_i * inv_tc;
-  const double sum = a + b;
-  const double M = (b * Te1 + a * Ti) / sum;
+  const double sum = a + b, rs = 1.0 / sum;
+  const double M = (b * Te1 + a * Ti) * rs;
   const double D = (Te1 - Ti) * exp(-sum * dt);
-  const double Te2 = M + a / sum * D;
-  const double Ti2 = M - b / sum * D;
+  const double Te2 = M + a * rs * D;
+  const double Ti2 = M - b * rs * D;
   Te = Te2;
   Ti = Ti2;
-  if (fixed_eta && !fs) return;
+  if (fixed_eta && !want_fs) return;
   const double Zs2 = zstar(s, Te2);
   if (!fixed_eta) eta = resistivity_z(s, Te2, Ti2, Zs2);
-  if (fs) *fs = f_sigma(s, Ti2, Zs2);
+  if (want_fs) fs = f_sigma(s, Ti2, Zs2);
 }
 
 // Compound resistivity: sum(x Z* eta_el) / sum(x Z*), each element's
@@ -145,9 +154,9 @@ __host__ __device__ inline double resistivity_mix(const Mix& m, double Te, doubl
 // resistivity.  One element: heat_cell.
 __host__ __device__ inline void heat_cell_mix(const Mix& m, double& Te, double& Ti, double& eta, double j2,
                                               double ion_heat_J, double dt, double dV, bool fixed_eta,
-                                              double* fs = nullptr) {
+                                              bool want_fs, double& fs) {
   if (m.n == 1) {
-    heat_cell(m.el[0], Te, Ti, eta, j2, ion_heat_J, dt, dV, fixed_eta, fs);
+    heat_cell(m.el[0], Te, Ti, eta, j2, ion_heat_J, dt, dV, fixed_eta, want_fs, fs);
     return;
   }
   const double rho_eps = eta * j2 * dt + ion_heat_J / dV;
