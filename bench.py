@@ -47,18 +47,18 @@ METRIC = "macro-electron steps/s (FP32-mixed vs FP64, same GPU); p50/p99 scan-ru
 
 # (name, workload function, precision, description)
 WORKLOADS = (
-    ("c5_fp32", "config_huge", 1, "gold slab 250 um, 512^3 cells of 0.5 um, 2e8 macro-electrons, "
+    ("gold_512cube_2e8_fp32", "config_huge", 1, "gold slab 250 um, 512^3 cells of 0.5 um, 2e8 macro-electrons, "
                                   "T_hot 10.8 MeV (1e22 W/cm^2), 2 um spot, 30 deg cone, dt 10 fs, "
                                   "paper reflux, 128x180 tally"),
-    ("c5_fp64", "config_huge", 0, None),
-    ("c3_fp32", "config_mixed_large", 1, "gold slab x in [2, 254] um, 256^3 cells of 1 um, 1e8 "
+    ("gold_512cube_2e8_fp64", "config_huge", 0, None),
+    ("gold_256cube_1e8_fp32", "config_mixed_large", 1, "gold slab x in [2, 254] um, 256^3 cells of 1 um, 1e8 "
                                          "macro-electrons, T_hot 10.8 MeV, 5 um spot, 30 deg cone, "
                                          "dt 20 fs, 1 % energy loss per reflux, 64x90 tally"),
-    ("c3_fp64", "config_mixed_large", 0, None),
-    ("c2_fp64", "config_fp64_large", 0, "gold slab 200 um, 256x128x128 cells of 1 um, 2e7 "
+    ("gold_256cube_1e8_fp64", "config_mixed_large", 0, None),
+    ("gold_256x128x128_2e7_fp64", "config_fp64_large", 0, "gold slab 200 um, 256x128x128 cells of 1 um, 2e7 "
                                         "macro-electrons, T_hot 3.4 MeV (1e21 W/cm^2), 3 um spot, "
                                         "40 deg cone, dt 20 fs, paper reflux, 64x90 tally"),
-    ("c2_fp32", "config_fp64_large", 1, None),
+    ("gold_256x128x128_2e7_fp32", "config_fp64_large", 1, None),
 )
 
 KERNEL_SOURCES = ("paper_2107_01723_amd/csrc/hyb_kernels.hip", "paper_2107_01723_amd/csrc/hyb_internal.h",
@@ -299,10 +299,14 @@ def main():
         del src, dst, evict
 
     only = [x for x in a.only.split(",") if x]
+    unknown = [x for x in only if x not in [w[0] for w in WORKLOADS]]
+    if unknown:
+        print(f"bench.py: unknown workload(s) {unknown}; known: {[w[0] for w in WORKLOADS]}", file=sys.stderr)
+        sys.exit(2)
     res, desc = {}, {}
     for name, fn, prec, d in WORKLOADS:
         if d:
-            desc[name.split("_")[0]] = d
+            desc[name.rsplit("_", 1)[0]] = d
         if only and name not in only:
             continue
         cfg, srcs, _ = getattr(W, fn)()
@@ -321,10 +325,10 @@ def main():
                                ("urban_scatter", W.PHYS_URBAN, 1.0)):
             cfg, srcs, _ = W.config_fp64_large()
             cfg = dict(cfg, physics=cfg["physics"] | bit, max_particles=int(cfg["max_particles"] * extra))
-            r = time_run(P, "c2_fp64_" + nm, cfg, srcs, a.steps, a.warmup)
+            r = time_run(P, "gold_256x128x128_2e7_fp64_" + nm, cfg, srcs, a.steps, a.warmup)
             opt_in[nm] = {k: r[k] for k in ("value", "ms_per_step", "particle_kernel_ms", "alive_mean",
                                             "roofline", "ledger_closure", "n_delta", "n_delta_lost")}
-            print(f"# c2 fp64 + {nm}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+            print(f"# gold_256x128x128_2e7_fp64 + {nm}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     model = None
     if a.model:
         import numpy as np
@@ -354,8 +358,8 @@ def main():
         print(f"# cpu oracle: {cpu['value']:.3e} electron-steps/s (particles), "
               f"{cpu['headline_sample']['cell_steps_per_s']:.3e} cell-steps/s", file=sys.stderr, flush=True)
 
-    head = res.get("c5_fp32") or next(iter(res.values()), None)
-    hname = "c5_fp32" if "c5_fp32" in res else (next(iter(res)) if res else None)
+    head = res.get("gold_512cube_2e8_fp32") or next(iter(res.values()), None)
+    hname = "gold_512cube_2e8_fp32" if "gold_512cube_2e8_fp32" in res else (next(iter(res)) if res else None)
     line = {"metric": METRIC, "unit": "macro-electron steps/s", "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "data": "synthetic"}
@@ -364,7 +368,7 @@ def main():
         line.update(
             value=head["value"], ms_per_step=head["ms_per_step"],
             dtype="f32" if fp32 else "f64",
-            config={"workload": f"{hname}: {desc[hname.split('_')[0]]}; "
+            config={"workload": f"{hname}: {desc[hname.rsplit('_', 1)[0]]}; "
                                 + ("FP32-mixed (FP32 particle state, push and table sampling; FP64 heating "
                                    "and resistivity; int64 fixed-point current, ledger and tallies)" if fp32
                                    else "FP64 throughout (int64 fixed-point current, ledger and tallies)")
@@ -374,14 +378,14 @@ def main():
             roofline=head["roofline"], step_roofline=head["step_roofline"],
             particle_kernel_ms=head["particle_kernel_ms"], injection_phase=head["injection_phase"],
             ledger_closure=head["ledger_closure"])
-        if hname == "c5_fp32" and "c5_fp64" in res:
-            f64 = res["c5_fp64"]
+        if hname == "gold_512cube_2e8_fp32" and "gold_512cube_2e8_fp64" in res:
+            f64 = res["gold_512cube_2e8_fp64"]
             line["fp64"] = {k: f64[k] for k in ("value", "ms_per_step", "particle_kernel_ms", "roofline",
                                                 "step_roofline", "injection_phase", "ledger_closure")}
             line["mixed_over_fp64"] = round(head["value"] / f64["value"], 3)
-        line["workloads"] = {k: v for k, v in res.items() if k not in (hname, "c5_fp64" if hname == "c5_fp32" else "")}
+        line["workloads"] = {k: v for k, v in res.items() if k not in (hname, "gold_512cube_2e8_fp64" if hname == "gold_512cube_2e8_fp32" else "")}
         ratios = {}
-        for c in ("c5", "c3", "c2"):
+        for c in {k.rsplit("_", 1)[0] for k in res}:
             if f"{c}_fp32" in res and f"{c}_fp64" in res:
                 ratios[c] = round(res[f"{c}_fp32"]["value"] / res[f"{c}_fp64"]["value"], 3)
         line["mixed_over_fp64_by_workload"] = ratios
