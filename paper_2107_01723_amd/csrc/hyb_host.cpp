@@ -484,7 +484,7 @@ static void add_run_plans(PlanSpec& ps, int run, const RunDesc& h) {
   int npb = clampi((cap + 255) / 256, 8, 4096);
   npb = (npb + 7) / 8 * 8;
   add(ps.particle, npb);
-  add(ps.gather, clampi((long long)((h.ny >> 2) + 1) * ((h.nz >> 2) + 1), 1, 4096));   // rows of tiles
+  add(ps.gather, clampi((long long)((h.ny >> 2) + 1) * ((h.nz >> 2) + 1) * gather_segments(h.nx), 1, 4096));
   add(ps.grid, clampi((h.nodes + 511) / 512, 1, 4096));
   const long long sc = (long long)(h.ix_hi - h.ix_lo) * h.ny * h.nz;
   add(ps.cells, clampi((sc + 255) / 256, 1, 4096));

@@ -274,6 +274,13 @@ constexpr int kNoTile = 0x7FFFFFFF;
 constexpr int kHistCopies = 32;
 constexpr int kScanTile = 1024;    // tiles per scan block
 
+// Segments of a row of tiles that the gather's workgroups take apart: rows
+// of (nx >> 2) + 1 tiles in groups of 4, at most 8 groups per segment.
+__host__ __device__ __forceinline__ uint32_t gather_segments(int nx) {
+  const uint32_t ngr = ((uint32_t)(nx >> 2) + 1 + 3) / 4;
+  return (ngr + 7) / 8;
+}
+
 // Does the step `step` end with a tile sort?
 __host__ __device__ __forceinline__ bool sort_step(int sort_every, long long step) {
   return sort_every > 0 && (step + 1) % sort_every == 0;

@@ -1790,24 +1790,33 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
   const long long pstr = hc ? kTile * kTile * kTile : 3 * kHaloN;   // words per tile
   const gptr<const A> pj = G((const A*)R.pj);
   const gptr<const long long> ph = G((const long long*)R.ph);
-  // A workgroup sweeps whole rows of tiles along x, kGatherU tiles per
-  // iteration, so that the partials and the node rows are read as
-  // sequential streams; the workgroups stride over the rows, so that those
-  // running at a time share one window of the grid.  The claims of the 27
-  // tiles around each tile of an iteration are staged in LDS one iteration
-  // ahead.
+  // A workgroup sweeps segments of rows of tiles along x (up to 8 groups of
+  // kGatherU tiles, one group per iteration), so that the partials and the
+  // node rows are read as sequential streams; the workgroups stride over
+  // the segments, so that those running at a time share one window of the
+  // grid.  The claims of the 27 tiles around each tile of an iteration are
+  // staged in LDS one iteration ahead.
   const uint32_t ngr = (uint32_t)(gx + kGatherU - 1) / kGatherU, nrows = (uint32_t)gy * gz;
-  const uint32_t myrows = (uint32_t)bm.lb < nrows ? (nrows - 1 - bm.lb) / bm.nb + 1 : 0;
-  const uint32_t nit = myrows * ngr;
+  const uint32_t nseg = gather_segments(R.nx), kseg = (ngr + nseg - 1) / nseg;   // segments per row, groups per segment
+  const uint32_t nunit = nrows * nseg;
+  const uint32_t myunits = (uint32_t)bm.lb < nunit ? (nunit - 1 - bm.lb) / bm.nb + 1 : 0;
+  const uint32_t nit = myunits * kseg;
+  auto place = [&](uint32_t it, int& vx0, int& vy, int& vz) {   // first tile of iteration it's group
+    const uint32_t unit = bm.lb + (it / kseg) * bm.nb;
+    const uint32_t row = unit / nseg;
+    const uint32_t vzu = R.fd_gy.div(row);
+    vy = (int)(row - vzu * (uint32_t)gy);
+    vz = (int)vzu;
+    vx0 = (int)((unit - row * nseg) * kseg + it % kseg) * kGatherU;
+  };
   __shared__ int st[2][kGatherU][27];
   const bool stager = threadIdx.x < 27 * kGatherU;
   auto claim_of = [&](uint32_t it) -> int {   // the claim a stager thread stages for iteration it
     if (it >= nit) return 0;
     const int g = (int)threadIdx.x / 27, n = (int)threadIdx.x % 27;
-    const uint32_t row = bm.lb + (it / ngr) * bm.nb;
-    const uint32_t vzu = R.fd_gy.div(row);
-    const int ux = (int)(it % ngr) * kGatherU + g + n % 3 - 1, uy = (int)(row - vzu * (uint32_t)gy) + (n / 3) % 3 - 1,
-              uz = (int)vzu + n / 9 - 1;
+    int vx0, vy, vz;
+    place(it, vx0, vy, vz);
+    const int ux = vx0 + g + n % 3 - 1, uy = vy + (n / 3) % 3 - 1, uz = vz + n / 9 - 1;
     const bool in = ux >= 0 && uy >= 0 && uz >= 0 && ux < R.ntx && uy < R.nty && uz < R.ntz;
     return in ? G((const int*)R.tstamp)[ux + R.ntx * (uy + R.nty * uz)] : 0;
   };
@@ -1822,9 +1831,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
     int buf = 0;
     for (uint32_t it = 0; it < nit; ++it, buf ^= 1) {
       const int nxt = stager ? claim_of(it + 1) : 0;   // lands while this iteration's loads run
-      const uint32_t row = bm.lb + (it / ngr) * bm.nb;
-      const uint32_t vzu = R.fd_gy.div(row);
-      const int vy = (int)(row - vzu * (uint32_t)gy), vz = (int)vzu, vx0 = (int)(it % ngr) * kGatherU;
+      int vx0, vy, vz;
+      place(it, vx0, vy, vz);
       bool in[kGatherU];
       int at[kGatherU], usem[kGatherU];
       long long a0[kGatherU];
