@@ -10,6 +10,7 @@ their slot and memory for the queue.  Latency is arrival -> tally returned.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -58,7 +59,7 @@ def run_scan(requests, ticks_per_poll: int = 8, max_runs: int = 64, hbm_budget: 
                 eng.retire(r)
                 if verbose:
                     print(f"# run {i:3d} done: latency {lat[i]:7.2f} s, resident {len(resident)}, "
-                          f"queued {len(queue)}", flush=True)
+                          f"queued {len(queue)}", file=sys.stderr, flush=True)
         elif pending:
             time.sleep(max(0.0, min(0.05, requests[pending[0]]["arrival"] - now)))
     torch.cuda.synchronize()
