@@ -90,12 +90,16 @@ def step_bytes(precision: int, electrons: float, nodes: int, solid_cells: int, n
 
 
 def kernel_digest() -> str:
-    """Digest of the device sources; a counter summary holds the digest of
-    the kernels it was taken on."""
+    """Digest of the device sources without their comments and blank lines
+    (what the compiler sees); a counter summary holds the digest of the
+    kernels it was taken on."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        code = [ln.split("//", 1)[0].rstrip() for ln in src.splitlines()]
+        h.update("\n".join(ln for ln in code if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

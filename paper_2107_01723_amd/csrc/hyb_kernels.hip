@@ -320,13 +320,15 @@ __device__ __forceinline__ bool boundary_axis(const RunDesc& R, int axis, int& c
 // its 4x4x4 cells of collisional heat; the two most populated regions also
 // stage their field halos for the gather; destinations are counted in the
 // 5x5x5 tiles around the most populated one, where its electrons can move in
-// one step; everything else falls back to global gathers and atomics.  The
-// LDS sums are flushed with one atomic per non-zero entry.
+// one step; everything else falls back to global gathers and atomics.  A
+// region's sums go to HBM as its tile's partials (plain stores) if this
+// workgroup holds the tile's claim for the step, else with one atomic per
+// non-zero entry into the accumulators; k_gather adds both into j_h.
 // ---------------------------------------------------------------------------
 // Current contributions are fixed point.  FP64 runs use 2^40 units per
 // (e w_ref c / dx^3) in 64-bit LDS words.  FP32-mixed runs round each
-// contribution to 2^20 units and sum them in 32-bit LDS words, widened to the
-// 2^40 HBM accumulators at the flush.  Every contribution is rounded the same
+// contribution to 2^20 units and sum them in 32-bit LDS words (and partials),
+// widened to the 2^40 HBM accumulators at the flush or in the gather.  Every contribution is rounded the same
 // way whether it goes through LDS or straight to HBM, so the sums stay
 // independent of the electron order.
 //
