@@ -38,7 +38,7 @@ size_t hist_stride(const hyb_config& c) {
 // Sizes of everything a run keeps in device memory.
 struct Layout {
   size_t off_E[3], off_B[3], off_J[3], off_Te, off_Ti, off_eta[2], off_heat, off_fsig;
-  size_t off_Jacc[3], off_heat_acc, off_stamp, off_pj, off_ph;
+  size_t off_Jacc[3], off_heat_acc, off_stamp, off_dirty, off_pj, off_ph;
   size_t off_part[2][11];
   size_t off_sp_cell, off_sp_pid, off_sp_f[7], off_sp_cnt, off_sp_start, off_sp_blk, off_sp_grp, off_sp_gpid;
   size_t off_tabX, off_tabSIG, off_tabSUB;
@@ -72,6 +72,7 @@ Layout make_layout(const hyb_config& c) {
   for (int d = 0; d < 3; ++d) L.off_Jacc[d] = take(nodes * 8);
   L.off_heat_acc = take(cells * 8);
   L.off_stamp = take(ntl * 4);
+  L.off_dirty = take(ntl * 4);
   L.off_pj = take(ntl * 3 * kPjHalo * ts);
   L.off_ph = take(ntl * kTile * kTile * kTile * 8);
   for (int b = 0; b < 2; ++b) {
@@ -403,6 +404,7 @@ static void point_desc(hyb_run* r) {
   }
   h.heat_acc = (long long*)(b + L.off_heat_acc);
   h.tstamp = (int*)(b + L.off_stamp);
+  h.tdirty = (int*)(b + L.off_dirty);
   h.pj = b + L.off_pj;
   h.ph = (long long*)(b + L.off_ph);
   h.Te = (double*)(b + L.off_Te);
@@ -1322,6 +1324,7 @@ hyb_status hyb_set_state(hyb_run* r, const hyb_state* st) {
   HIPCHK(r, hipMemset(r->h.heat_acc, 0, cells * 8));
   // claims carry the step number, which a state may set back
   HIPCHK(r, hipMemset(r->h.tstamp, 0, (size_t)r->h.ntiles * 4));
+  HIPCHK(r, hipMemset(r->h.tdirty, 0, (size_t)r->h.ntiles * 4));
   if (delta) HIPCHK(r, hipMemset(r->h.sp_cnt, 0, (size_t)r->h.ntiles * 4));
   HIPCHK(r, hipMemset(r->h.acc_led, 0, 16 * 8));
   HIPCHK(r, hipMemset(r->h.acc_hist, 0, hist_stride(c) * kHistCopies * 8));

@@ -227,10 +227,13 @@ struct RunDesc {
   // every other contribution is added atomically into Jacc / heat_acc.  The
   // gather then sums, per node and cell, the accumulators and the partials
   // of the claimed tiles whose halos hold it into J / ion_heat, and clears
-  // the accumulators it found non-zero.
+  // the accumulators it found non-zero.  Every atomic into them marks the
+  // tile whose halo (or cell) it lands in, so that the gather reads the
+  // accumulators of the nodes and cells of marked tiles only.
   long long* Jacc[3];
   long long* heat_acc;
   int* tstamp;              // [ntiles] step + 1 of the tile's last claim (0: never)
+  int* tdirty;              // [ntiles] step + 1 of the last atomic into the tile's halo or cells
   void* pj;                 // [ntiles][3][216] current partials of the tiles (32-bit FP32, 64-bit FP64)
   long long* ph;            // [ntiles][64] heat partials of the tile's cells
   FastDiv fd_gx, fd_gy;     // by the gather's tile counts along x and y: (nx >> 2) + 1, (ny >> 2) + 1

@@ -455,9 +455,9 @@ __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
 // Moves the LDS sums of one region to HBM and clears them for the next
 // chunk: the tile's partials as whole lines of plain stores if this
 // workgroup holds the tile's claim of the step, else one atomic per
-// non-zero entry into the accumulators.
+// non-zero entry into the accumulators (the tile marked for the gather).
 template <typename T>
-__device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& L, int r, int tile) {
+__device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& L, int r, int tile, int stampv) {
   using A = typename JAcc<T>::type;
   A* J = L.J[r];
   if (L.own[r]) {
@@ -476,6 +476,7 @@ __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& 
   }
   const Home h = make_home(R, tile);
   const int sx = R.nx + 1, sxy = (R.nx + 1) * (R.ny + 1);
+  if (threadIdx.x == 0) G(R.tdirty)[tile] = stampv;
   for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
     long long v = (long long)J[t];
     if (v == 0) continue;
@@ -1022,7 +1023,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     if (!kFlushEarly && pch >= 0) {
 #pragma unroll
       for (int k = 0; k < kRegions; ++k)
-        if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k]);
+        if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k], stampv);
       if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
     }
     __syncthreads();
@@ -1082,6 +1083,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
       int js = -1;
 #pragma unroll
       for (int k = 0; k < kRegions; ++k) js = my_tile == rt[k] ? k : js;
+      // no LDS region: its current and heat go to the accumulators, and the
+      // tile is marked for the gather
+      if (js < 0) G(R.tdirty)[my_tile] = stampv;
       const int rbx = (ci & ~(kTile - 1)) - 1, rby = (cj & ~(kTile - 1)) - 1, rbz = (ck & ~(kTile - 1)) - 1;
       const int fsl = my_tile == f_tile0 ? 0 : (my_tile == f_tile1 ? 1 : -1);
       typename JAcc<T>::type* Js = js >= 0 ? S.J[js] : nullptr;
@@ -1440,7 +1444,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     if (kFlushEarly) {
 #pragma unroll
       for (int k = 0; k < kRegions; ++k)
-        if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k]);
+        if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k], stampv);
       if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
     }
   }
@@ -1448,7 +1452,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
   if (!kFlushEarly && pch >= 0) {
 #pragma unroll
     for (int k = 0; k < kRegions; ++k)
-      if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k]);
+      if (fl[k] >= 0) lds_flush_region(R, S, k, fl[k], stampv);
     if (count) lds_flush_counts(R, S, make_home(R, pta), pch, base_val, base_at);
   }
   if (base_at >= 0) G(R.chunk_base)[base_at] = base_val;
@@ -1732,6 +1736,7 @@ __global__ __launch_bounds__(kBlock) void k_spawn_append(const RunDesc* __restri
       acc[L_STOPPED] += to_fixed(e * (T)kLedScale);
       acc[L_N + C_DELTA_LOST] += 1;
       atomic_add_i64(&R.heat_acc[cell_i(c) + R.nx * (cell_j(c) + R.ny * cell_k(c))], to_fixed(e * (T)kHeatScale));
+      G(R.tdirty)[tile_of(R, cell_i(c), cell_j(c), cell_k(c))] = (int)(step + 1);
     }
   }
   block_flush<L_N, C_N>(acc, R.acc_led, R.events);
@@ -1757,7 +1762,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_step(const RunDesc* __restrict_
 // multiple of 4), each of its nodes sums the accumulator and, of the up to
 // eight tiles whose deposit halos hold the node, the partials of those
 // claimed this step; each cell its accumulator and its own tile's partial.
-// The accumulators are cleared where they were not zero.
+// Accumulators are read only where one of those tiles took an atomic this
+// step (the others hold zero), and cleared where they were not zero.
 constexpr int kGatherU = 4;   // tiles per workgroup iteration of the gather
 
 template <typename T>
@@ -1796,8 +1802,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
   // kGatherU tiles, one group per iteration), so that the partials and the
   // node rows are read as sequential streams; the workgroups stride over
   // the segments, so that those running at a time share one window of the
-  // grid.  The claims of the 27 tiles around each tile of an iteration are
-  // staged in LDS one iteration ahead.
+  // grid.  The claims and atomic marks of the 27 tiles around each tile of
+  // an iteration are staged in LDS one iteration ahead (claim: low bit set
+  // if claimed this step; mark: bit 1).  A node's accumulator is read only
+  // if one of its tiles is marked; else it loads a word it does not use.
   const uint32_t ngr = (uint32_t)(gx + kGatherU - 1) / kGatherU, nrows = (uint32_t)gy * gz;
   const uint32_t nseg = gather_segments(R.nx), kseg = (ngr + nseg - 1) / nseg;   // segments per row, groups per segment
   const uint32_t nunit = nrows * nseg;
@@ -1813,14 +1821,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
   };
   __shared__ int st[2][kGatherU][27];
   const bool stager = threadIdx.x < 27 * kGatherU;
-  auto claim_of = [&](uint32_t it) -> int {   // the claim a stager thread stages for iteration it
+  auto claim_of = [&](uint32_t it) -> int {   // the flags a stager thread stages for iteration it
     if (it >= nit) return 0;
     const int g = (int)threadIdx.x / 27, n = (int)threadIdx.x % 27;
     int vx0, vy, vz;
     place(it, vx0, vy, vz);
     const int ux = vx0 + g + n % 3 - 1, uy = vy + (n / 3) % 3 - 1, uz = vz + n / 9 - 1;
     const bool in = ux >= 0 && uy >= 0 && uz >= 0 && ux < R.ntx && uy < R.nty && uz < R.ntz;
-    return in ? G((const int*)R.tstamp)[ux + R.ntx * (uy + R.nty * uz)] : 0;
+    const long long u = in ? ux + (long long)R.ntx * (uy + (long long)R.nty * uz) : 0;
+    const int cl = G((const int*)R.tstamp)[u], mk = G((const int*)R.tdirty)[u];
+    return in ? (cl == stampv ? 1 : 0) | (mk == stampv ? 2 : 0) : 0;
   };
   if (stager) st[0][threadIdx.x / 27][threadIdx.x % 27] = claim_of(0);
   __syncthreads();
@@ -1835,7 +1845,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
       const int nxt = stager ? claim_of(it + 1) : 0;   // lands while this iteration's loads run
       int vx0, vy, vz;
       place(it, vx0, vy, vz);
-      bool in[kGatherU];
+      bool in[kGatherU], rd[kGatherU];
       int at[kGatherU], usem[kGatherU];
       long long a0[kGatherU];
       using W = std::conditional_t<HC, long long, A>;   // partials: 32-bit words in FP32 runs
@@ -1846,19 +1856,22 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
         const int i = kTile * vx + ox, j = kTile * vy + oy, k = kTile * vz + oz;
         in[g] = HC ? (i < nx && j < ny && k < nz) : (i <= nx && j <= ny && k <= nz);
         at[g] = in[g] ? (HC ? i + nx * (j + ny * k) : i + sx * j + sxy * k) : 0;
-        a0[g] = acc[at[g]];
         usem[g] = 0;
+        rd[g] = false;
 #pragma unroll
         for (int m = 0; m < (HC ? 1 : 8); ++m) {
           const int dx = m & 1 ? ax : 0, dy = m & 2 ? ay : 0, dz = m & 4 ? az : 0;
-          const bool use = in[g] && (!(m & 1) || ax) && (!(m & 2) || ay) && (!(m & 4) || az) &&
-                           st[buf][g][13 + dx + 3 * dy + 9 * dz] == stampv;
+          const bool holds = in[g] && (!(m & 1) || ax) && (!(m & 2) || ay) && (!(m & 4) || az);
+          const int fl = st[buf][g][13 + dx + 3 * dy + 9 * dz];
+          const bool use = holds && (fl & 1);
+          rd[g] |= holds && (fl & 2);
           const long long u = (vx + dx) + (long long)R.ntx * ((vy + dy) + (long long)R.nty * (vz + dz));
           const long long wa = use ? pb[m] + u * pstr : 0;
           if constexpr (HC) w[g][m] = ph[wa];
           else w[g][m] = pj[wa];
           usem[g] |= use ? 1 << m : 0;
         }
+        a0[g] = acc[rd[g] ? at[g] : 0];
       }
       __builtin_amdgcn_sched_barrier(0);   // every load above is issued before the first sum waits
 #pragma unroll
@@ -1867,9 +1880,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
 #pragma unroll
         for (int m = 0; m < (HC ? 1 : 8); ++m) a += (usem[g] >> m) & 1 ? w[g][m] : 0LL;
         if (!HC) a *= (1LL << JAcc<T>::shift);
+        const long long a0g = rd[g] ? a0[g] : 0LL;
         if (in[g]) {
-          if (a0[g] != 0) acc[at[g]] = 0;
-          out[at[g]] = a0[g] + a;
+          if (a0g != 0) acc[at[g]] = 0;
+          out[at[g]] = a0g + a;
         }
       }
       if (stager) st[buf ^ 1][threadIdx.x / 27][threadIdx.x % 27] = nxt;
