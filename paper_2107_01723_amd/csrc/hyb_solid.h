@@ -10,6 +10,35 @@
 
 namespace hyb {
 
+// Natural logarithm of a positive, finite x, within a few units in the last
+// place: x = m 2^e with m in [sqrt(1/2), sqrt(2)), and ln m = 2 atanh(s),
+// s = (m - 1) / (m + 1), |s| < 0.172, by its Taylor series
+// 2 (s + s^3/3 + ... + s^23/23) (the next term is below 2^-60 of 2s);
+// e ln 2 in two parts, the first exact for any exponent.  The per-cell
+// update is bound by FP64 issue, and this takes a third of the
+// instructions of the correctly rounded library logarithm.
+__host__ __device__ inline double ln_pos(double x) {
+  const double kLn2Hi = 0x1.62e42ffp-1, kLn2Lo = -0x1.718432a1b0e26p-35;
+  int e;
+  double m = frexp(x, &e);                     // [0.5, 1)
+  if (m < 0x1.6a09e667f3bcdp-1) { m += m; --e; }   // [sqrt(1/2), sqrt(2))
+  const double f = m - 1.0;                    // exact
+  const double s = f / (m + 1.0), z = s * s;
+  double p = 1.0 / 23.0;
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double s2 = s + s, de = (double)e;
+  return fma(de, kLn2Hi, s2 + fma(s2 * z, p, de * kLn2Lo));
+}
+
 __host__ __device__ inline Solid make_solid(double Z, double A, double rho, double n_i, double lambda1,
                                             double lambda2) {
   Solid s;
@@ -44,17 +73,20 @@ __host__ __device__ inline double zstar(const Solid& s, double Te) {
   const double a1 = 0.003323, a2 = 0.971832, a3 = 9.26148e-5, a4 = 3.10165;
   const double b0 = -1.7630, b1 = 1.43175, b2 = 0.31546;
   const double c1 = -0.366667, c2 = 0.983333;
+  const double kLnA1 = -5.706887289609679;   // ln a1
   const double T0 = Te * s.t_ev;
   const double Tf = T0 / (1.0 + T0);
-  const double lnT0 = log(T0);
-  const double Ac = a1 * exp(a2 * lnT0) + a3 * exp(a4 * lnT0);
+  const double lnT0 = ln_pos(T0);
+  // ln A = ln(a1 T0^a2 + a3 T0^a4) = ln a1 + a2 ln T0 + ln(1 + (a3/a1) T0^(a4-a2))
+  const double lnA = kLnA1 + a2 * lnT0 + ln_pos(1.0 + (a3 / a1) * exp((a4 - a2) * lnT0));
   const double Tf2 = Tf * Tf, Tf7 = Tf2 * Tf2 * Tf2 * Tf;
   const double Bc = -exp(b0 + b1 * Tf + b2 * Tf7);
   const double Cc = c1 * Tf + c2;                                    // > 0.6 for Tf in [0, 1]
-  const double lnQ1 = log(Ac) + Bc * s.lnR;                          // Q1 = Ac R^Bc
+  const double lnQ1 = lnA + Bc * s.lnR;                              // Q1 = A R^Bc
   // Q = (R^C + Q1^C)^(1/C): ln Q = max + ln(1 + e^(-C |ln Q1 - ln R|)) / C
+  // (the second term is taken to an absolute, not relative, accuracy)
   const double dl = lnQ1 - s.lnR;
-  const double lnQ = (dl > 0.0 ? lnQ1 : s.lnR) + log1p(exp(-Cc * fabs(dl))) / Cc;
+  const double lnQ = (dl > 0.0 ? lnQ1 : s.lnR) + ln_pos(1.0 + exp(-Cc * fabs(dl))) / Cc;
   const double x = alpha * exp(beta * lnQ);
   return s.Z * x / (1.0 + x + sqrt(1.0 + 2.0 * x));
 }
@@ -71,7 +103,7 @@ __host__ __device__ inline double coulomb_log(const Solid& s, double Te, double 
   const double inv_ld2 = s.ld_e * ne * rT + s.ld_i * Zs * Zs / Ti;
   const double bmax2 = fmax(1.0 / inv_ld2, s.r02);
   const double bmin2 = fmax(s.bc2 * Zs * Zs * rT * rT, s.bq2 * rT);
-  return fmax(2.0, 0.5 * log(1.0 + bmax2 / bmin2));
+  return fmax(2.0, 0.5 * ln_pos(1.0 + bmax2 / bmin2));
 }
 
 // Bremsstrahlung enhancement by the ionised background, eq. (F_sigma):
