@@ -73,7 +73,7 @@ Layout make_layout(const hyb_config& c) {
   L.off_heat_acc = take(cells * 8);
   L.off_stamp = take(ntl * 4);
   L.off_dirty = take(ntl * 4);
-  L.off_pj = take(ntl * 3 * kPjHalo * ts);
+  L.off_pj = take(ntl * 3 * kPjWords * ts);
   L.off_ph = take(ntl * kTile * kTile * kTile * 8);
   for (int b = 0; b < 2; ++b) {
     // one record per electron: cell, id, then ox oy oz ux uy uz wn tau

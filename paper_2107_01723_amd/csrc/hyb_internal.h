@@ -234,7 +234,7 @@ struct RunDesc {
   long long* heat_acc;
   int* tstamp;              // [ntiles] step + 1 of the tile's last claim (0: never)
   int* tdirty;              // [ntiles] step + 1 of the last atomic into the tile's halo or cells
-  void* pj;                 // [ntiles][3][216] current partials of the tiles (32-bit FP32, 64-bit FP64)
+  void* pj;                 // [ntiles][3][kPjWords] current partials of the tiles (32-bit FP32, 64-bit FP64)
   long long* ph;            // [ntiles][64] heat partials of the tile's cells
   FastDiv fd_gx, fd_gy;     // by the gather's tile counts along x and y: (nx >> 2) + 1, (ny >> 2) + 1
   PartPtrs p[2];
@@ -265,7 +265,9 @@ struct RunDesc {
 };
 
 constexpr int kTile = 4;           // tile edge in cells
-constexpr int kPjHalo = (kTile + 2) * (kTile + 2) * (kTile + 2);   // nodes of a tile's deposit halo
+// words per current component in a tile's partials: the nodes of its deposit
+// halo (6^3) that the component reaches, staggered on one axis (6 x 5 x 5)
+constexpr int kPjWords = (kTile + 2) * (kTile + 1) * (kTile + 1);
 constexpr int kChunk = 256;        // electrons per chunk of the particle kernels (one workgroup)
 constexpr int kNb = 5;             // destination tiles counted per chunk: home +-2 per axis
 constexpr int kNbN = kNb * kNb * kNb;

@@ -356,43 +356,54 @@ constexpr int kLdsTab = 128;   // table rows staged in LDS
 // A tile's 216 halo nodes split into 27 parts by the tile that owns the
 // node: part e (a step of -1, 0 or +1 per axis, index (ex + 1) + 3 (ey + 1)
 // + 9 (ez + 1); 13 is the tile itself) holds the halo layer 0 (e = -1) or 5
-// (e = +1) on its fixed axes and layers 1..4 on the others, x fastest.  A
-// tile's partials (pj: [tile][component][216]) list the parts one after
-// the other, part 13 first: position p is halo node l[p] (x + 6 y + 36 z),
-// part e starts at off[e].  The gather of a tile reads the part of each
-// neighbour that lies in it as one run of words.
+// (e = +1) on its fixed axes and layers 1..4 on the others, x fastest.  The
+// deposit of current component c reaches layer 0 only along axis c (its
+// stencil is staggered there, node-centred on the other axes), so c's
+// partials hold the 150 nodes of the parts without e = -1 on another axis.
+// A tile's partials (pj: [tile][component][150]) list those parts one after
+// the other, part 13 first: position p of component c is halo node l[c][p]
+// (x + 6 y + 36 z), part e starts at off[c][e] (-1: none).  The gather of a
+// tile reads the part of each neighbour that lies in it as one run of words.
 struct PjPerm {
-  unsigned char l[kHaloN];
-  short off[27];
+  unsigned char l[3][kPjWords];
+  short off[3][27];
 };
 __host__ __device__ constexpr int pj_layer(int e, int o) { return e < 0 ? 0 : (e > 0 ? kHalo - 1 : 1 + o); }
 constexpr PjPerm make_pj_perm() {
   PjPerm P{};
-  int pos = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int e = 0; e < 27; ++e) {
-      if ((pass == 0) != (e == 13)) continue;
-      const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
-      P.off[e] = (short)pos;
-      for (int oz = 0; oz < (ez ? 1 : kTile); ++oz)
-        for (int oy = 0; oy < (ey ? 1 : kTile); ++oy)
-          for (int ox = 0; ox < (ex ? 1 : kTile); ++ox)
-            P.l[pos++] = (unsigned char)(pj_layer(ex, ox) + kHalo * (pj_layer(ey, oy) + kHalo * pj_layer(ez, oz)));
-    }
+  for (int c = 0; c < 3; ++c) {
+    int pos = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int e = 0; e < 27; ++e) {
+        if ((pass == 0) != (e == 13)) continue;
+        const int ed[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
+        P.off[c][e] = -1;
+        if ((c != 0 && ed[0] < 0) || (c != 1 && ed[1] < 0) || (c != 2 && ed[2] < 0)) continue;
+        P.off[c][e] = (short)pos;
+        for (int oz = 0; oz < (ed[2] ? 1 : kTile); ++oz)
+          for (int oy = 0; oy < (ed[1] ? 1 : kTile); ++oy)
+            for (int ox = 0; ox < (ed[0] ? 1 : kTile); ++ox)
+              P.l[c][pos++] =
+                  (unsigned char)(pj_layer(ed[0], ox) + kHalo * (pj_layer(ed[1], oy) + kHalo * pj_layer(ed[2], oz)));
+      }
+  }
   return P;
 }
 __constant__ PjPerm kPjPerm = make_pj_perm();
-static_assert(make_pj_perm().off[13] == 0 && make_pj_perm().l[kHaloN - 1] == kHaloN - 1, "halo order");
+static_assert(make_pj_perm().off[0][13] == 0 && make_pj_perm().l[2][kPjWords - 1] == kHaloN - 1 &&
+                  make_pj_perm().off[1][0] < 0 && make_pj_perm().off[0][12] >= 0 && make_pj_perm().off[1][12] < 0,
+              "halo order");
 
 // Word, inside the partials of tile u = v - e, of component c of own node o
 // of tile v, which u holds in its part e (indexed by o over the axes where
-// e is 0).
+// e is 0); -1 where component c has no such part.
 __device__ __forceinline__ int pj_word(int ex, int ey, int ez, int c, int ox, int oy, int oz) {
   int idx = 0, sc = 1;
   if (!ex) { idx += ox; sc = kTile; }
   if (!ey) { idx += oy * sc; sc *= kTile; }
   if (!ez) idx += oz * sc;
-  return c * kHaloN + kPjPerm.off[(ex + 1) + 3 * (ey + 1) + 9 * (ez + 1)] + idx;
+  const int off = kPjPerm.off[c][(ex + 1) + 3 * (ey + 1) + 9 * (ez + 1)];
+  return off < 0 ? -1 : c * kPjWords + off + idx;
 }
 
 // The per-tile counts that pick the regions use slots that alternate between
@@ -408,7 +419,7 @@ struct ChunkLds {
   T tsig[kLdsTab], tsub[kLdsTab];   // cross-section columns of the tables, if they fit
   T F[2][6][kHaloN];                // E, B on the 6^3-node halos of the two fullest regions
   int own[kRegions];                // the region's tile was first claimed this step by this workgroup
-  unsigned char perm[kHaloN];       // halo node of each position of the partials (kPjPerm.l)
+  unsigned char perm[3 * kPjWords]; // halo node of each position of the partials (kPjPerm.l)
 };
 
 struct Home {
@@ -449,7 +460,7 @@ __device__ __forceinline__ void lds_init(ChunkLds<T>& L) {
   if (threadIdx.x < kNbN) L.cnt[threadIdx.x] = 0;
   if (threadIdx.x < 2 * kKeys) { (&L.tc[0][0])[threadIdx.x] = 0; (&L.tt[0][0])[threadIdx.x] = -1; }
   if (threadIdx.x < L_N + C_N) L.led[threadIdx.x] = 0;
-  if (threadIdx.x < kHaloN) L.perm[threadIdx.x] = kPjPerm.l[threadIdx.x];
+  for (int t = threadIdx.x; t < 3 * kPjWords; t += kBlock) L.perm[t] = (&kPjPerm.l[0][0])[t];
 }
 
 // Moves the LDS sums of one region to HBM and clears them for the next
@@ -461,10 +472,10 @@ __device__ __forceinline__ void lds_flush_region(const RunDesc& R, ChunkLds<T>& 
   using A = typename JAcc<T>::type;
   A* J = L.J[r];
   if (L.own[r]) {
-    A* const dst = (A*)R.pj + (long long)tile * (3 * kHaloN);
-    for (int t = threadIdx.x; t < 3 * kHaloN; t += kBlock) {
-      const int c = t >= 2 * kHaloN ? 2 : (t >= kHaloN ? 1 : 0);
-      A* w = &J[c * kHaloN + L.perm[t - c * kHaloN]];
+    A* const dst = (A*)R.pj + (long long)tile * (3 * kPjWords);
+    for (int t = threadIdx.x; t < 3 * kPjWords; t += kBlock) {
+      const int c = t >= 2 * kPjWords ? 2 : (t >= kPjWords ? 1 : 0);
+      A* w = &J[c * kHaloN + L.perm[t]];
       dst[t] = *w;
       *w = 0;
     }
@@ -1794,8 +1805,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
   int pb[8];
 #pragma unroll
   for (int m = 0; m < 8; ++m)
-    pb[m] = hc ? o : pj_word(-(m & 1 ? ax : 0), -(m & 2 ? ay : 0), -(m & 4 ? az : 0), c, ox, oy, oz);
-  const long long pstr = hc ? kTile * kTile * kTile : 3 * kHaloN;   // words per tile
+    pb[m] = hc ? o : pj_word(-(m & 1 ? ax : 0), -(m & 2 ? ay : 0), -(m & 4 ? az : 0), hc ? 0 : c, ox, oy, oz);
+  const long long pstr = hc ? kTile * kTile * kTile : 3 * kPjWords;   // words per tile
   const gptr<const A> pj = G((const A*)R.pj);
   const gptr<const long long> ph = G((const long long*)R.ph);
   // A workgroup sweeps segments of rows of tiles along x (up to 8 groups of
@@ -1862,8 +1873,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
         for (int m = 0; m < (HC ? 1 : 8); ++m) {
           const int dx = m & 1 ? ax : 0, dy = m & 2 ? ay : 0, dz = m & 4 ? az : 0;
           const bool holds = in[g] && (!(m & 1) || ax) && (!(m & 2) || ay) && (!(m & 4) || az);
+          const bool part = pb[m] >= 0;   // the holder's partials of component c reach the node
           const int fl = st[buf][g][13 + dx + 3 * dy + 9 * dz];
-          const bool use = holds && (fl & 1);
+          const bool use = holds && part && (fl & 1);
           rd[g] |= holds && (fl & 2);
           const long long u = (vx + dx) + (long long)R.ntx * ((vy + dy) + (long long)R.nty * (vz + dz));
           const long long wa = use ? pb[m] + u * pstr : 0;

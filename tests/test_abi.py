@@ -45,7 +45,7 @@ def test_footprint_and_validation(P):
     # accumulator (int64) per node; Te, Ti, two eta, heat and its
     # accumulator (FP64) and F_sigma per cell; two particle buffers of
     # records (cell, id, 8 values); per tile of 4^3 cells the current
-    # partials (3 x 216 words), 64 heat partials, a claim and a mark of
+    # partials (3 x 150 words), 64 heat partials, a claim and a mark of
     # atomics into its accumulators; per particle
     # a scatter offset, per chunk of 256 its 125 destination counts
     ts = 8 if big["precision"] == W.FP64 else 4
@@ -54,7 +54,7 @@ def test_footprint_and_validation(P):
     tiles = -(-big["nx"] // 4) * -(-big["ny"] // 4) * -(-big["nz"] // 4)
     cap = big["max_particles"]
     need = (nodes * (6 * ts + 6 * 8) + cells * (6 * 8 + ts) + 2 * cap * (8 + 8 * ts)
-            + tiles * (3 * 216 * ts + 64 * 8 + 8) + cap * 4 + -(-cap // 256) * 125 * 4)
+            + tiles * (3 * 150 * ts + 64 * 8 + 8) + cap * 4 + -(-cap // 256) * 125 * 4)
     assert need <= P.footprint(big) <= 1.02 * need + 1e8
     bad = dict(cfg, x_lo=2.5e-6)                  # slab face off the cell faces
     with pytest.raises(P.HybError) as e:
