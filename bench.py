@@ -25,8 +25,14 @@ during the timed steps.  `traffic` is the HBM bytes per launch that
 rocprofv3's FETCH_SIZE and WRITE_SIZE counters gave for the same kernel on
 the same workload and step window (the summary under profiles/), scaled by
 the copy-kernel factors, or null when that summary was taken on other
-kernel sources or another window.  `step_roofline` is the whole step's
-algorithmic bytes (particles, sort, grid) over the step's wall time.
+kernel sources or another window.  `valu_roofline` sets the same kernel
+against its VALU issue rate: wave-level VALU instructions per launch
+(rocprofv3's SQ_INSTS_VALU, from a summary under profiles/ with the same
+guards) over the live launch duration, against one 64-lane instruction
+per SIMD every 4 cycles (the FP64 vector peak of 78.6 TFLOP/s over 128
+flops per wave-level FMA: 6.14e11 per second).  `step_roofline` is the
+whole step's algorithmic bytes (particles, sort, grid) over the step's
+wall time.
 """
 from __future__ import annotations
 
@@ -43,6 +49,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK = 78.6e12 / 128          # wave-level VALU instructions per second (1024 SIMDs, 4 cycles each)
 METRIC = "macro-electron steps/s (FP32-mixed vs FP64, same GPU); p50/p99 scan-run latency"
 
 # (name, workload function, precision, description)
@@ -121,6 +128,23 @@ def counted_traffic(name: str, window: tuple[int, int]):
     return int(float(v)) if v else None
 
 
+def counted_valu(name: str, window: tuple[int, int]):
+    """Wave-level VALU instructions per particle-kernel launch (SQ_INSTS_VALU)
+    from the committed counter summary of this workload, or None when it is
+    missing, was taken on other kernel sources or on another step window."""
+    path = os.path.join(ROOT, "profiles", f"particle_kernel_valu_{name}.txt")
+    try:
+        with open(path) as fh:
+            kv = dict(ln.split(":", 1) for ln in fh if ":" in ln and not ln.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_digest") != kernel_digest() or kv.get("window") != f"{window[0]}-{window[1]}":
+        return None
+    v = kv.get("valu_insts_per_launch")
+    return float(v) if v else None
+
+
 def injection_steps(cfg, srcs) -> int:
     return max(int(math.floor(s["t_end"] / cfg["dt"] + 0.5)) for s in srcs)
 
@@ -164,6 +188,13 @@ def time_run(P, name, cfg, srcs, steps, warmup):
     achieved = (rd + wr) * per_launch / (kernel_ms * 1e-3) / 1e9
     window = (n_inj + warmup, n_inj + warmup + steps)
     traffic = counted_traffic(name, window)
+    valu = counted_valu(name, window)
+    valu_roof = None
+    if valu:
+        va = valu / (kernel_ms * 1e-3)
+        valu_roof = dict(bound="alu", achieved=round(va, -6), peak=round(VALU_PEAK, -6), unit="wave-instr/s",
+                         frac=round(va / VALU_PEAK, 4), insts_per_electron_step=round(64 * valu / per_launch, 1),
+                         kernel="k_particle")
     solid = (round(cfg["x_hi"] / cfg["dx"]) - round(cfg["x_lo"] / cfg["dx"])) * cfg["ny"] * cfg["nz"]
     sb = step_bytes(prec, per_launch, info["nodes"], solid, info["n_sub"])
     led = t1["ledger"]
@@ -176,6 +207,7 @@ def time_run(P, name, cfg, srcs, steps, warmup):
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                       bytes_per_electron_step=rd + wr, kernel="k_particle"),
+        valu_roofline=valu_roof,
         step_roofline=dict(bytes_per_step=round(sb), achieved=round(sb / (wall / steps) / 1e9, 1),
                            peak=HBM_PEAK_GBS, unit="GB/s", frac=round(sb / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4)),
         injection_phase=dict(steps=n_inj, ms_per_step=round(1e3 * wall_inj / n_inj, 4),
@@ -379,13 +411,14 @@ def main():
                                 + f"; timed after the untimed {head['injection_phase']['steps']}-step "
                                   f"injection window",
                     "timed_steps": head["timed_steps"], "alive_mean": head["alive_mean"]},
-            roofline=head["roofline"], step_roofline=head["step_roofline"],
+            roofline=head["roofline"], valu_roofline=head["valu_roofline"], step_roofline=head["step_roofline"],
             particle_kernel_ms=head["particle_kernel_ms"], injection_phase=head["injection_phase"],
             ledger_closure=head["ledger_closure"])
         if hname == "gold_512cube_2e8_fp32" and "gold_512cube_2e8_fp64" in res:
             f64 = res["gold_512cube_2e8_fp64"]
             line["fp64"] = {k: f64[k] for k in ("value", "ms_per_step", "particle_kernel_ms", "roofline",
-                                                "step_roofline", "injection_phase", "ledger_closure")}
+                                                "valu_roofline", "step_roofline", "injection_phase",
+                                                "ledger_closure")}
             line["mixed_over_fp64"] = round(head["value"] / f64["value"], 3)
         line["workloads"] = {k: v for k, v in res.items() if k not in (hname, "gold_512cube_2e8_fp64" if hname == "gold_512cube_2e8_fp32" else "")}
         ratios = {}

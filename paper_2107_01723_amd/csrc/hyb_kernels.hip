@@ -195,7 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_inject(const RunDesc* __restrict__ r
 // Yee stencil helpers.  Along an axis a node quantity uses indices (c, c+1)
 // with weights (1-o, o); a staggered quantity sits at half-integers and uses
 // (c-1, c) or (c, c+1).  A staggered index one past either end is the mirror
-// ghost of the nearest index, with the opposite sign.
+// ghost of the nearest index, with the opposite sign: its weight joins that
+// index's, and the pair keeps i1 = i0 + 1 with a zero weight on the other
+// (an index inside the node-sized arrays), so that the two values of a pair
+// are always neighbours in memory and load together.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Axis { int i0, i1; T w0, w1; };
@@ -209,11 +212,11 @@ __device__ __forceinline__ Axis<T> stag_axis(int c, T o, int n) {
   T f;
   if (o >= (T)0.5) { a.i0 = c; f = o - (T)0.5; }
   else { a.i0 = c - 1; f = o + (T)0.5; }
-  a.i1 = a.i0 + 1;
   a.w0 = (T)1 - f;
   a.w1 = f;
-  if (a.i0 < 0) { a.i0 = 0; a.w0 = -a.w0; }
-  if (a.i1 > n - 1) { a.i1 = n - 1; a.w1 = -a.w1; }
+  if (a.i0 < 0) { a.i0 = 0; a.w0 = a.w1 - a.w0; a.w1 = (T)0; }     // ghost at -1: odd image of 0
+  else if (a.i0 + 1 > n - 1) { a.w0 = a.w0 - a.w1; a.w1 = (T)0; }  // ghost at n: odd image of n - 1
+  a.i1 = a.i0 + 1;
   return a;
 }
 
