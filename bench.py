@@ -234,7 +234,7 @@ def cpu_baseline():
     """The FP64 oracle, as it stands, on the host's cores (one process; its
     NumPy work is single-threaded): (1) the whole small workload (1e4
     electrons, 32x16x16 cells, 200 steps); (2) a sample of the headline
-    workload: its material, cells, time step and source, 1e5 electrons
+    workload: its material, cells, time step and source, 5e5 electrons
     injected in one step (untimed) on a 512x64x64 part of its grid around
     the spot, then timed steps, with the particle part and the grid update
     timed apart (electron-steps/s and cell-steps/s), and the whole 2e8 /
@@ -266,13 +266,13 @@ def cpu_baseline():
 
     cfg5, srcs5, _ = W.config_huge()
     c = copy.deepcopy(cfg5)
-    c.update(ny=64, nz=64, max_particles=100_000)
+    c.update(ny=64, nz=64, max_particles=500_000)
     s = copy.deepcopy(srcs5[0])
-    s.update(n_macro=100_000, t_end=c["dt"], y0=16e-6, z0=16e-6)
+    s.update(n_macro=500_000, t_end=c["dt"], y0=16e-6, z0=16e-6)
     ora = OracleRun(c)
     ora.add_source(s)
     ora.step()
-    k = 5
+    k = 8
     tot5, grid5, es5 = timed(ora, k)
     cells5 = c["nx"] * c["ny"] * c["nz"]
     p_rate = es5 / (tot5 - grid5)
@@ -281,7 +281,7 @@ def cpu_baseline():
     extrap = 2e8 / p_rate + full_cells / c_rate
     return dict(
         value=round(p_rate, 1), unit="macro-electron steps/s", cores=1, kind="oracle",
-        sample=(f"FP64 oracle on one core: the headline workload's physics, cells and source, 1e5 "
+        sample=(f"FP64 oracle on one core: the headline workload's physics, cells and source, 5e5 "
                 f"electrons on a 512x64x64 part of its grid, {k} timed steps; value = particle "
                 f"part only ({tot5 - grid5:.1f} s); grid update {c_rate:.3e} cell-steps/s "
                 f"({grid5:.1f} s); the whole small workload (1e4 electrons, 32x16x16 cells, "
