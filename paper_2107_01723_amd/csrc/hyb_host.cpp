@@ -387,6 +387,8 @@ static void fill_desc(hyb_run* r) {
   h.scan_nblk = (h.ntiles + kScanTile - 1) / kScanTile;
   h.fd_gx = make_fastdiv((uint32_t)(c.nx >> 2) + 1);
   h.fd_gy = make_fastdiv((uint32_t)(c.ny >> 2) + 1);
+  h.fd_tx = make_fastdiv((uint32_t)h.ntx);
+  h.fd_ty = make_fastdiv((uint32_t)h.nty);
   h.hist_stride = (long long)hist_stride(c);
   set_units(h, r->w_ref > 0 ? r->w_ref : 1.0);
   r->solid_cells = (int64_t)(h.ix_hi - h.ix_lo) * c.ny * c.nz;

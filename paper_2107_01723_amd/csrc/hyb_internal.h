@@ -237,6 +237,7 @@ struct RunDesc {
   void* pj;                 // [ntiles][3][kPjWords] current partials of the tiles (32-bit FP32, 64-bit FP64)
   long long* ph;            // [ntiles][64] heat partials of the tile's cells
   FastDiv fd_gx, fd_gy;     // by the gather's tile counts along x and y: (nx >> 2) + 1, (ny >> 2) + 1
+  FastDiv fd_tx, fd_ty;     // by the tile counts ntx, nty
   PartPtrs p[2];
   Counters* ctr;
   const SourceDesc* src;

@@ -439,10 +439,10 @@ __device__ __forceinline__ Home make_home(const RunDesc& R, int t) {
   Home h;
   h.ok = t >= 0 && t != kNoTile;
   if (!h.ok) t = 0;
-  h.tx = t % R.ntx;
-  const int q = t / R.ntx;
-  h.ty = q % R.nty;
-  h.tz = q / R.nty;
+  const uint32_t q = R.fd_tx.div((uint32_t)t), z = R.fd_ty.div(q);
+  h.tx = t - (int)q * R.ntx;
+  h.ty = (int)q - (int)z * R.nty;
+  h.tz = (int)z;
   h.bx = kTile * h.tx - 1;
   h.by = kTile * h.ty - 1;
   h.bz = kTile * h.tz - 1;
@@ -835,6 +835,19 @@ __device__ __forceinline__ void chunk_census(const RunDesc& R, ChunkLds<T>& S, u
   if ((threadIdx.x & 63) == 0 && al) lds_add(&S.led[L_N + C_ESTEPS], (long long)__popcll(al));
 }
 
+// Maximum over the 64 lanes of a wave, in every lane (a scalar): pairs and
+// quads, rows of 16 by rotation, then rows 1 and 3 take the last lane of
+// the row before and rows 2 and 3 lane 31 (DPP lane moves, no LDS).
+__device__ __forceinline__ int wave_max(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x124, 0xF, 0xF, false));   // row_ror:4
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false));   // row_ror:8
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x142, 0xA, 0xF, false));   // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false));   // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
 // The regions of a chunk from its census (slot q): each region of the
 // previous chunk (tile rt[k], cn holding 5 bits per slot: the chunks it has
 // summed) whose tile recurs keeps its slot and its sums, up to the carry
@@ -854,10 +867,7 @@ __device__ __forceinline__ void pick_regions(const ChunkLds<T>& S, int q, const 
     nrt[k] = -1;
     const int m = (cn >> (5 * k)) & 31;
     if (rt[k] < 0 || m >= JAcc<T>::max_chunks) continue;
-    int cc = t == rt[k] ? c : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cc = max(cc, __shfl_xor(cc, o, 64));
-    cc = __builtin_amdgcn_readfirstlane(cc);
+    const int cc = wave_max(t == rt[k] ? c : 0);
     if (cc == 0) continue;
     nrt[k] = rt[k];
     m_cn |= (m + 1) << (5 * k);
@@ -870,12 +880,10 @@ __device__ __forceinline__ void pick_regions(const ChunkLds<T>& S, int q, const 
 #pragma unroll
   for (int k = 0; k < kRegions; ++k) {
     if (!more || nrt[k] >= 0) continue;
-    int key = c > 0 ? (c << 6) | l : -1;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) key = max(key, __shfl_xor(key, o, 64));
-    key = __builtin_amdgcn_readfirstlane(key);
+    const int key = wave_max(c > 0 ? (c << 6) | l : -1);
     if (key < 0) { more = false; continue; }
-    const int tile = __builtin_amdgcn_readfirstlane(__shfl(t, key & 63, 64));
+    const int tile = __builtin_amdgcn_readlane(t, key & 63);
+    if (tile < 0) { more = false; continue; }   // (a counted key always names its tile)
     const int cnt = key >> 6;
     nrt[k] = tile;
     m_cn |= 1 << (5 * k);
