@@ -574,7 +574,8 @@ __device__ __forceinline__ void deposit8(long long* __restrict__ J, typename JAc
 
 // Ranks of the lanes in their bins (b < 0: none), taken in lane order from
 // the block's LDS counters: one LDS atomic per distinct bin of the wave, so
-// lanes of one bin get consecutive ranks and their writes coalesce.
+// lanes of one bin get consecutive ranks and their writes coalesce.  Every
+// lane of the wave takes part; the leader's values are read with readlane.
 __device__ __forceinline__ unsigned wave_rank(unsigned* cnt, int b) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -582,11 +583,11 @@ __device__ __forceinline__ unsigned wave_rank(unsigned* cnt, int b) {
   unsigned long long todo = __ballot(b >= 0);
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
-    const int lb = __shfl(b, leader, 64);
+    const int lb = __builtin_amdgcn_readlane(b, leader);
     const unsigned long long m = __ballot(b == lb);
     unsigned base = 0;
     if (lane == leader) base = atomicAdd(&cnt[lb], (unsigned)__popcll(m));
-    base = __shfl(base, leader, 64);
+    base = (unsigned)__builtin_amdgcn_readlane((int)base, leader);
     if (b == lb) rank = base + (unsigned)__popcll(m & below);
     todo &= ~m;
   }
@@ -867,7 +868,9 @@ __device__ __forceinline__ void pick_regions(const ChunkLds<T>& S, int q, const 
     nrt[k] = -1;
     const int m = (cn >> (5 * k)) & 31;
     if (rt[k] < 0 || m >= JAcc<T>::max_chunks) continue;
-    const int cc = wave_max(t == rt[k] ? c : 0);
+    // a tile has one census key, so at most one lane holds rt[k]
+    const unsigned long long mk = __ballot(t == rt[k]);
+    const int cc = mk ? __builtin_amdgcn_readlane(c, __ffsll((long long)mk) - 1) : 0;
     if (cc == 0) continue;
     nrt[k] = rt[k];
     m_cn |= (m + 1) << (5 * k);
@@ -1440,7 +1443,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PartOcc<
     if (count) {
       // most electrons of a chunk land in one tile: count it with one atomic
       // per wave, the rest one by one
-      const int lead = __shfl(dest_bin, 0, 64);
+      const int lead = __builtin_amdgcn_readlane(dest_bin, 0);
       const unsigned long long same = __ballot(dest_bin == lead && dest_bin >= 0);
       if ((threadIdx.x & 63) == 0 && same) atomicAdd(&S.cnt[lead], (unsigned)__popcll(same));
       if (dest_bin >= 0 && dest_bin != lead) atomicAdd(&S.cnt[dest_bin], 1u);
