@@ -1808,7 +1808,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const RunDesc* __restrict__ r
   const int ox = o & 3, oy = (o >> 2) & 3, oz = o >> 4;
   // The node's other tile along each axis (-1, +1; 0: none; cells have
   // none) and, for the up to eight tiles u holding it (m: bit 0 x, 1 y, 2 z
-  // take the other tile), the node's word in u's partials: pb + p3 u.  Every
+  // take the other tile), the node's word in u's partials: pb + p3 u (pb
+  // -1: component c's deposit from u never reaches the node).  Every
   // load below is issued unconditionally (lanes with nothing to read load a
   // word they do not use), so that the loads of an iteration are all in
   // flight together instead of each waiting at the end of its branch.
