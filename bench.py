@@ -314,7 +314,7 @@ def main():
                     help="first copy 512 MiB with torch (reference kernel for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (this build runs "
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (the step runs "
               f"on a single GPU)", file=sys.stderr)
         sys.exit(2)
 
