@@ -70,3 +70,14 @@ def test_status_strings(P):
     L = P.lib()
     assert L.hyb_status_string(0) == b"ok"
     assert L.hyb_status_string(7) == b"busy"
+
+
+def test_binding_fails_loudly_without_the_library():
+    """No CPU fallback: without libhyb.so the binding raises."""
+    import subprocess
+    import sys
+    code = ("import paper_2107_01723_amd.hyb as H\n"
+            "H.LIB_PATH = '/nonexistent/libhyb.so'\n"
+            "try:\n    H.lib()\nexcept RuntimeError as e:\n    print('raised', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert "raised" in out.stdout and "missing" in out.stdout, (out.stdout, out.stderr[-2000:])
